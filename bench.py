@@ -1,0 +1,151 @@
+"""Benchmark of the fused imaginary-time FDTD step on one MI355X.
+
+One "step" is one pass of the whole hot path over the lattice: the update of
+Eq. (updateeq) at every site, fused with the FP64 norm / <H> / r^2 reductions
+of the state it reads, the norm of the state it writes, and the deferred
+renormalisation.  Default workload: the finest level of the Cornell-type
+multi-resolution chain, V = -0.4/r + 0.2 r + 0.05 z^2 on 512^3, L = 30,
+dt = a^2/8, FP32 state and potential in HBM, FP64 reductions.
+
+Prints one JSON line with site-updates/s, the roofline of the step kernel
+(algorithmic bytes per launch over the measured average launch time) and the
+FP64 CPU oracle timed on a bounded sample of the same lattice.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "site-updates/s & HBM roofline %; time-to-E(1e-6 rel) plain vs FP32/batched"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_SITE = {"f64": 24, "f32": 12, "bf16": 8}  # read psi + V, write psi'
+KERNEL_SRC = os.path.join(ROOT, "paper_0904_0939_amd", "csrc", "fdtd_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(key: str, sites: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha") != kernel_hash() or key not in rec.get("workloads", {}):
+        return None
+    w = rec["workloads"][key]
+    if w.get("sites") != sites:
+        return None
+    return w.get("bytes_per_launch")
+
+
+def cpu_baseline(N, L, params, steps):
+    """The FP64 oracle on the same lattice: setup untimed, `steps` steps timed."""
+    import oracle as orc
+
+    a = L / N
+    V = orc.potential(orc.POT_CORNELL, params, N, L)
+    psi = orc.initial(N, 3)
+    orc.step(psi, V, L, a * a / 8)  # first touch / thread start-up
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psi = orc.step(psi, V, L, a * a / 8)
+    dt = time.perf_counter() - t0
+    return {"value": N**3 * steps / dt, "unit": "site-updates/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle update sweeps of the same {N}^3 Cornell lattice "
+                      f"({dt:.1f} s; potential and noise set-up untimed)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the lattice "
+              "fits one MI355X and the multi-GPU slab exchange is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    lat = W.cornell(args.n)
+    N, L = lat.N, lat.L
+    s = Solver(N, L, dtype=args.dtype)
+    s.set_potential(F.POT_CORNELL, lat.pot_params)
+    s.set_initial(lat.seed)
+    if args.autotune:
+        s.autotune(10)
+    tun = s.tuning()
+    graph = not args.no_graph
+    chunk = 50
+    # warm-up: also captures the graph
+    s.evolve(args.warmup, check_every=0, use_graph=graph)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.evolve(args.steps, check_every=0, use_graph=graph)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    ms_per_step = gpu_ms / args.steps
+    sites = N ** 3
+    rate = sites * args.steps / (gpu_ms * 1e-3)
+    alg_bytes = BYTES_PER_SITE[args.dtype] * sites
+    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    ob = s.observables()[0]
+    key = f"cornell{N}_{args.dtype}"
+    traffic = measured_traffic(key, sites)
+    out = {
+        "metric": METRIC,
+        "value": rate,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"cornell_{N}^3_{args.dtype}_fused_step",
+                   "potential": "-0.4/r + 0.2 r + 0.05 z^2", "N": N, "L": L, "dt": lat.dt,
+                   "reductions": "FP64 norm, <H>, r^2 of the input + norm of the output, every step",
+                   "renormalise_every": 1, "hip_graph": graph, "tuning": tun,
+                   "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic},
+        "energy_after_timed_steps": ob["energy"],
+        "wall_s_timed_region": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, L, lat.pot_params, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * fdtd.h -- C ABI of the MI355X (gfx950) imaginary-time FDTD library.
+ *
+ * Method: Strickland & Yager-Elorriaga, "A Parallel Algorithm for Solving the
+ * 3d Schroedinger Equation", arXiv:0904.0939.  A real wavefunction psi on an
+ * N^3 lattice of spacing a = L/N (Sec. III) is relaxed in imaginary time by
+ * the update of Eq. (updateeq),
+ *     psi' = A psi + (B dt / 2m) sum_i (D . Psi-hat)_i,
+ *     A = (1 - dt V/2) / (1 + dt V/2),   B = 1 / (1 + dt V/2),
+ * with psi = 0 on the ghost sites around the lattice (Sec. III, Sec. V).  Each
+ * step also reduces, over the state it reads, the norm, the energy of
+ * Eq. (energysum) (taken as +<H>; the printed sign is reversed) and the rms
+ * radius, and renormalises the state (Sec. III).
+ *
+ * Conventions shared by every call:
+ *  - Sites i = 0..N-1 per axis sit at x_i = (2i - (N-1)) a/2, centred on the
+ *    origin; a field is stored f[(ix*N + iy)*N + iz], z fastest, no padding.
+ *  - Every call returns an fdtd_status; no C++ exception crosses the ABI.
+ *    fdtd_last_error() gives a thread-local message for the last failure.
+ *    A handle stays valid after FDTD_EINVAL and FDTD_ENONFINITE.
+ *  - All device work is ordered on the stream given at creation (NULL = the
+ *    device's default stream).  Calls that return host values synchronise it.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Host buffers passed in are copied before the call returns and stay owned
+ *    by the caller.  Device pointers passed in must stay valid until the call
+ *    has completed on the stream.
+ *  - The library never falls back to a CPU path: without a usable gfx950 GPU
+ *    every call that touches device memory returns FDTD_EHIP.
+ */
+#ifndef FDTD_H
+#define FDTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fdtd_ctx* fdtd_t;
+
+typedef enum {
+  FDTD_OK = 0,
+  FDTD_EINVAL = 1,     /* bad argument; nothing was changed */
+  FDTD_ENOMEM = 2,     /* device or host allocation failed, or workspace too small */
+  FDTD_EHIP = 3,       /* HIP runtime error (no device, launch failure, ...) */
+  FDTD_EUNSTABLE = 4,  /* dt >= m a^2 / 3, the von Neumann bound of Sec. III */
+  FDTD_ENOTREADY = 5,  /* call order: potential and initial state must be set first */
+  FDTD_ENONFINITE = 6  /* a reduction produced NaN/Inf; the offending step is reported */
+} fdtd_status;
+
+/* Storage type of psi (and of user arrays).  V is stored in FP64 when psi is
+ * FP64 and in FP32 otherwise.  Arithmetic: FP64 storage computes in FP64;
+ * FP32 and BF16 storage compute the update in FP32.  The reductions are
+ * always accumulated in FP64. */
+typedef enum { FDTD_F64 = 0, FDTD_F32 = 1, FDTD_BF16 = 2 } fdtd_dtype;
+
+/* Analytic potentials, evaluated in FP64 at the site coordinates and rounded
+ * to the storage type of V.  p[] holds the parameters listed. */
+enum {
+  FDTD_POT_CONST = 0,       /* V = p0                                              */
+  FDTD_POT_HO = 1,          /* V = (p0^2 x^2 + p1^2 y^2 + p2^2 z^2)/2  (Sec. VII.D)  */
+  FDTD_POT_COULOMB = 2,     /* V = -p0 / r                                         */
+  FDTD_POT_COULOMB_REG = 3, /* Eq. (coulombpot): 0 for r < a, -p0/r + p0/a else     */
+  FDTD_POT_CORNELL = 4,     /* V = -p0/r + p1 r + p2 z^2                           */
+  FDTD_POT_WELLS = 5        /* HO(p0,p1,p2) - sum_k A_k exp(-|r-c_k|^2 / 2 s_k^2);
+                               p[3+5k .. 7+5k] = A_k, cx, cy, cz, s_k             */
+};
+
+/* Initial-state kinds (Sec. III: random start; Sec. VI: a coarser solution). */
+enum { FDTD_INIT_UNIFORM = 0, FDTD_INIT_GAUSS = 1, FDTD_INIT_USER = 2 };
+
+/* Parity word for the symmetry operators of Sec. IV: two bits per axis
+ * (x: bits 0-1, y: bits 2-3, z: bits 4-5); 0 free, 1 S_i, 2 A_i. */
+#define FDTD_PARITY(px, py, pz) ((uint32_t)(((px) & 3) | (((py) & 3) << 2) | (((pz) & 3) << 4)))
+
+typedef struct {
+  int32_t n;          /* lattice side N >= 2 (N^3 sites)                       */
+  int32_t psi_dtype;  /* fdtd_dtype of the stored wavefunction                 */
+  double box_len;     /* L = N a > 0                                           */
+  double mass;        /* m > 0                                                 */
+  double dt;          /* imaginary-time step; must satisfy 0 < dt < m a^2 / 3  */
+  double v_inf;       /* V at infinity, for the binding energy (Eq. bindingenergy) */
+  int32_t device;     /* HIP device ordinal                                    */
+  int32_t history;    /* per-step observable records kept on the device (ring);
+                         0 selects 4096                                        */
+  void* stream;       /* hipStream_t, or NULL                                  */
+} fdtd_config;
+
+/* Observables of one lattice (Sec. III, Eq. energysum, Eq. bindingenergy):
+ * norm2 = a^3 sum psi^2 of the stored state, energy = <H>, its kinetic and
+ * potential parts, r_rms = sqrt(<r^2>) from the lattice centre,
+ * binding = energy - v_inf, tau = step * dt, step = steps taken so far. */
+typedef struct {
+  double norm2, energy, kinetic, potential, r_rms, binding, tau;
+  int64_t step;
+} fdtd_obs;
+
+/* Options of fdtd_evolve.
+ *  max_steps        steps to run at most (>= 0).
+ *  renorm_every     rescale the state to a^3 sum psi^2 = 1 after every k-th
+ *                   step (0: never).  The scale is folded into the next
+ *                   step's update (exact: the update is linear).
+ *  check_every      K > 0: every K steps compare the energy of the state
+ *                   entering the K-th step with the previous check and stop
+ *                   when |dE| <= rel_tol |E - v_inf| (Sec. V); 0: no check.
+ *  reimpose_parity_every  re-apply the set_initial parity every k steps
+ *                   (Sec. IV; 0: never -- the update preserves it bit-exactly).
+ *  use_graph        1: capture the K-step loop in a HIP graph and replay it.
+ */
+typedef struct {
+  int64_t max_steps;
+  int32_t renorm_every;
+  int32_t check_every;
+  int32_t reimpose_parity_every;
+  int32_t use_graph;
+  double rel_tol;
+} fdtd_evolve_opts;
+
+/* Launch shape of the fused step kernel (see fdtd_autotune).
+ *  vz     sites per lane along z, 1 or the dtype's vector width (F64 2,
+ *         F32 4, BF16 8; requires N % vz == 0);
+ *  ry     vectors per lane per plane (1, 2 or 4);
+ *  xchunk planes streamed per work item (>= 1);
+ *  grid   work-groups launched (0: one per work item);
+ *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles. */
+typedef struct {
+  int32_t vz, ry, xchunk, grid, xcd_remap;
+} fdtd_tuning;
+
+/* ---- lifetime -------------------------------------------------------------*/
+
+/* Create a handle for one lattice.  Validates the config (FDTD_EINVAL) and the
+ * stability bound dt < m a^2/3 (FDTD_EUNSTABLE).  No device memory is taken
+ * until fdtd_bind_workspace or the first call that needs it. */
+fdtd_status fdtd_create(const fdtd_config* cfg, fdtd_t* out);
+
+/* Create one handle for `count` lattices of possibly different N, box, mass
+ * and dt that advance together: one launch per step covers every member.  All
+ * members share psi_dtype, device, history and stream (taken from cfgs[0]). */
+fdtd_status fdtd_create_batch(const fdtd_config* cfgs, int32_t count, fdtd_t* out);
+
+/* Bytes of device memory the handle needs (fields, reductions, history). */
+fdtd_status fdtd_workspace_size(fdtd_t h, size_t* bytes);
+
+/* Use caller-owned device memory (e.g. a torch tensor) of at least
+ * fdtd_workspace_size bytes, 256-byte aligned, kept alive until fdtd_destroy.
+ * Must precede every other device call; without it the library allocates. */
+fdtd_status fdtd_bind_workspace(fdtd_t h, void* dev_ptr, size_t bytes);
+
+/* Release the handle and any memory the library allocated.  NULL is a no-op. */
+fdtd_status fdtd_destroy(fdtd_t h);
+
+/* ---- state preparation ----------------------------------------------------*/
+
+/* Set V of `member` from an array of N^3 values (dtype F64 or F32), on the host
+ * (on_device = 0) or the device. */
+fdtd_status fdtd_set_potential(fdtd_t h, int32_t member, const void* v, int32_t dtype,
+                               int32_t on_device);
+
+/* Set V of `member` (-1: every member) from an analytic kind FDTD_POT_*. */
+fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, const double* p,
+                                        int32_t np);
+
+/* Initial state of `member` (-1: every member).  UNIFORM draws U[-1, 1) and
+ * GAUSS unit normals (Box-Muller) from counter-based SplitMix64 (Steele, Lea
+ * & Flood 2014): draw j of site s of member m is the (2^36 m + 2s + j + 1)-th
+ * output of the stream seeded with `seed`.  The parity word then copies the
+ * lower half (i < N/2) of each masked axis onto the upper half, with a sign
+ * flip for A_i, zeroing the mid plane of odd N under A_i (Sec. IV).  USER
+ * copies N^3 values of `dtype` from `user` (host or device).  Resets the step
+ * counter and the history; the state is normalised on entry to the first step. */
+fdtd_status fdtd_set_initial(fdtd_t h, int32_t member, int32_t kind, uint64_t seed,
+                             uint32_t parity, const void* user, int32_t dtype, int32_t on_device);
+
+/* ---- the hot path ----------------------------------------------------------*/
+
+/* Advance every member; see fdtd_evolve_opts.  steps_done and converged
+ * (optional) receive the steps run and whether the check was met (for a batch:
+ * every member converged).  Returns FDTD_ENONFINITE if a reduction went
+ * non-finite; the state is then left as computed. */
+fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* opts, int64_t* steps_done,
+                        int32_t* converged);
+
+/* Observables of the current state of every member (out[count]): one
+ * reduction pass over the lattice(s). */
+fdtd_status fdtd_observables(fdtd_t h, fdtd_obs* out);
+
+/* Recorded per-step observables of `member`: for the last `max` steps (at most
+ * the history size), out[k] describes the state entering step
+ * first_step + k.  count receives the number written. */
+fdtd_status fdtd_history(fdtd_t h, int32_t member, fdtd_obs* out, int64_t max, int64_t* count);
+
+/* Copy the state of `member`, normalised to a^3 sum psi^2 = 1, into N^3
+ * values of `dtype` (F64, F32 or BF16) at dst (host or device). */
+fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int32_t on_device);
+
+/* Copy the stored state of `member` exactly as held (its storage dtype, not
+ * normalised: the pending renormalisation scale is not applied) to dst (host
+ * or device), with the number of steps it has taken.  For bit-level checks
+ * and checkpoints; fdtd_set_initial(USER) restores such a copy. */
+fdtd_status fdtd_get_state(fdtd_t h, int32_t member, void* dst, int32_t on_device, int64_t* step);
+
+/* Multi-resolution reseeding (Sec. VI, Sec. VII.G): trilinear interpolation of
+ * the coarse member's state onto the fine member's lattice (same box_len,
+ * coarse ghosts zero), normalised; resets the fine member's step counter.  The
+ * fine member needs its potential set; psi dtypes may differ. */
+fdtd_status fdtd_upsample(fdtd_t coarse, int32_t coarse_member, fdtd_t fine, int32_t fine_member);
+
+/* Gradient of the energy after `steps` renormalised steps from the current
+ * state of a single-lattice handle, held fixed, with respect to V: reverse-mode
+ * differentiation of Eq. (updateeq) (adjoint stencil with the same A, B),
+ * forward states checkpointed every `checkpoint_every` steps and recomputed
+ * segment by segment.  Outputs (each optional):
+ *   dE_dV     device FP64 N^3 field dE/dV_i;
+ *   dE_dtheta for an FDTD_POT_WELLS potential with parameters theta[ntheta]
+ *             (which must be the ones V was set from), the derivatives with
+ *             respect to theta[wrt[k]] for k < nwrt (A_k and s_k entries only);
+ *   energy    E after `steps` steps.
+ * The handle's state is advanced by `steps` steps, as fdtd_evolve would. */
+fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,
+                             const double* theta, int32_t ntheta, const int32_t* wrt,
+                             int32_t nwrt, void* dE_dV, double* dE_dtheta, double* energy);
+
+/* ---- launch shape -----------------------------------------------------------*/
+
+fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out);
+fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
+
+/* Time every valid launch shape of the step kernel on this handle (its state
+ * is saved and restored) with HIP events, keep the fastest, and cache it per
+ * (device, dtype, lattice sizes) for later handles of this process.
+ * chosen (optional) receives it; best_ms (optional) its time per step. */
+fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen,
+                          double* best_ms);
+
+/* ---- misc -------------------------------------------------------------------*/
+
+/* Wait for all work of the handle. */
+fdtd_status fdtd_synchronize(fdtd_t h);
+
+/* Number of members, and the stream the handle launches on. */
+fdtd_status fdtd_info(fdtd_t h, int32_t* count, void** stream);
+
+const char* fdtd_status_string(fdtd_status s);
+const char* fdtd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTD_H */

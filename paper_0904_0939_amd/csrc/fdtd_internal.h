@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libfdtd.  Device-side descriptors, work items and kernel launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdtd {
+
+constexpr int kBlock = 256;  // threads per work-group: 4 wave64s
+constexpr int kRec = 8;      // doubles per observable record
+
+// Layout of one observable record (per member, per step).
+enum RecordField {
+  kS0 = 0,     // sum psi^2 of the state entering the step
+  kKin = 1,    // kinetic energy sum: -(1/2m a^2) sum psi * (a^2 lap psi)
+  kPot = 2,    // sum V psi^2
+  kR2 = 3,     // sum r^2 psi^2
+  kS0Out = 4,  // sum psi'^2 of the written state
+  kStep = 5,   // step index
+  kScale = 6,  // scale folded into this step's update
+  kSpare = 7
+};
+
+// Read-only description of one lattice, resident on the device.
+struct MemberDev {
+  void* psi[2];       // ping-pong state buffers (storage dtype)
+  const void* V;      // potential (double when psi is FP64, float otherwise)
+  int N;
+  int item_begin;     // this member's work items are [item_begin, item_end)
+  int item_end;
+  int pad0;
+  long long plane;    // N * N
+  double ha;          // a / 2 (site coordinate = (2 i - (N - 1)) * ha)
+  double c;           // dt / (2 m a^2)
+  double dt;
+  double kin_scale;   // 1 / (2 m a^2)
+  double a3;          // a^3
+};
+
+// Mutable per-member state, resident on the device.
+struct MemberState {
+  double scale;         // multiplies the next step's update (deferred renormalisation)
+  long long step;       // steps taken
+  unsigned int counter; // work items finished in the current launch
+  int bad;              // a reduction went non-finite
+  long long bad_step;
+  double spare[3];
+};
+
+// One work item: a chunk of a member's flattened (y, z) plane, for planes
+// x in [xb, xe).
+struct Item {
+  int member;
+  int f0;
+  int xb;
+  int xe;
+};
+
+struct StepArgs {
+  const MemberDev* members;
+  MemberState* states;
+  const Item* items;
+  int item_offset;      // this launch processes items [item_offset, item_offset + n_items)
+  int n_items;
+  int src;              // input buffer index (0 / 1); the output is src ^ 1
+  int renorm_every;     // > 0: rescale after every k-th step
+  int set_scale;        // observe mode: set scale = 1 / sqrt(a^3 S0)
+  double* partials;     // n_items * kRec
+  double* ring;         // history: n_members * ring_cap * kRec
+  int ring_cap;
+  double* obs_out;      // observe mode: n_members * kRec
+};
+
+enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+// Launch the fused step (update = true) or the reduction-only pass.
+hipError_t launch_step(int dtype, int vz, int ry, bool update, int grid, const StepArgs& a,
+                       hipStream_t s);
+
+// One thread per site, member m only.
+hipError_t launch_potential(int vdtype, void* V, int N, double ha, double a, int kind,
+                            const double* p_dev, int np, hipStream_t s);
+hipError_t launch_initial(int dtype, void* psi, int N, uint64_t seed, uint32_t member, int kind,
+                          uint32_t parity, hipStream_t s);
+hipError_t launch_convert(int sdtype, const void* src, int ddtype, void* dst, long long n,
+                          double scale, hipStream_t s);
+hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, double ac, int fdtype,
+                           void* pf, int Nf, double haf, hipStream_t s);
+hipError_t launch_reimpose(int dtype, void* psi, int N, uint32_t parity, hipStream_t s);
+hipError_t launch_set_state(MemberState* st, int member, double scale, long long step,
+                            int reset_bad, hipStream_t s);
+
+// ---- adjoint (gradient) kernels ------------------------------------------------
+struct AdjArgs {
+  const void* V;        // float (F32 path) or double (F64 path)
+  const void* lam_in;   // lambda_{t+1}
+  void* lam_out;        // lambda_t
+  const void* psi_t;    // psi_t  (as stored by the forward)
+  const void* psi_t1;   // psi_{t+1}
+  double* G;            // dE/dV accumulator, FP64
+  int N;
+  int pad0;
+  double c, dt;
+  double s_t;           // scale applied in forward step t
+};
+hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s);
+
+struct AdjInitArgs {
+  const void* V;
+  const void* psi;      // psi_T
+  void* lam;            // out: 2 (H psi - E psi) / S0
+  double* G;            // out: psi^2 / S0
+  int N;
+  int pad0;
+  double kin_scale;     // 1 / (2 m a^2)
+  double E, S0;
+};
+hipError_t launch_adjoint_init(int dtype, const AdjInitArgs& a, hipStream_t s);
+
+// dE/dtheta_j = sum_i G_i dV_i/dtheta_j for Gaussian-well parameters.
+hipError_t launch_wells_contract(const double* G, int N, double ha, const double* p_dev, int np,
+                                 const int* wrt_dev, int nwrt, double* partials, int nblocks,
+                                 double* out_dev, hipStream_t s);
+
+}  // namespace fdtd

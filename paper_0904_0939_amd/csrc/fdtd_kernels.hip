@@ -1,0 +1,810 @@
+// HIP kernels (gfx950, wave64) of the imaginary-time FDTD library.
+//
+// The hot kernel is k_step: one pass over the lattice that applies the update
+// of Eq. (updateeq) (Strickland & Yager-Elorriaga, Sec. III) to every site and,
+// in the same pass, reduces the norm, the kinetic and potential energy sums of
+// Eq. (energysum) and the r^2 moment of the state it reads, plus the norm of
+// the state it writes.  It is HBM-bound (about 1.7 flop per byte in FP32), so
+// the design is about bytes, not flops:
+//   * z is the contiguous axis; each lane owns VZ consecutive z sites of
+//     RY (y, z) vectors and streams them along x, keeping planes x-1, x, x+1 in
+//     registers, so every psi value comes from HBM once per step;
+//   * the y +- 1 and z +- 1 neighbours are re-read from the plane the
+//     work-group (and its XCD neighbours, see the work-item order built on the
+//     host) has just streamed, i.e. from L1/L2, not HBM;
+//   * the update is written in increment form psi' = s (psi + B (c lap - dt V
+//     psi)) with B = 1/(1 + dt V/2) computed in registers from V (algebraically
+//     A psi + B c lap with A = 2B - 1), so V is the only stored coefficient;
+//   * the Laplacian is summed from neighbour differences in mirror-symmetric
+//     pairs, so a parity-symmetric state stays exactly symmetric;
+//   * reductions accumulate in FP64 per lane, then wave shuffle, LDS and a
+//     fixed-order sum of per-work-item partials by the last work-group to
+//     finish a member (deterministic run to run);
+//   * the renormalisation scale of step t is computed from the output norm of
+//     step t - 1 and folded into the update (the update is linear), so no
+//     extra pass and no host round trip is needed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "fdtd_internal.h"
+
+namespace fdtd {
+namespace {
+
+// ---------------------------------------------------------------- types ----
+template <int DT>
+struct Types;
+template <>
+struct Types<kF64> {
+  using S = double;  // storage
+  using V = double;  // potential storage
+  using C = double;  // arithmetic
+  static constexpr int kVec = 2;
+};
+template <>
+struct Types<kF32> {
+  using S = float;
+  using V = float;
+  using C = float;
+  static constexpr int kVec = 4;
+};
+template <>
+struct Types<kBF16> {
+  using S = uint16_t;
+  using V = float;
+  using C = float;
+  static constexpr int kVec = 8;
+};
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Round to nearest even; NaN stays a (quiet) NaN.  Acts on the magnitude
+// bits only, so it commutes with negation.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ C to_c(S v) {
+  if constexpr (sizeof(S) == 2) {
+    return (C)bf16_to_f32(v);
+  } else {
+    return (C)v;
+  }
+}
+
+template <typename S, typename C>
+__device__ __forceinline__ S from_c(C v) {
+  if constexpr (sizeof(S) == 2) {
+    return f32_to_bf16((float)v);
+  } else {
+    return (S)v;
+  }
+}
+
+template <typename S, int VZ>
+struct alignas(sizeof(S) * VZ) Pack {
+  S v[VZ];
+};
+
+template <typename S, int VZ, typename C>
+__device__ __forceinline__ void load_vec(const S* __restrict__ p, C (&o)[VZ]) {
+  const Pack<S, VZ> t = *reinterpret_cast<const Pack<S, VZ>*>(p);
+#pragma unroll
+  for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
+}
+
+template <typename S, int VZ>
+__device__ __forceinline__ void store_vec(S* __restrict__ p, const Pack<S, VZ>& t) {
+  *reinterpret_cast<Pack<S, VZ>*>(p) = t;
+}
+
+template <typename C, int VZ>
+__device__ __forceinline__ void zero_vec(C (&o)[VZ]) {
+#pragma unroll
+  for (int j = 0; j < VZ; ++j) o[j] = C(0);
+}
+
+__device__ __forceinline__ float rcp_c(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_c(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum NV values over the work-group; the result is valid in thread 0.
+// Fixed order: lanes by butterfly, then waves 0..3 left to right.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[tid >> 6][k] = v[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = red[0][k];
+#pragma unroll
+      for (int w = 1; w < kBlock / 64; ++w) t += red[w][k];
+      v[k] = t;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool finite_d(double x) { return !(isnan(x) || isinf(x)); }
+
+// ------------------------------------------------------- fused step kernel --
+template <int DT, int VZ, int RY, bool UPD>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+  using S = typename Types<DT>::S;
+  using TV = typename Types<DT>::V;
+  using C = typename Types<DT>::C;
+  __shared__ double s_red[kBlock / 64][5];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+
+  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
+    const int it = A.item_offset + li;  // position of the item: also its partial slot
+    const Item item = A.items[it];
+    const int m = item.member;
+    const MemberDev& M = A.members[m];
+    const int N = M.N;
+    const long long P = M.plane;
+    const S* __restrict__ in = static_cast<const S*>(M.psi[A.src]);
+    S* __restrict__ out = static_cast<S*>(M.psi[A.src ^ 1]);
+    const TV* __restrict__ Vp = static_cast<const TV*>(M.V);
+    const C c = (C)M.c;
+    const C dt = (C)M.dt;
+    const C eps = (C)(0.5 * M.dt);
+    const C sc = (C)A.states[m].scale;
+    const double ha = M.ha;
+    const double cN = (double)(N - 1);
+
+    long long f[RY];
+    bool ok[RY], ym_ok[RY], yp_ok[RY], zm_ok[RY], zp_ok[RY];
+    int z0[RY];
+    double ry2[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      f[r] = (long long)item.f0 + (long long)(r * kBlock + tid) * VZ;
+      ok[r] = f[r] < P;
+      const int y = ok[r] ? (int)(f[r] / N) : 0;
+      z0[r] = ok[r] ? (int)(f[r] - (long long)y * N) : 0;
+      ym_ok[r] = ok[r] && y > 0;
+      yp_ok[r] = ok[r] && y < N - 1;
+      zm_ok[r] = ok[r] && z0[r] > 0;
+      zp_ok[r] = ok[r] && z0[r] + VZ < N;
+      const double yc = (2.0 * y - cN) * ha;
+      ry2[r] = yc * yc;
+    }
+
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    C prev[RY][VZ], cur[RY][VZ], nxt[RY][VZ];
+    const int xb = item.xb, xe = item.xe;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      if (ok[r] && xb > 0) load_vec<S, VZ, C>(in + (long long)(xb - 1) * P + f[r], prev[r]);
+      else zero_vec<C, VZ>(prev[r]);
+      if (ok[r]) load_vec<S, VZ, C>(in + (long long)xb * P + f[r], cur[r]);
+      else zero_vec<C, VZ>(cur[r]);
+    }
+
+    for (int x = xb; x < xe; ++x) {
+      const long long base = (long long)x * P;
+      const double xc = (2.0 * x - cN) * ha;
+      const double rx2 = xc * xc;
+      const bool has_next = x + 1 < N;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (ok[r] && has_next) load_vec<S, VZ, C>(in + base + P + f[r], nxt[r]);
+        else zero_vec<C, VZ>(nxt[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        if (!ok[r]) continue;
+        const long long g = base + f[r];
+        C v[VZ], ym[VZ], yp[VZ];
+        load_vec<TV, VZ, C>(Vp + g, v);
+        if (ym_ok[r]) load_vec<S, VZ, C>(in + g - N, ym);
+        else zero_vec<C, VZ>(ym);
+        if (yp_ok[r]) load_vec<S, VZ, C>(in + g + N, yp);
+        else zero_vec<C, VZ>(yp);
+        const C zm = zm_ok[r] ? to_c<S, C>(in[g - 1]) : C(0);
+        const C zp = zp_ok[r] ? to_c<S, C>(in[g + VZ]) : C(0);
+        const double rxy2 = rx2 + ry2[r];
+        Pack<S, VZ> o;
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          const C p = cur[r][j];
+          C lft = zm, rgt = zp;
+          if (j > 0) lft = cur[r][j - 1];
+          if (j < VZ - 1) rgt = cur[r][j + 1];
+          // a^2 * Laplacian from neighbour differences, mirror-symmetric pairs
+          const C lap = (((prev[r][j] - p) + (nxt[r][j] - p)) + ((ym[j] - p) + (yp[j] - p))) +
+                        ((lft - p) + (rgt - p));
+          const double pd = (double)p;
+          const double p2 = pd * pd;
+          acc[0] += p2;
+          acc[1] += pd * (double)lap;
+          acc[2] += (double)v[j] * p2;
+          const double zc = (2.0 * (z0[r] + j) - cN) * ha;
+          acc[3] += (rxy2 + zc * zc) * p2;
+          if constexpr (UPD) {
+            const C B = rcp_c(C(1) + eps * v[j]);
+            const C nv = sc * (p + B * (c * lap - dt * v[j] * p));
+            o.v[j] = from_c<S, C>(nv);
+            const double od = (double)to_c<S, C>(o.v[j]);
+            acc[4] += od * od;
+          }
+        }
+        if constexpr (UPD) store_vec<S, VZ>(out + g, o);
+      }
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          prev[r][j] = cur[r][j];
+          cur[r][j] = nxt[r][j];
+        }
+      }
+    }
+
+    // ---- per-item partials, then the last work-group of the member sums them
+    block_sum<5>(acc, s_red);
+    if (tid == 0) {
+      double* part = A.partials + (long long)it * kRec;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) part[k] = acc[k];
+      __threadfence();
+      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+      s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = M.item_begin + tid; i < M.item_end; i += kBlock) {
+        const double* part = A.partials + (long long)i * kRec;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) tot[k] += part[k];
+      }
+      block_sum<5>(tot, s_red);
+      if (tid == 0) {
+        MemberState& st = A.states[m];
+        const double kin = -M.kin_scale * tot[1];
+        const long long t = st.step;
+        double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, (double)st.scale, 0.0};
+        if (UPD) {
+          double* dst = A.ring + ((long long)m * A.ring_cap + (t % A.ring_cap)) * kRec;
+#pragma unroll
+          for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
+          const long long nt = t + 1;
+          const bool renorm = A.renorm_every > 0 && (nt % A.renorm_every) == 0;
+          st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
+          st.step = nt;
+          if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) &&
+              !st.bad) {
+            st.bad = 1;
+            st.bad_step = t;
+          }
+        } else {
+          // reduction-only pass: the host inspects the sums itself
+          double* dst = A.obs_out + (long long)m * kRec;
+#pragma unroll
+          for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
+          if (A.set_scale) st.scale = 1.0 / sqrt(M.a3 * tot[0]);
+        }
+        st.counter = 0u;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------- potentials ----
+template <typename TV>
+__global__ __launch_bounds__(kBlock) void k_potential(TV* __restrict__ V, int N, double ha,
+                                                      double a, int kind,
+                                                      const double* __restrict__ p, int np) {
+  const long long n3 = (long long)N * N * N;
+  const double cN = (double)(N - 1);
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int iz = (int)(s % N);
+    const long long q = s / N;
+    const int iy = (int)(q % N);
+    const int ix = (int)(q / N);
+    const double x = (2.0 * ix - cN) * ha, y = (2.0 * iy - cN) * ha, z = (2.0 * iz - cN) * ha;
+    const double r = sqrt(x * x + y * y + z * z);
+    double v = 0.0;
+    switch (kind) {
+      case 0: v = p[0]; break;
+      case 1: v = 0.5 * (p[0] * p[0] * x * x + p[1] * p[1] * y * y + p[2] * p[2] * z * z); break;
+      case 2: v = -p[0] / r; break;
+      case 3: v = (r < a) ? 0.0 : (-p[0] / r + p[0] / a); break;
+      case 4: v = -p[0] / r + p[1] * r + p[2] * z * z; break;
+      case 5: {
+        v = 0.5 * (p[0] * p[0] * x * x + p[1] * p[1] * y * y + p[2] * p[2] * z * z);
+        for (int k = 3; k + 4 < np; k += 5) {
+          const double dx = x - p[k + 1], dy = y - p[k + 2], dz = z - p[k + 3];
+          const double d2 = dx * dx + dy * dy + dz * dz;
+          v -= p[k] * exp(-d2 / (2.0 * p[k + 4] * p[k + 4]));
+        }
+        break;
+      }
+      default: v = 0.0;
+    }
+    V[s] = (TV)v;
+  }
+}
+
+// -------------------------------------------------------- initial state ----
+__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double unit53(uint64_t r) {
+  return (double)(r >> 11) * (1.0 / 9007199254740992.0);
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_initial(S* __restrict__ psi, int N, uint64_t seed,
+                                                    uint32_t member, int kind, uint32_t parity) {
+  const long long n3 = (long long)N * N * N;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    int c[3];
+    c[2] = (int)(s % N);
+    const long long q = s / N;
+    c[1] = (int)(q % N);
+    c[0] = (int)(q / N);
+    double sign = 1.0;
+    bool zero = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const uint32_t mode = (parity >> (2 * ax)) & 3u;
+      if (mode == 0u) continue;
+      const int mir = N - 1 - c[ax];
+      if (c[ax] > mir) {  // upper half takes the value of its mirror site
+        c[ax] = mir;
+        if (mode == 2u) sign = -sign;
+      } else if (c[ax] == mir && mode == 2u) {
+        zero = true;
+      }
+    }
+    const long long src = ((long long)c[0] * N + c[1]) * N + c[2];
+    const uint64_t ctr = ((uint64_t)member << 36) + 2ull * (uint64_t)src;
+    double val;
+    if (kind == 0) {
+      val = 2.0 * unit53(splitmix(seed, ctr)) - 1.0;
+    } else {
+      const double u1 = unit53(splitmix(seed, ctr)) + 1.0 / 9007199254740992.0;
+      const double u2 = unit53(splitmix(seed, ctr + 1ull));
+      val = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    }
+    val = zero ? 0.0 : sign * val;
+    if constexpr (sizeof(S) == 2) psi[s] = f32_to_bf16((float)val);
+    else psi[s] = (S)val;
+  }
+}
+
+// ----------------------------------------------------------- conversion ----
+template <typename SS, typename DS>
+__global__ __launch_bounds__(kBlock) void k_convert(const SS* __restrict__ src,
+                                                    DS* __restrict__ dst, long long n,
+                                                    double scale) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v;
+    if constexpr (sizeof(SS) == 2) v = (double)bf16_to_f32(src[i]);
+    else v = (double)src[i];
+    v *= scale;
+    if constexpr (sizeof(DS) == 2) dst[i] = f32_to_bf16((float)v);
+    else dst[i] = (DS)v;
+  }
+}
+
+// ------------------------------------------------------------- upsample ----
+template <typename CS>
+__device__ __forceinline__ double fetch_c(const CS* __restrict__ pc, int N, int x, int y, int z) {
+  if (x < 0 || y < 0 || z < 0 || x >= N || y >= N || z >= N) return 0.0;  // ghost
+  const CS v = pc[((long long)x * N + y) * N + z];
+  if constexpr (sizeof(CS) == 2) return (double)bf16_to_f32(v);
+  else return (double)v;
+}
+
+// Trilinear spread of a coarse state onto a finer lattice of the same box
+// (Sec. VI).  Interpolates along z, then y, then x; each 1-d step adds the
+// two weighted ends, so mirrored fine sites see the same sums.
+template <typename CS, typename FS>
+__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc,
+                                                     double hac, double ac,
+                                                     FS* __restrict__ pf, int Nf, double haf) {
+  const long long n3 = (long long)Nf * Nf * Nf;
+  const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
+  (void)hac;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    int j[3];
+    j[2] = (int)(s % Nf);
+    const long long q = s / Nf;
+    j[1] = (int)(q % Nf);
+    j[0] = (int)(q / Nf);
+    int i0[3];
+    double w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double t = ((2.0 * j[d] - cNf) * haf) / ac + halfc;
+      const double fl = floor(t);
+      i0[d] = (int)fl;
+      w[d] = t - fl;
+    }
+    double vy[2];
+#pragma unroll
+    for (int cx = 0; cx < 2; ++cx) {
+      double vz[2];
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy) {
+        const double lo = fetch_c(pc, Nc, i0[0] + cx, i0[1] + cy, i0[2]);
+        const double hi = fetch_c(pc, Nc, i0[0] + cx, i0[1] + cy, i0[2] + 1);
+        vz[cy] = (1.0 - w[2]) * lo + w[2] * hi;
+      }
+      vy[cx] = (1.0 - w[1]) * vz[0] + w[1] * vz[1];
+    }
+    const double v = (1.0 - w[0]) * vy[0] + w[0] * vy[1];
+    if constexpr (sizeof(FS) == 2) pf[s] = f32_to_bf16((float)v);
+    else pf[s] = (FS)v;
+  }
+}
+
+// ----------------------------------------------------- parity reimposed ----
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_reimpose(S* __restrict__ psi, int N, uint32_t parity) {
+  const long long n3 = (long long)N * N * N;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    int c[3];
+    c[2] = (int)(s % N);
+    const long long q = s / N;
+    c[1] = (int)(q % N);
+    c[0] = (int)(q / N);
+    bool neg = false, zero = false, moved = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const uint32_t mode = (parity >> (2 * ax)) & 3u;
+      if (mode == 0u) continue;
+      const int mir = N - 1 - c[ax];
+      if (c[ax] > mir) {
+        c[ax] = mir;
+        moved = true;
+        if (mode == 2u) neg = !neg;
+      } else if (c[ax] == mir && mode == 2u) {
+        zero = true;
+      }
+    }
+    if (zero) {
+      psi[s] = S(0);
+    } else if (moved) {
+      // the source lies in the lower half of every masked axis: never written here
+      const S v = psi[((long long)c[0] * N + c[1]) * N + c[2]];
+      if constexpr (sizeof(S) == 2) psi[s] = neg ? (uint16_t)(v ^ 0x8000u) : v;
+      else psi[s] = neg ? -v : v;
+    }
+  }
+}
+
+__global__ void k_set_state(MemberState* st, int member, double scale, long long step,
+                            int reset_bad) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    MemberState& s = st[member];
+    s.scale = scale;
+    s.step = step;
+    s.counter = 0u;
+    if (reset_bad) {
+      s.bad = 0;
+      s.bad_step = -1;
+    }
+  }
+}
+
+// -------------------------------------------------------------- adjoint ----
+// One step of the adjoint recurrence of the renormalised update
+// psi_{t+1} = s_t M psi_t,  M = I + diag(B) (c Lap - dt diag(V)):
+//   lambda_t = s_t M^T lambda_{t+1},
+//   (M^T l)_j = l_j + c (Lap w)_j - dt V_j w_j,   w = B l,
+//   G_j += lambda_{t+1,j} (-(dt/2) B_j) (s_t psi_{t,j} + psi_{t+1,j}),
+// the last line being d psi_{t+1,j} / dV_j (through A_j and B_j) times the
+// adjoint.  One thread per site; neighbour w values are recomputed from V.
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_adjoint_step(AdjArgs a) {
+  using C = typename std::conditional<sizeof(S) == 8, double, float>::type;
+  const S* __restrict__ V = static_cast<const S*>(a.V);
+  const S* __restrict__ li = static_cast<const S*>(a.lam_in);
+  S* __restrict__ lo = static_cast<S*>(a.lam_out);
+  const S* __restrict__ pt = static_cast<const S*>(a.psi_t);
+  const S* __restrict__ pt1 = static_cast<const S*>(a.psi_t1);
+  const int N = a.N;
+  const long long P = (long long)N * N, n3 = P * N;
+  const C c = (C)a.c, dt = (C)a.dt, eps = (C)(0.5 * a.dt), st = (C)a.s_t;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int iz = (int)(s % N);
+    const long long q = s / N;
+    const int iy = (int)(q % N);
+    const int ix = (int)(q / N);
+    auto wv = [&](long long k) -> C { return li[k] * rcp_c(C(1) + eps * (C)V[k]); };
+    const C l = li[s];
+    const C v = V[s];
+    const C B = rcp_c(C(1) + eps * v);
+    const C w = l * B;
+    const C wxm = ix > 0 ? wv(s - P) : C(0), wxp = ix < N - 1 ? wv(s + P) : C(0);
+    const C wym = iy > 0 ? wv(s - N) : C(0), wyp = iy < N - 1 ? wv(s + N) : C(0);
+    const C wzm = iz > 0 ? wv(s - 1) : C(0), wzp = iz < N - 1 ? wv(s + 1) : C(0);
+    const C lapw = (((wxm - w) + (wxp - w)) + ((wym - w) + (wyp - w))) + ((wzm - w) + (wzp - w));
+    lo[s] = st * (l + c * lapw - dt * v * w);
+    a.G[s] += (double)l * (-0.5 * a.dt * (double)B) *
+              ((double)st * (double)pt[s] + (double)pt1[s]);
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_adjoint_init(AdjInitArgs a) {
+  const S* __restrict__ V = static_cast<const S*>(a.V);
+  const S* __restrict__ p = static_cast<const S*>(a.psi);
+  S* __restrict__ lam = static_cast<S*>(a.lam);
+  const int N = a.N;
+  const long long P = (long long)N * N, n3 = P * N;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int iz = (int)(s % N);
+    const long long q = s / N;
+    const int iy = (int)(q % N);
+    const int ix = (int)(q / N);
+    const double c0 = (double)p[s];
+    auto at = [&](bool okk, long long k) -> double { return okk ? (double)p[k] : 0.0; };
+    const double lap = (((at(ix > 0, s - P) - c0) + (at(ix < N - 1, s + P) - c0)) +
+                        ((at(iy > 0, s - N) - c0) + (at(iy < N - 1, s + N) - c0))) +
+                       ((at(iz > 0, s - 1) - c0) + (at(iz < N - 1, s + 1) - c0));
+    const double hp = -a.kin_scale * lap + (double)V[s] * c0;
+    lam[s] = (S)(2.0 * (hp - a.E * c0) / a.S0);
+    a.G[s] = c0 * c0 / a.S0;
+  }
+}
+
+// Contraction of dE/dV with the analytic derivatives of the Gaussian wells:
+// dV/dA_k = -e_k, dV/ds_k = -A_k e_k d_k^2 / s_k^3, e_k = exp(-d_k^2 / 2 s_k^2).
+constexpr int kMaxWrt = 64;
+
+__global__ __launch_bounds__(kBlock) void k_wells_contract(const double* __restrict__ G, int N,
+                                                           double ha,
+                                                           const double* __restrict__ p, int np,
+                                                           const int* __restrict__ wrt, int nwrt,
+                                                           double* __restrict__ partials) {
+  __shared__ double red[kBlock / 64][8];
+  const long long n3 = (long long)N * N * N;
+  const double cN = (double)(N - 1);
+  for (int k0 = 0; k0 < nwrt; k0 += 8) {
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
+         s += (long long)gridDim.x * blockDim.x) {
+      const int iz = (int)(s % N);
+      const long long q = s / N;
+      const int iy = (int)(q % N);
+      const int ix = (int)(q / N);
+      const double x = (2.0 * ix - cN) * ha, y = (2.0 * iy - cN) * ha, z = (2.0 * iz - cN) * ha;
+      const double g = G[s];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int k = k0 + kk;
+        if (k >= nwrt) break;
+        const int j = wrt[k];
+        const int base = 3 + ((j - 3) / 5) * 5;
+        const bool is_s = ((j - 3) % 5) == 4;
+        const double dx = x - p[base + 1], dy = y - p[base + 2], dz = z - p[base + 3];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double sw = p[base + 4];
+        const double e = exp(-d2 / (2.0 * sw * sw));
+        const double dv = is_s ? -p[base] * e * d2 / (sw * sw * sw) : -e;
+        acc[kk] += g * dv;
+      }
+    }
+    block_sum<8>(acc, red);
+    if (threadIdx.x == 0) {
+      for (int kk = 0; kk < 8 && k0 + kk < nwrt; ++kk)
+        partials[(long long)blockIdx.x * kMaxWrt + k0 + kk] = acc[kk];
+    }
+    __syncthreads();
+  }
+  (void)np;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials,
+                                                         int nblocks, int nwrt,
+                                                         double* __restrict__ out) {
+  const int k = threadIdx.x;
+  if (k < nwrt) {
+    double t = 0.0;
+    for (int b = 0; b < nblocks; ++b) t += partials[(long long)b * kMaxWrt + k];
+    out[k] = t;
+  }
+}
+
+// ------------------------------------------------------------- dispatch ----
+int grid_for(long long n) {
+  long long g = (n + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+template <int DT, int VZ, bool UPD>
+hipError_t step_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
+  switch (ry) {
+    case 1: hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_step<DT, VZ, 2, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_step<DT, VZ, 4, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int DT, bool UPD>
+hipError_t step_vz(int vz, int ry, int grid, const StepArgs& a, hipStream_t s) {
+  if (vz == 1) return step_ry<DT, 1, UPD>(ry, grid, a, s);
+  if (vz == Types<DT>::kVec) return step_ry<DT, Types<DT>::kVec, UPD>(ry, grid, a, s);
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t step_dt(int vz, int ry, bool upd, int grid, const StepArgs& a, hipStream_t s) {
+  return upd ? step_vz<DT, true>(vz, ry, grid, a, s) : step_vz<DT, false>(vz, ry, grid, a, s);
+}
+
+}  // namespace
+
+hipError_t launch_step(int dtype, int vz, int ry, bool update, int grid, const StepArgs& a,
+                       hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  switch (dtype) {
+    case kF64: return step_dt<kF64>(vz, ry, update, grid, a, s);
+    case kF32: return step_dt<kF32>(vz, ry, update, grid, a, s);
+    case kBF16: return step_dt<kBF16>(vz, ry, update, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_potential(int vdtype, void* V, int N, double ha, double a, int kind,
+                            const double* p_dev, int np, hipStream_t s) {
+  const int g = grid_for((long long)N * N * N);
+  if (vdtype == kF64)
+    hipLaunchKernelGGL(k_potential<double>, dim3(g), dim3(kBlock), 0, s, (double*)V, N, ha, a,
+                       kind, p_dev, np);
+  else
+    hipLaunchKernelGGL(k_potential<float>, dim3(g), dim3(kBlock), 0, s, (float*)V, N, ha, a, kind,
+                       p_dev, np);
+  return hipGetLastError();
+}
+
+hipError_t launch_initial(int dtype, void* psi, int N, uint64_t seed, uint32_t member, int kind,
+                          uint32_t parity, hipStream_t s) {
+  const int g = grid_for((long long)N * N * N);
+  switch (dtype) {
+    case kF64: hipLaunchKernelGGL(k_initial<double>, dim3(g), dim3(kBlock), 0, s, (double*)psi, N, seed, member, kind, parity); break;
+    case kF32: hipLaunchKernelGGL(k_initial<float>, dim3(g), dim3(kBlock), 0, s, (float*)psi, N, seed, member, kind, parity); break;
+    case kBF16: hipLaunchKernelGGL(k_initial<uint16_t>, dim3(g), dim3(kBlock), 0, s, (uint16_t*)psi, N, seed, member, kind, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+namespace {
+template <typename SS>
+hipError_t convert_to(const SS* src, int ddtype, void* dst, long long n, double scale,
+                      hipStream_t s) {
+  const int g = grid_for(n);
+  switch (ddtype) {
+    case kF64: hipLaunchKernelGGL((k_convert<SS, double>), dim3(g), dim3(kBlock), 0, s, src, (double*)dst, n, scale); break;
+    case kF32: hipLaunchKernelGGL((k_convert<SS, float>), dim3(g), dim3(kBlock), 0, s, src, (float*)dst, n, scale); break;
+    case kBF16: hipLaunchKernelGGL((k_convert<SS, uint16_t>), dim3(g), dim3(kBlock), 0, s, src, (uint16_t*)dst, n, scale); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename CS>
+hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, void* pf, int Nf,
+                       double haf, hipStream_t s) {
+  const int g = grid_for((long long)Nf * Nf * Nf);
+  switch (fdtype) {
+    case kF64: hipLaunchKernelGGL((k_upsample<CS, double>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (double*)pf, Nf, haf); break;
+    case kF32: hipLaunchKernelGGL((k_upsample<CS, float>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (float*)pf, Nf, haf); break;
+    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (uint16_t*)pf, Nf, haf); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_convert(int sdtype, const void* src, int ddtype, void* dst, long long n,
+                          double scale, hipStream_t s) {
+  switch (sdtype) {
+    case kF64: return convert_to((const double*)src, ddtype, dst, n, scale, s);
+    case kF32: return convert_to((const float*)src, ddtype, dst, n, scale, s);
+    case kBF16: return convert_to((const uint16_t*)src, ddtype, dst, n, scale, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, double ac, int fdtype,
+                           void* pf, int Nf, double haf, hipStream_t s) {
+  switch (cdtype) {
+    case kF64: return upsample_to((const double*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
+    case kF32: return upsample_to((const float*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
+    case kBF16: return upsample_to((const uint16_t*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reimpose(int dtype, void* psi, int N, uint32_t parity, hipStream_t s) {
+  const int g = grid_for((long long)N * N * N);
+  switch (dtype) {
+    case kF64: hipLaunchKernelGGL(k_reimpose<double>, dim3(g), dim3(kBlock), 0, s, (double*)psi, N, parity); break;
+    case kF32: hipLaunchKernelGGL(k_reimpose<float>, dim3(g), dim3(kBlock), 0, s, (float*)psi, N, parity); break;
+    case kBF16: hipLaunchKernelGGL(k_reimpose<uint16_t>, dim3(g), dim3(kBlock), 0, s, (uint16_t*)psi, N, parity); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(MemberState* st, int member, double scale, long long step,
+                            int reset_bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, member, scale, step, reset_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s) {
+  const int g = grid_for((long long)a.N * a.N * a.N);
+  if (dtype == kF64) hipLaunchKernelGGL(k_adjoint_step<double>, dim3(g), dim3(kBlock), 0, s, a);
+  else if (dtype == kF32) hipLaunchKernelGGL(k_adjoint_step<float>, dim3(g), dim3(kBlock), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(int dtype, const AdjInitArgs& a, hipStream_t s) {
+  const int g = grid_for((long long)a.N * a.N * a.N);
+  if (dtype == kF64) hipLaunchKernelGGL(k_adjoint_init<double>, dim3(g), dim3(kBlock), 0, s, a);
+  else if (dtype == kF32) hipLaunchKernelGGL(k_adjoint_init<float>, dim3(g), dim3(kBlock), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_wells_contract(const double* G, int N, double ha, const double* p_dev, int np,
+                                 const int* wrt_dev, int nwrt, double* partials, int nblocks,
+                                 double* out_dev, hipStream_t s) {
+  if (nwrt < 1 || nwrt > kMaxWrt || nblocks < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_wells_contract, dim3(nblocks), dim3(kBlock), 0, s, G, N, ha, p_dev, np,
+                     wrt_dev, nwrt, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kMaxWrt), 0, s, partials, nblocks, nwrt,
+                     out_dev);
+  return hipGetLastError();
+}
+
+}  // namespace fdtd

@@ -1,0 +1,1133 @@
+// Host runtime of libfdtd: handles, device memory layout, work items, the
+// evolution loop (direct launches or a replayed HIP graph), observables,
+// upsampling, the adjoint gradient driver and the launch-shape autotuner.
+// Exposes the C ABI declared in include/fdtd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fdtd.h"
+#include "fdtd_internal.h"
+
+using namespace fdtd;
+
+namespace {
+
+thread_local std::string g_err;
+
+fdtd_status fail(fdtd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+fdtd_status hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return FDTD_EHIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+#define ST_TRY(expr)                 \
+  do {                               \
+    fdtd_status s_ = (expr);         \
+    if (s_ != FDTD_OK) return s_;    \
+  } while (0)
+
+size_t elem_size(int dt) { return dt == kF64 ? 8 : (dt == kF32 ? 4 : 2); }
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+int vec_width(int dt) { return dt == kF64 ? 2 : (dt == kF32 ? 4 : 8); }
+
+struct MemberHost {
+  int N = 0;
+  double L = 0, mass = 1, dt = 0, v_inf = 0;
+  double a = 0, ha = 0, c = 0, kin_scale = 0, a3 = 0;
+  long long n3 = 0;
+  size_t off_psi[2] = {0, 0}, off_V = 0;
+  bool pot_set = false, init_set = false;
+  uint32_t parity = 0;
+  int item_begin = 0, item_end = 0;
+};
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  int K = 0, renorm = 0, src = 0;
+  fdtd_tuning tun{};
+};
+
+}  // namespace
+
+struct fdtd_ctx {
+  int count = 0;
+  int dtype = kF32;
+  int vdtype = kF32;
+  int device = 0;
+  int ring_cap = 4096;
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::vector<MemberHost> mem;
+
+  // device memory
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_owned = false;
+  size_t off_members = 0, off_states = 0, off_ring = 0, off_obs = 0, off_params = 0;
+  size_t need_bytes = 0;
+
+  // work items (library-allocated, depend on the tuning)
+  Item* d_items = nullptr;
+  double* d_partials = nullptr;
+  int n_items = 0;
+  int items_cap = 0;
+  bool items_valid = false;
+
+  int cur = 0;  // buffer holding the current state (all members)
+  fdtd_tuning tun{};
+  bool tuned = false;
+
+  // pinned host staging for small readbacks
+  double* h_pin = nullptr;
+  size_t h_pin_doubles = 0;
+
+  std::vector<GraphEntry> graphs;
+
+  MemberDev* d_members() { return reinterpret_cast<MemberDev*>(ws + off_members); }
+  MemberState* d_states() { return reinterpret_cast<MemberState*>(ws + off_states); }
+  double* d_ring() { return reinterpret_cast<double*>(ws + off_ring); }
+  double* d_obs() { return reinterpret_cast<double*>(ws + off_obs); }
+  double* d_params() { return reinterpret_cast<double*>(ws + off_params); }
+  void* psi(int m, int b) { return ws + mem[m].off_psi[b]; }
+  void* V(int m) { return ws + mem[m].off_V; }
+};
+
+namespace {
+
+constexpr int kMaxParams = 3 + 5 * 256;
+
+void compute_layout(fdtd_ctx* h) {
+  size_t off = 0;
+  const size_t es = elem_size(h->dtype), vs = elem_size(h->vdtype);
+  for (auto& m : h->mem) {
+    m.off_psi[0] = off;
+    off = align256(off + es * (size_t)m.n3);
+    m.off_psi[1] = off;
+    off = align256(off + es * (size_t)m.n3);
+    m.off_V = off;
+    off = align256(off + vs * (size_t)m.n3);
+  }
+  h->off_members = off;
+  off = align256(off + sizeof(MemberDev) * h->count);
+  h->off_states = off;
+  off = align256(off + sizeof(MemberState) * h->count);
+  h->off_ring = off;
+  off = align256(off + sizeof(double) * kRec * (size_t)h->ring_cap * h->count);
+  h->off_obs = off;
+  off = align256(off + sizeof(double) * kRec * h->count);
+  h->off_params = off;
+  off = align256(off + sizeof(double) * (kMaxParams + 64));
+  h->need_bytes = off;
+}
+
+fdtd_status validate_cfg(const fdtd_config& c, const char* who) {
+  if (c.n < 2 || c.n > 46340) return fail(FDTD_EINVAL, std::string(who) + ": n must be in [2, 46340]");
+  if (!(c.box_len > 0) || !std::isfinite(c.box_len)) return fail(FDTD_EINVAL, std::string(who) + ": box_len must be > 0");
+  if (!(c.mass > 0) || !std::isfinite(c.mass)) return fail(FDTD_EINVAL, std::string(who) + ": mass must be > 0");
+  if (!(c.dt > 0) || !std::isfinite(c.dt)) return fail(FDTD_EINVAL, std::string(who) + ": dt must be > 0");
+  if (!std::isfinite(c.v_inf)) return fail(FDTD_EINVAL, std::string(who) + ": v_inf must be finite");
+  if (c.psi_dtype < FDTD_F64 || c.psi_dtype > FDTD_BF16) return fail(FDTD_EINVAL, std::string(who) + ": bad psi_dtype");
+  if (c.history < 0) return fail(FDTD_EINVAL, std::string(who) + ": history must be >= 0");
+  const double a = c.box_len / c.n;
+  if (!(c.dt < c.mass * a * a / 3.0)) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s: dt = %.6g violates the stability bound dt < m a^2 / 3 = %.6g", who,
+             c.dt, c.mass * a * a / 3.0);
+    return fail(FDTD_EUNSTABLE, buf);
+  }
+  return FDTD_OK;
+}
+
+fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
+  if (!cfgs || !out || count < 1) return fail(FDTD_EINVAL, "create: null argument or count < 1");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    ST_TRY(validate_cfg(cfgs[i], "create"));
+    if (cfgs[i].psi_dtype != cfgs[0].psi_dtype)
+      return fail(FDTD_EINVAL, "create_batch: every member must share psi_dtype");
+  }
+  fdtd_ctx* h = new (std::nothrow) fdtd_ctx();
+  if (!h) return fail(FDTD_ENOMEM, "create: host allocation failed");
+  h->count = count;
+  h->dtype = cfgs[0].psi_dtype;
+  h->vdtype = h->dtype == kF64 ? kF64 : kF32;
+  h->device = cfgs[0].device;
+  h->ring_cap = cfgs[0].history > 0 ? cfgs[0].history : 4096;
+  h->stream = static_cast<hipStream_t>(cfgs[0].stream);
+  h->mem.resize(count);
+  for (int i = 0; i < count; ++i) {
+    MemberHost& m = h->mem[i];
+    m.N = cfgs[i].n;
+    m.L = cfgs[i].box_len;
+    m.mass = cfgs[i].mass;
+    m.dt = cfgs[i].dt;
+    m.v_inf = cfgs[i].v_inf;
+    m.a = m.L / m.N;
+    m.ha = 0.5 * m.a;
+    m.c = m.dt / (2.0 * m.mass * m.a * m.a);
+    m.kin_scale = 1.0 / (2.0 * m.mass * m.a * m.a);
+    m.a3 = m.a * m.a * m.a;
+    m.n3 = (long long)m.N * m.N * m.N;
+  }
+  compute_layout(h);
+  // default launch shape: widest vector the sizes allow
+  const int vw = vec_width(h->dtype);
+  bool all_div = true;
+  for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
+  h->tun.vz = all_div ? vw : 1;
+  h->tun.ry = 2;
+  h->tun.xchunk = 32;
+  h->tun.grid = 0;
+  h->tun.xcd_remap = 1;
+  *out = h;
+  return FDTD_OK;
+}
+
+fdtd_status set_device(fdtd_ctx* h) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(FDTD_EHIP, "no HIP device available (the library has no CPU fallback)");
+  if (h->device < 0 || h->device >= n) return fail(FDTD_EINVAL, "device ordinal out of range");
+  HIP_TRY(hipSetDevice(h->device));
+  return FDTD_OK;
+}
+
+MemberDev member_dev(fdtd_ctx* h, int i) {
+  const MemberHost& m = h->mem[i];
+  MemberDev d;
+  memset(&d, 0, sizeof d);
+  d.psi[0] = h->psi(i, 0);
+  d.psi[1] = h->psi(i, 1);
+  d.V = h->V(i);
+  d.N = m.N;
+  d.item_begin = m.item_begin;
+  d.item_end = m.item_end;
+  d.plane = (long long)m.N * m.N;
+  d.ha = m.ha;
+  d.c = m.c;
+  d.dt = m.dt;
+  d.kin_scale = m.kin_scale;
+  d.a3 = m.a3;
+  return d;
+}
+
+fdtd_status upload_members(fdtd_ctx* h) {
+  std::vector<MemberDev> md(h->count);
+  for (int i = 0; i < h->count; ++i) md[i] = member_dev(h, i);
+  HIP_TRY(hipMemcpyAsync(h->d_members(), md.data(), sizeof(MemberDev) * h->count,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));  // md is a temporary
+  return FDTD_OK;
+}
+
+// Device memory: bound workspace or a library allocation, made on first use.
+fdtd_status ensure_memory(fdtd_ctx* h) {
+  ST_TRY(set_device(h));
+  if (!h->ws) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, h->need_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDTD_ENOMEM, "device allocation of the workspace failed");
+    }
+    h->ws = static_cast<char*>(p);
+    h->ws_bytes = h->need_bytes;
+    h->ws_owned = true;
+    for (int m = 0; m < h->count; ++m) HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
+  }
+  if (!h->h_pin) {
+    h->h_pin_doubles = (size_t)kRec * (h->count + 8) + 4096;
+    HIP_TRY(hipHostMalloc((void**)&h->h_pin, h->h_pin_doubles * sizeof(double), hipHostMallocDefault));
+  }
+  return FDTD_OK;
+}
+
+void xcd_permute(std::vector<int>& pos, int n) {
+  // hardware dispatches work-group b to XCD b % 8: give each XCD a contiguous
+  // run of work items so tiles that share halos share an L2
+  pos.resize(n);
+  const int q = n / 8;
+  for (int b = 0; b < n; ++b) pos[b] = (b < 8 * q) ? (b % 8) * q + b / 8 : b;
+}
+
+fdtd_status build_items(fdtd_ctx* h) {
+  if (h->items_valid) return FDTD_OK;
+  const fdtd_tuning& t = h->tun;
+  std::vector<Item> phys;
+  for (int i = 0; i < h->count; ++i) {
+    MemberHost& m = h->mem[i];
+    const long long P = (long long)m.N * m.N;
+    const long long F = (long long)kBlock * t.vz * t.ry;
+    const int nchunk = (int)((P + F - 1) / F);
+    const int xc = std::max(1, std::min(t.xchunk, m.N));
+    const int nx = (m.N + xc - 1) / xc;
+    m.item_begin = (int)phys.size();
+    for (int bx = 0; bx < nx; ++bx)
+      for (int ch = 0; ch < nchunk; ++ch) {
+        Item it;
+        it.member = i;
+        it.f0 = (int)(ch * F);
+        it.xb = bx * xc;
+        it.xe = std::min(m.N, (bx + 1) * xc);
+        phys.push_back(it);
+      }
+    m.item_end = (int)phys.size();
+  }
+  const int n = (int)phys.size();
+  // Processing order: within each member (items stay member-contiguous, so a
+  // member's partial slots are its position range), optionally permuted so
+  // that the work-groups one XCD runs take neighbouring tiles.
+  std::vector<Item> order;
+  order.reserve(n);
+  for (int i = 0; i < h->count; ++i) {
+    const MemberHost& m = h->mem[i];
+    const int cnt = m.item_end - m.item_begin;
+    std::vector<int> p;
+    if (t.xcd_remap) xcd_permute(p, cnt);
+    else {
+      p.resize(cnt);
+      for (int b = 0; b < cnt; ++b) p[b] = b;
+    }
+    for (int b = 0; b < cnt; ++b) order.push_back(phys[m.item_begin + p[b]]);
+  }
+  if (n > h->items_cap) {
+    if (h->d_items) (void)hipFree(h->d_items);
+    if (h->d_partials) (void)hipFree(h->d_partials);
+    h->d_items = nullptr;
+    h->d_partials = nullptr;
+    h->items_cap = 0;
+    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * n);
+    hipError_t e2 = hipMalloc((void**)&h->d_partials, sizeof(double) * kRec * n);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDTD_ENOMEM, "device allocation of work items failed");
+    }
+    h->items_cap = n;
+  }
+  HIP_TRY(hipMemcpyAsync(h->d_items, order.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->n_items = n;
+  ST_TRY(upload_members(h));
+  h->items_valid = true;
+  return FDTD_OK;
+}
+
+int launch_grid(const fdtd_ctx* h, int n_items) {
+  if (h->tun.grid > 0) return std::min(h->tun.grid, n_items);
+  return n_items;
+}
+
+StepArgs base_args(fdtd_ctx* h) {
+  StepArgs a;
+  memset(&a, 0, sizeof a);
+  a.members = h->d_members();
+  a.states = h->d_states();
+  a.items = h->d_items;
+  a.n_items = h->n_items;
+  a.item_offset = 0;
+  a.src = h->cur;
+  a.partials = h->d_partials;
+  a.ring = h->d_ring();
+  a.ring_cap = h->ring_cap;
+  a.obs_out = h->d_obs();
+  return a;
+}
+
+// Reduction-only pass over member m (-1: all); optionally sets the scale of
+// the next step to 1/sqrt(a^3 S0).  Results land in d_obs.
+fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
+  ST_TRY(build_items(h));
+  StepArgs a = base_args(h);
+  a.set_scale = set_scale ? 1 : 0;
+  if (member >= 0) {
+    a.item_offset = h->mem[member].item_begin;
+    a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
+  }
+  HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, false, launch_grid(h, a.n_items), a, h->stream));
+  return FDTD_OK;
+}
+
+fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
+  for (int k = 0; k < n; ++k) {
+    StepArgs a = base_args(h);
+    a.renorm_every = renorm_every;
+    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, true, launch_grid(h, a.n_items), a, s));
+    h->cur ^= 1;
+  }
+  return FDTD_OK;
+}
+
+bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
+  return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
+         a.xcd_remap == b.xcd_remap;
+}
+
+void drop_graphs(fdtd_ctx* h) {
+  for (auto& g : h->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  h->graphs.clear();
+}
+
+// Run K steps through a cached, replayed HIP graph.
+fdtd_status graph_steps(fdtd_ctx* h, int K, int renorm_every) {
+  GraphEntry* ge = nullptr;
+  for (auto& g : h->graphs)
+    if (g.K == K && g.renorm == renorm_every && g.src == h->cur && same_tuning(g.tun, h->tun)) ge = &g;
+  if (!ge) {
+    if (!h->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    const int cur0 = h->cur;
+    HIP_TRY(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    fdtd_status st = launch_steps(h, K, renorm_every, h->capture_stream);
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
+    h->cur = cur0;
+    if (st != FDTD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    if (h->graphs.size() >= 8) drop_graphs(h);
+    GraphEntry g;
+    g.exec = exec;
+    g.K = K;
+    g.renorm = renorm_every;
+    g.src = cur0;
+    g.tun = h->tun;
+    h->graphs.push_back(g);
+    ge = &h->graphs.back();
+  }
+  HIP_TRY(hipGraphLaunch(ge->exec, h->stream));
+  if (K & 1) h->cur ^= 1;
+  return FDTD_OK;
+}
+
+fdtd_status require_ready(fdtd_ctx* h) {
+  for (int i = 0; i < h->count; ++i) {
+    if (!h->mem[i].pot_set) return fail(FDTD_ENOTREADY, "potential not set for member " + std::to_string(i));
+    if (!h->mem[i].init_set) return fail(FDTD_ENOTREADY, "initial state not set for member " + std::to_string(i));
+  }
+  return FDTD_OK;
+}
+
+// Copy member states (device) to host pinned staging.
+fdtd_status read_states(fdtd_ctx* h, std::vector<MemberState>& out) {
+  out.resize(h->count);
+  HIP_TRY(hipMemcpyAsync(out.data(), h->d_states(), sizeof(MemberState) * h->count,
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FDTD_OK;
+}
+
+fdtd_status check_bad(fdtd_ctx* h, const std::vector<MemberState>& st) {
+  for (int i = 0; i < h->count; ++i)
+    if (st[i].bad) {
+      char buf[128];
+      snprintf(buf, sizeof buf, "non-finite reduction in member %d at step %lld", i,
+               (long long)st[i].bad_step);
+      return fail(FDTD_ENONFINITE, buf);
+    }
+  return FDTD_OK;
+}
+
+fdtd_obs to_obs(const MemberHost& m, const double* r, long long step) {
+  fdtd_obs o;
+  const double s0 = r[kS0];
+  o.norm2 = m.a3 * s0;
+  o.kinetic = r[kKin] / s0;
+  o.potential = r[kPot] / s0;
+  o.energy = (r[kKin] + r[kPot]) / s0;
+  o.r_rms = std::sqrt(r[kR2] / s0);
+  o.binding = o.energy - m.v_inf;
+  o.step = step;
+  o.tau = (double)step * m.dt;
+  return o;
+}
+
+fdtd_status copy_in_field(fdtd_ctx* h, const void* src, int sdtype, int on_device, int ddtype,
+                          void* dst, long long n) {
+  if (sdtype < FDTD_F64 || sdtype > FDTD_BF16) return fail(FDTD_EINVAL, "bad source dtype");
+  const size_t bytes = elem_size(sdtype) * (size_t)n;
+  const void* dsrc = src;
+  void* tmp = nullptr;
+  if (!on_device) {
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDTD_ENOMEM, "staging allocation failed");
+    }
+    e = hipMemcpyAsync(tmp, src, bytes, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return hip_fail(e, "hipMemcpyAsync H2D");
+    }
+    dsrc = tmp;
+  }
+  hipError_t e = launch_convert(sdtype, dsrc, ddtype, dst, n, 1.0, h->stream);
+  if (tmp) {
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+  }
+  if (e != hipSuccess) return hip_fail(e, "convert kernel");
+  return FDTD_OK;
+}
+
+fdtd_status check_member(fdtd_ctx* h, int member, bool allow_all) {
+  if (member == -1 && allow_all) return FDTD_OK;
+  if (member < 0 || member >= h->count) return fail(FDTD_EINVAL, "member index out of range");
+  return FDTD_OK;
+}
+
+// after a new initial state: zero step, clear flags, scale = 1/norm
+fdtd_status start_state(fdtd_ctx* h, int m) {
+  HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
+  ST_TRY(observe(h, m, true));
+  h->mem[m].init_set = true;
+  return FDTD_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, fdtd_tuning> g_tune_cache;
+
+std::string tune_key(const fdtd_ctx* h) {
+  std::string k = std::to_string(h->device) + ":" + std::to_string(h->dtype);
+  for (auto& m : h->mem) k += ":" + std::to_string(m.N);
+  return k;
+}
+
+fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
+  if (t.vz != 1 && t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: vz must be 1 or the dtype's vector width");
+  for (auto& m : h->mem)
+    if (m.N % t.vz != 0) return fail(FDTD_EINVAL, "tuning: vz must divide every N");
+  if (t.ry != 1 && t.ry != 2 && t.ry != 4) return fail(FDTD_EINVAL, "tuning: ry must be 1, 2 or 4");
+  if (t.xchunk < 1) return fail(FDTD_EINVAL, "tuning: xchunk must be >= 1");
+  if (t.grid < 0) return fail(FDTD_EINVAL, "tuning: grid must be >= 0");
+  return FDTD_OK;
+}
+
+}  // namespace
+
+// =============================================================== C ABI =====
+extern "C" {
+
+fdtd_status fdtd_create(const fdtd_config* cfg, fdtd_t* out) { return make_ctx(cfg, 1, out); }
+
+fdtd_status fdtd_create_batch(const fdtd_config* cfgs, int32_t count, fdtd_t* out) {
+  return make_ctx(cfgs, count, out);
+}
+
+fdtd_status fdtd_workspace_size(fdtd_t h, size_t* bytes) {
+  if (!h || !bytes) return fail(FDTD_EINVAL, "workspace_size: null argument");
+  *bytes = h->need_bytes;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_bind_workspace(fdtd_t h, void* dev_ptr, size_t bytes) {
+  if (!h || !dev_ptr) return fail(FDTD_EINVAL, "bind_workspace: null argument");
+  if (h->ws) return fail(FDTD_EINVAL, "bind_workspace: the handle already has device memory");
+  if (bytes < h->need_bytes) return fail(FDTD_ENOMEM, "bind_workspace: workspace smaller than fdtd_workspace_size");
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return fail(FDTD_EINVAL, "bind_workspace: pointer must be 256-byte aligned");
+  ST_TRY(set_device(h));
+  h->ws = static_cast<char*>(dev_ptr);
+  h->ws_bytes = bytes;
+  h->ws_owned = false;
+  for (int m = 0; m < h->count; ++m) HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_destroy(fdtd_t h) {
+  if (!h) return FDTD_OK;
+  if (h->ws || h->h_pin || h->d_items) {
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+  }
+  drop_graphs(h);
+  if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  if (h->d_items) (void)hipFree(h->d_items);
+  if (h->d_partials) (void)hipFree(h->d_partials);
+  if (h->ws && h->ws_owned) (void)hipFree(h->ws);
+  if (h->h_pin) (void)hipHostFree(h->h_pin);
+  delete h;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_set_potential(fdtd_t h, int32_t member, const void* v, int32_t dtype,
+                               int32_t on_device) {
+  if (!h || !v) return fail(FDTD_EINVAL, "set_potential: null argument");
+  ST_TRY(check_member(h, member, false));
+  if (dtype != FDTD_F64 && dtype != FDTD_F32) return fail(FDTD_EINVAL, "set_potential: dtype must be F64 or F32");
+  ST_TRY(ensure_memory(h));
+  ST_TRY(copy_in_field(h, v, dtype, on_device, h->vdtype, h->V(member), h->mem[member].n3));
+  h->mem[member].pot_set = true;
+  drop_graphs(h);
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, const double* p,
+                                        int32_t np) {
+  if (!h) return fail(FDTD_EINVAL, "set_potential_analytic: null handle");
+  ST_TRY(check_member(h, member, true));
+  if (kind < FDTD_POT_CONST || kind > FDTD_POT_WELLS) return fail(FDTD_EINVAL, "set_potential_analytic: unknown kind");
+  const int need = (kind == FDTD_POT_HO || kind == FDTD_POT_CORNELL) ? 3 : (kind == FDTD_POT_WELLS ? 3 : 1);
+  if (np < need || (np > 0 && !p)) return fail(FDTD_EINVAL, "set_potential_analytic: too few parameters");
+  if (kind == FDTD_POT_WELLS && (np - 3) % 5 != 0) return fail(FDTD_EINVAL, "set_potential_analytic: wells need 3 + 5k parameters");
+  if (np > kMaxParams) return fail(FDTD_EINVAL, "set_potential_analytic: too many parameters");
+  for (int i = 0; i < np; ++i)
+    if (!std::isfinite(p[i])) return fail(FDTD_EINVAL, "set_potential_analytic: non-finite parameter");
+  ST_TRY(ensure_memory(h));
+  HIP_TRY(hipMemcpyAsync(h->d_params(), p, sizeof(double) * np, hipMemcpyHostToDevice, h->stream));
+  const int m0 = member < 0 ? 0 : member, m1 = member < 0 ? h->count : member + 1;
+  for (int m = m0; m < m1; ++m) {
+    const MemberHost& mh = h->mem[m];
+    HIP_TRY(launch_potential(h->vdtype, h->V(m), mh.N, mh.ha, mh.a, kind, h->d_params(), np, h->stream));
+    h->mem[m].pot_set = true;
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));  // p is the caller's host memory
+  drop_graphs(h);
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_set_initial(fdtd_t h, int32_t member, int32_t kind, uint64_t seed, uint32_t parity,
+                             const void* user, int32_t dtype, int32_t on_device) {
+  if (!h) return fail(FDTD_EINVAL, "set_initial: null handle");
+  ST_TRY(check_member(h, member, true));
+  if (kind < FDTD_INIT_UNIFORM || kind > FDTD_INIT_USER) return fail(FDTD_EINVAL, "set_initial: unknown kind");
+  if (parity >> 6) return fail(FDTD_EINVAL, "set_initial: parity uses bits 0-5 only");
+  for (int ax = 0; ax < 3; ++ax)
+    if (((parity >> (2 * ax)) & 3u) == 3u) return fail(FDTD_EINVAL, "set_initial: parity code 3 is invalid");
+  if (kind == FDTD_INIT_USER && (!user || member < 0)) return fail(FDTD_EINVAL, "set_initial: USER needs a buffer and one member");
+  if (kind == FDTD_INIT_USER && (dtype < FDTD_F64 || dtype > FDTD_BF16)) return fail(FDTD_EINVAL, "set_initial: bad user dtype");
+  ST_TRY(ensure_memory(h));
+  const int m0 = member < 0 ? 0 : member, m1 = member < 0 ? h->count : member + 1;
+  for (int m = m0; m < m1; ++m) {
+    const MemberHost& mh = h->mem[m];
+    if (kind == FDTD_INIT_USER) {
+      ST_TRY(copy_in_field(h, user, dtype, on_device, h->dtype, h->psi(m, h->cur), mh.n3));
+    } else {
+      HIP_TRY(launch_initial(h->dtype, h->psi(m, h->cur), mh.N, seed, (uint32_t)m, kind, parity, h->stream));
+    }
+    h->mem[m].parity = parity;
+  }
+  for (int m = m0; m < m1; ++m) {
+    ST_TRY(start_state(h, m));
+    HIP_TRY(hipMemcpyAsync(h->h_pin, h->d_obs() + (size_t)m * kRec, sizeof(double) * kRec,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double s0 = h->h_pin[kS0];
+    if (!(s0 > 0) || !std::isfinite(s0)) {
+      h->mem[m].init_set = false;
+      return fail(FDTD_ENONFINITE, "set_initial: the initial state has a zero or non-finite norm");
+    }
+  }
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* o, int64_t* steps_done, int32_t* converged) {
+  if (!h || !o) return fail(FDTD_EINVAL, "evolve: null argument");
+  if (o->max_steps < 0 || o->renorm_every < 0 || o->check_every < 0 || o->reimpose_parity_every < 0)
+    return fail(FDTD_EINVAL, "evolve: negative option");
+  if (o->check_every > 0 && !(o->rel_tol >= 0)) return fail(FDTD_EINVAL, "evolve: rel_tol must be >= 0");
+  if (steps_done) *steps_done = 0;
+  if (converged) *converged = 0;
+  ST_TRY(require_ready(h));
+  ST_TRY(ensure_memory(h));
+  ST_TRY(build_items(h));
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  ST_TRY(check_bad(h, st));
+  const long long step0 = st[0].step;
+  const int K = o->check_every > 0 ? o->check_every : 64;
+  const int P = o->reimpose_parity_every;
+  std::vector<double> e_prev(h->count, NAN);
+  long long done = 0;
+  bool conv = false;
+  while (done < o->max_steps) {
+    long long n = std::min<long long>(K, o->max_steps - done);
+    if (P > 0) n = std::min<long long>(n, P - (done % P));
+    if (o->use_graph && n == K && P == 0) ST_TRY(graph_steps(h, K, o->renorm_every));
+    else ST_TRY(launch_steps(h, (int)n, o->renorm_every, h->stream));
+    done += n;
+    if (P > 0 && done % P == 0)
+      for (int m = 0; m < h->count; ++m)
+        if (h->mem[m].parity) HIP_TRY(launch_reimpose(h->dtype, h->psi(m, h->cur), h->mem[m].N, h->mem[m].parity, h->stream));
+    const bool check = o->check_every > 0 && done % K == 0;
+    if (check) {
+      const long long t = step0 + done - 1;  // the step whose input is checked
+      double* pin = h->h_pin;
+      for (int m = 0; m < h->count; ++m)
+        HIP_TRY(hipMemcpyAsync(pin + (size_t)m * kRec,
+                               h->d_ring() + ((size_t)m * h->ring_cap + (size_t)(t % h->ring_cap)) * kRec,
+                               sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+      ST_TRY(read_states(h, st));
+      ST_TRY(check_bad(h, st));
+      bool all = true;
+      for (int m = 0; m < h->count; ++m) {
+        const double* r = pin + (size_t)m * kRec;
+        const double e = (r[kKin] + r[kPot]) / r[kS0];
+        const bool c = !std::isnan(e_prev[m]) &&
+                       std::fabs(e - e_prev[m]) <= o->rel_tol * std::fabs(e - h->mem[m].v_inf);
+        all = all && c;
+        e_prev[m] = e;
+      }
+      if (all) {
+        conv = true;
+        break;
+      }
+    }
+  }
+  ST_TRY(read_states(h, st));
+  if (steps_done) *steps_done = done;
+  if (converged) *converged = conv ? 1 : 0;
+  ST_TRY(check_bad(h, st));
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_observables(fdtd_t h, fdtd_obs* out) {
+  if (!h || !out) return fail(FDTD_EINVAL, "observables: null argument");
+  ST_TRY(require_ready(h));
+  ST_TRY(ensure_memory(h));
+  ST_TRY(observe(h, -1, false));
+  double* pin = h->h_pin;
+  HIP_TRY(hipMemcpyAsync(pin, h->d_obs(), sizeof(double) * kRec * h->count, hipMemcpyDeviceToHost, h->stream));
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  for (int m = 0; m < h->count; ++m) out[m] = to_obs(h->mem[m], pin + (size_t)m * kRec, st[m].step);
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_history(fdtd_t h, int32_t member, fdtd_obs* out, int64_t max, int64_t* count) {
+  if (!h || !out || !count || max < 0) return fail(FDTD_EINVAL, "history: bad argument");
+  ST_TRY(check_member(h, member, false));
+  *count = 0;
+  if (!h->ws) return FDTD_OK;
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  const long long steps = st[member].step;
+  const long long n = std::min<long long>({(long long)max, steps, (long long)h->ring_cap});
+  std::vector<double> buf((size_t)h->ring_cap * kRec);
+  HIP_TRY(hipMemcpyAsync(buf.data(), h->d_ring() + (size_t)member * h->ring_cap * kRec,
+                         sizeof(double) * kRec * h->ring_cap, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (long long k = 0; k < n; ++k) {
+    const long long t = steps - n + k;
+    const double* r = buf.data() + (size_t)(t % h->ring_cap) * kRec;
+    out[k] = to_obs(h->mem[member], r, t);
+  }
+  *count = n;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int32_t on_device) {
+  if (!h || !dst) return fail(FDTD_EINVAL, "get_psi: null argument");
+  ST_TRY(check_member(h, member, false));
+  if (dtype < FDTD_F64 || dtype > FDTD_BF16) return fail(FDTD_EINVAL, "get_psi: bad dtype");
+  if (!h->mem[member].init_set) return fail(FDTD_ENOTREADY, "get_psi: no state set");
+  ST_TRY(ensure_memory(h));
+  ST_TRY(build_items(h));
+  // norm of the stored state from a reduction pass
+  {
+    StepArgs a = base_args(h);
+    a.item_offset = h->mem[member].item_begin;
+    a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
+    // the reduction needs V only for the energy sums; it is harmless if unset
+    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, false, launch_grid(h, a.n_items), a, h->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(h->h_pin, h->d_obs() + (size_t)member * kRec, sizeof(double) * kRec,
+                         hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const MemberHost& m = h->mem[member];
+  const double s0 = h->h_pin[kS0];
+  if (!(s0 > 0) || !std::isfinite(s0)) return fail(FDTD_ENONFINITE, "get_psi: state has zero or non-finite norm");
+  const double scale = 1.0 / std::sqrt(m.a3 * s0);
+  const size_t bytes = elem_size(dtype) * (size_t)m.n3;
+  if (on_device) {
+    HIP_TRY(launch_convert(h->dtype, h->psi(member, h->cur), dtype, dst, m.n3, scale, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  } else {
+    void* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDTD_ENOMEM, "get_psi: staging allocation failed");
+    }
+    e = launch_convert(h->dtype, h->psi(member, h->cur), dtype, tmp, m.n3, scale, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, bytes, hipMemcpyDeviceToHost, h->stream);
+    hipError_t e2 = hipStreamSynchronize(h->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(e, "get_psi copy");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamSynchronize");
+  }
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_get_state(fdtd_t h, int32_t member, void* dst, int32_t on_device, int64_t* step) {
+  if (!h || !dst) return fail(FDTD_EINVAL, "get_state: null argument");
+  ST_TRY(check_member(h, member, false));
+  if (!h->mem[member].init_set) return fail(FDTD_ENOTREADY, "get_state: no state set");
+  ST_TRY(ensure_memory(h));
+  const size_t bytes = elem_size(h->dtype) * (size_t)h->mem[member].n3;
+  HIP_TRY(hipMemcpyAsync(dst, h->psi(member, h->cur), bytes,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  if (step) *step = st[member].step;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_upsample(fdtd_t coarse, int32_t cm, fdtd_t fine, int32_t fm) {
+  if (!coarse || !fine) return fail(FDTD_EINVAL, "upsample: null handle");
+  ST_TRY(check_member(coarse, cm, false));
+  ST_TRY(check_member(fine, fm, false));
+  if (coarse->device != fine->device) return fail(FDTD_EINVAL, "upsample: handles on different devices");
+  const MemberHost& c = coarse->mem[cm];
+  MemberHost& f = fine->mem[fm];
+  if (std::fabs(c.L - f.L) > 1e-12 * std::max(c.L, f.L)) return fail(FDTD_EINVAL, "upsample: box lengths differ");
+  if (!c.init_set) return fail(FDTD_ENOTREADY, "upsample: coarse state not set");
+  if (!f.pot_set) return fail(FDTD_ENOTREADY, "upsample: fine potential not set");
+  ST_TRY(ensure_memory(coarse));
+  ST_TRY(ensure_memory(fine));
+  // order the fine stream after the coarse work
+  HIP_TRY(hipStreamSynchronize(coarse->stream));
+  HIP_TRY(launch_upsample(coarse->dtype, coarse->psi(cm, coarse->cur), c.N, c.ha, c.a, fine->dtype,
+                          fine->psi(fm, fine->cur), f.N, f.ha, fine->stream));
+  f.parity = c.parity;
+  ST_TRY(start_state(fine, fm));
+  HIP_TRY(hipStreamSynchronize(fine->stream));
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out) {
+  if (!h || !out) return fail(FDTD_EINVAL, "get_tuning: null argument");
+  *out = h->tun;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t) {
+  if (!h || !t) return fail(FDTD_EINVAL, "set_tuning: null argument");
+  ST_TRY(validate_tuning(h, *t));
+  if (!same_tuning(*t, h->tun)) {
+    h->tun = *t;
+    h->items_valid = false;
+  }
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_synchronize(fdtd_t h) {
+  if (!h) return fail(FDTD_EINVAL, "synchronize: null handle");
+  if (!h->ws) return FDTD_OK;
+  HIP_TRY(hipSetDevice(h->device));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_info(fdtd_t h, int32_t* count, void** stream) {
+  if (!h) return fail(FDTD_EINVAL, "info: null handle");
+  if (count) *count = h->count;
+  if (stream) *stream = h->stream;
+  return FDTD_OK;
+}
+
+const char* fdtd_status_string(fdtd_status s) {
+  switch (s) {
+    case FDTD_OK: return "FDTD_OK";
+    case FDTD_EINVAL: return "FDTD_EINVAL: invalid argument";
+    case FDTD_ENOMEM: return "FDTD_ENOMEM: out of memory";
+    case FDTD_EHIP: return "FDTD_EHIP: HIP runtime error";
+    case FDTD_EUNSTABLE: return "FDTD_EUNSTABLE: dt >= m a^2 / 3";
+    case FDTD_ENOTREADY: return "FDTD_ENOTREADY: potential or initial state not set";
+    case FDTD_ENONFINITE: return "FDTD_ENONFINITE: non-finite reduction";
+  }
+  return "unknown fdtd_status";
+}
+
+const char* fdtd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotune --
+extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen,
+                                     double* best_ms) {
+  if (!h) return fail(FDTD_EINVAL, "autotune: null handle");
+  if (steps_per_trial < 2) return fail(FDTD_EINVAL, "autotune: steps_per_trial must be >= 2");
+  ST_TRY(require_ready(h));
+  ST_TRY(ensure_memory(h));
+  const std::string key = tune_key(h);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      ST_TRY(fdtd_set_tuning(h, &it->second));
+      if (chosen) *chosen = it->second;
+      if (best_ms) *best_ms = -1.0;
+      return FDTD_OK;
+    }
+  }
+  // save the state: both buffers, the member states
+  size_t field_bytes = 0;
+  for (auto& m : h->mem) field_bytes += elem_size(h->dtype) * (size_t)m.n3;
+  char* save = nullptr;
+  hipError_t e = hipMalloc((void**)&save, field_bytes + sizeof(MemberState) * h->count);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDTD_ENOMEM, "autotune: no memory to save the state");
+  }
+  const int cur0 = h->cur;
+  size_t off = 0;
+  for (int m = 0; m < h->count; ++m) {
+    const size_t b = elem_size(h->dtype) * (size_t)h->mem[m].n3;
+    (void)hipMemcpyAsync(save + off, h->psi(m, cur0), b, hipMemcpyDeviceToDevice, h->stream);
+    off += b;
+  }
+  (void)hipMemcpyAsync(save + off, h->d_states(), sizeof(MemberState) * h->count, hipMemcpyDeviceToDevice, h->stream);
+
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const fdtd_tuning orig = h->tun;
+  fdtd_tuning best = orig;
+  double best_t = 1e30;
+  fdtd_status st = FDTD_OK;
+  const int vw = vec_width(h->dtype);
+  int maxN = 0;
+  for (auto& m : h->mem) maxN = std::max(maxN, m.N);
+  std::vector<int> vzs = {1};
+  bool all_div = true;
+  for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
+  if (all_div) vzs.push_back(vw);
+  for (int vz : vzs)
+    for (int ry : {1, 2, 4})
+      for (int xc : {8, 16, 32, 64, 128})
+        for (int remap : {0, 1}) {
+          if (xc > maxN && xc != 8) continue;
+          fdtd_tuning t{vz, ry, xc, 0, remap};
+          if (validate_tuning(h, t) != FDTD_OK) continue;
+          h->tun = t;
+          h->items_valid = false;
+          if ((st = build_items(h)) != FDTD_OK) goto done;
+          if ((st = launch_steps(h, 1, 1, h->stream)) != FDTD_OK) goto done;  // warm-up
+          (void)hipEventRecord(e0, h->stream);
+          if ((st = launch_steps(h, steps_per_trial, 1, h->stream)) != FDTD_OK) goto done;
+          (void)hipEventRecord(e1, h->stream);
+          if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hip_fail(e, "autotune timing");
+            goto done;
+          }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double per = ms / steps_per_trial;
+          if (per < best_t) {
+            best_t = per;
+            best = t;
+          }
+        }
+done:
+  // restore
+  h->cur = cur0;
+  off = 0;
+  for (int m = 0; m < h->count; ++m) {
+    const size_t b = elem_size(h->dtype) * (size_t)h->mem[m].n3;
+    (void)hipMemcpyAsync(h->psi(m, cur0), save + off, b, hipMemcpyDeviceToDevice, h->stream);
+    off += b;
+  }
+  (void)hipMemcpyAsync(h->d_states(), save + off, sizeof(MemberState) * h->count, hipMemcpyDeviceToDevice, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(save);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tun = (st == FDTD_OK) ? best : orig;
+  h->items_valid = false;
+  drop_graphs(h);
+  if (st != FDTD_OK) return st;
+  ST_TRY(build_items(h));
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
+  if (chosen) *chosen = best;
+  if (best_ms) *best_ms = best_t;
+  return FDTD_OK;
+}
+
+// ---------------------------------------------------------------- gradient --
+extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,
+                                        const double* theta, int32_t ntheta, const int32_t* wrt,
+                                        int32_t nwrt, void* dE_dV, double* dE_dtheta,
+                                        double* energy) {
+  if (!h) return fail(FDTD_EINVAL, "energy_grad: null handle");
+  if (h->count != 1) return fail(FDTD_EINVAL, "energy_grad: single-lattice handles only");
+  if (h->dtype == kBF16) return fail(FDTD_EINVAL, "energy_grad: psi dtype must be F64 or F32");
+  if (steps < 1 || checkpoint_every < 1) return fail(FDTD_EINVAL, "energy_grad: steps and checkpoint_every must be >= 1");
+  if (nwrt > 0) {
+    if (!theta || !wrt || !dE_dtheta || nwrt > 64) return fail(FDTD_EINVAL, "energy_grad: theta, wrt and dE_dtheta needed (nwrt <= 64)");
+    if (ntheta < 8 || (ntheta - 3) % 5 != 0 || ntheta > kMaxParams) return fail(FDTD_EINVAL, "energy_grad: theta must be a wells parameter vector");
+    for (int k = 0; k < nwrt; ++k) {
+      const int j = wrt[k];
+      if (j < 3 || j >= ntheta || ((j - 3) % 5 != 0 && (j - 3) % 5 != 4))
+        return fail(FDTD_EINVAL, "energy_grad: wrt entries must index A_k or s_k");
+    }
+  }
+  ST_TRY(require_ready(h));
+  ST_TRY(ensure_memory(h));
+  ST_TRY(build_items(h));
+  const MemberHost& m = h->mem[0];
+  const size_t es = elem_size(h->dtype);
+  const size_t fb = align256(es * (size_t)m.n3);
+  const int T = steps, k = checkpoint_every;
+  const int nck = (T + k - 1) / k;
+  const int seg = std::min(k, T);
+  // device buffers: checkpoints, one segment of states, two adjoints, G, descriptors
+  const size_t bytes = fb * (size_t)nck + fb * (size_t)(seg + 1) + 2 * fb +
+                       align256(sizeof(double) * (size_t)m.n3) + align256(sizeof(MemberDev) * seg) +
+                       align256(sizeof(MemberState) * (size_t)(nck + 1)) + 65536 * sizeof(double);
+  char* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FDTD_ENOMEM, "energy_grad: cannot allocate checkpoint memory");
+  }
+  struct Free {
+    char* p;
+    ~Free() { if (p) (void)hipFree(p); }
+  } guard{buf};
+  char* q = buf;
+  char* ck = q; q += fb * (size_t)nck;
+  char* sg = q; q += fb * (size_t)(seg + 1);
+  char* lam[2] = {q, q + fb}; q += 2 * fb;
+  double* G = reinterpret_cast<double*>(q); q += align256(sizeof(double) * (size_t)m.n3);
+  MemberDev* descs = reinterpret_cast<MemberDev*>(q); q += align256(sizeof(MemberDev) * seg);
+  MemberState* cks = reinterpret_cast<MemberState*>(q); q += align256(sizeof(MemberState) * (size_t)(nck + 1));
+  double* scratch = reinterpret_cast<double*>(q);
+
+  std::vector<double> scales((size_t)T, 1.0);
+  std::vector<double> rec((size_t)seg * kRec);
+  // ---- forward, checkpointing every k steps
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  ST_TRY(check_bad(h, st));
+  for (int j = 0; j < nck; ++j) {
+    const int len = std::min(k, T - j * k);
+    HIP_TRY(hipMemcpyAsync(ck + fb * j, h->psi(0, h->cur), es * (size_t)m.n3, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(cks + j, h->d_states(), sizeof(MemberState), hipMemcpyDeviceToDevice, h->stream));
+    ST_TRY(read_states(h, st));
+    const long long t0 = st[0].step;
+    ST_TRY(launch_steps(h, len, 1, h->stream));
+    // scales folded into each step, from the history ring
+    for (int i = 0; i < len; ++i) {
+      const long long t = t0 + i;
+      HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)i * kRec, h->d_ring() + (size_t)(t % h->ring_cap) * kRec,
+                             sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < len; ++i) scales[(size_t)j * k + i] = rec[(size_t)i * kRec + kScale];
+  }
+  ST_TRY(read_states(h, st));
+  ST_TRY(check_bad(h, st));
+  // ---- energy of psi_T
+  ST_TRY(observe(h, 0, false));
+  HIP_TRY(hipMemcpyAsync(h->h_pin, h->d_obs(), sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  const double S0 = h->h_pin[kS0];
+  const double E = (h->h_pin[kKin] + h->h_pin[kPot]) / S0;
+  if (!std::isfinite(E) || !(S0 > 0)) return fail(FDTD_ENONFINITE, "energy_grad: non-finite final energy");
+  // ---- adjoint start: lambda_T = 2 (H psi_T - E psi_T) / S0, G = psi_T^2 / S0
+  {
+    AdjInitArgs a;
+    memset(&a, 0, sizeof a);
+    a.V = h->V(0);
+    a.psi = h->psi(0, h->cur);
+    a.lam = lam[0];
+    a.G = G;
+    a.N = m.N;
+    a.kin_scale = m.kin_scale;
+    a.E = E;
+    a.S0 = S0;
+    HIP_TRY(launch_adjoint_init(h->dtype, a, h->stream));
+  }
+  int lc = 0;
+  // descriptors: descs[i] maps buffer 0 -> sg[i], buffer 1 -> sg[i+1]
+  {
+    std::vector<MemberDev> md(seg);
+    const MemberDev base = member_dev(h, 0);
+    for (int i = 0; i < seg; ++i) {
+      md[i] = base;
+      md[i].psi[0] = sg + fb * i;
+      md[i].psi[1] = sg + fb * (i + 1);
+    }
+    HIP_TRY(hipMemcpyAsync(descs, md.data(), sizeof(MemberDev) * seg, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  // recompute uses a private state slot so the handle's state is untouched
+  MemberState* rst = cks + nck;
+  for (int j = nck - 1; j >= 0; --j) {
+    const int len = std::min(k, T - j * k);
+    HIP_TRY(hipMemcpyAsync(sg, ck + fb * j, es * (size_t)m.n3, hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(rst, cks + j, sizeof(MemberState), hipMemcpyDeviceToDevice, h->stream));
+    for (int i = 0; i < len; ++i) {
+      StepArgs a = base_args(h);
+      a.members = descs + i;
+      a.states = rst;
+      a.src = 0;
+      a.renorm_every = 1;
+      a.ring = scratch;  // recompute records are not kept
+      a.ring_cap = 1;
+      HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, true, launch_grid(h, a.n_items), a, h->stream));
+    }
+    for (int i = len - 1; i >= 0; --i) {
+      AdjArgs a;
+      memset(&a, 0, sizeof a);
+      a.V = h->V(0);
+      a.lam_in = lam[lc];
+      a.lam_out = lam[lc ^ 1];
+      a.psi_t = sg + fb * i;
+      a.psi_t1 = sg + fb * (i + 1);
+      a.G = G;
+      a.N = m.N;
+      a.c = m.c;
+      a.dt = m.dt;
+      a.s_t = scales[(size_t)j * k + i];
+      HIP_TRY(launch_adjoint_step(h->dtype, a, h->stream));
+      lc ^= 1;
+    }
+  }
+  if (dE_dV) HIP_TRY(hipMemcpyAsync(dE_dV, G, sizeof(double) * (size_t)m.n3, hipMemcpyDeviceToDevice, h->stream));
+  if (nwrt > 0) {
+    double* p_dev = scratch + 1024;
+    int* wrt_dev = reinterpret_cast<int*>(scratch + 1024 + kMaxParams + 8);
+    double* part = scratch + 8192;
+    double* out_dev = scratch + 512;
+    HIP_TRY(hipMemcpyAsync(p_dev, theta, sizeof(double) * ntheta, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(wrt_dev, wrt, sizeof(int) * nwrt, hipMemcpyHostToDevice, h->stream));
+    const int nb = 512;
+    HIP_TRY(launch_wells_contract(G, m.N, m.ha, p_dev, ntheta, wrt_dev, nwrt, part, nb, out_dev, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->h_pin, out_dev, sizeof(double) * nwrt, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < nwrt; ++i) dE_dtheta[i] = h->h_pin[i];
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (energy) *energy = E;
+  return FDTD_OK;
+}

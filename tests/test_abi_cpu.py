@@ -1,0 +1,137 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/fdtd.h declares, and its host-side validation returns the
+documented status codes."""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_0904_0939_amd import fdtd as F
+
+
+def cfg(N=16, L=8.0, dt_over=0.125, mass=1.0, dtype=F.F32, history=0):
+    a = L / N
+    return F.fdtd_config(N, dtype, L, mass, dt_over * mass * a * a, 0.0, 0, history, None)
+
+
+def status_of(fn, *args):
+    return getattr(F.lib(), fn)(*args)
+
+
+def test_library_exports_every_header_function():
+    lib = F.lib()
+    names = F.header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_library_is_built_for_gfx950_only():
+    blob = open(F.LIB_PATH, "rb").read()
+    assert b"gfx950" in blob
+
+
+def test_potential_kind_numbering_matches_the_oracle():
+    import oracle
+    from paper_0904_0939_amd import workloads as W
+
+    for name in ("POT_CONST", "POT_HO", "POT_COULOMB", "POT_COULOMB_REG", "POT_CORNELL",
+                 "POT_WELLS"):
+        assert getattr(F, name) == getattr(oracle, name) == getattr(W, name)
+    hdr = open(F.HEADER).read()
+    for i, name in enumerate(["CONST", "HO", "COULOMB", "COULOMB_REG", "CORNELL", "WELLS"]):
+        assert f"FDTD_POT_{name} = {i}" in hdr
+
+
+def test_create_rejects_unstable_time_step():
+    h = C.c_void_p()
+    c = cfg(dt_over=1.0 / 3.0 * 1.0000001)
+    assert status_of("fdtd_create", C.byref(c), C.byref(h)) == F.EUNSTABLE
+    assert "stability" in F.fdtd_last_error()
+    c = cfg(dt_over=0.33, mass=2.0)
+    assert status_of("fdtd_create", C.byref(c), C.byref(h)) == F.OK
+    F.fdtd_destroy(h.value)
+
+
+@pytest.mark.parametrize("field,value", [("n", 1), ("box_len", -1.0), ("mass", 0.0),
+                                         ("dt", float("nan")), ("psi_dtype", 7),
+                                         ("history", -2)])
+def test_create_rejects_bad_config(field, value):
+    c = cfg()
+    setattr(c, field, value)
+    h = C.c_void_p()
+    assert status_of("fdtd_create", C.byref(c), C.byref(h)) == F.EINVAL
+    assert h.value is None
+
+
+def test_batch_requires_one_dtype():
+    arr = (F.fdtd_config * 2)(cfg(dtype=F.F32), cfg(dtype=F.F64))
+    h = C.c_void_p()
+    assert status_of("fdtd_create_batch", arr, 2, C.byref(h)) == F.EINVAL
+    assert status_of("fdtd_create_batch", arr, 0, C.byref(h)) == F.EINVAL
+
+
+def test_call_order_and_workspace_checks_without_device():
+    h = F.fdtd_create(cfg())
+    try:
+        opts = F.fdtd_evolve_opts(10, 1, 0, 0, 0, 0.0)
+        assert status_of("fdtd_evolve", h, C.byref(opts), None, None) == F.ENOTREADY
+        obs = F.fdtd_obs()
+        assert status_of("fdtd_observables", h, C.byref(obs)) == F.ENOTREADY
+        need = F.fdtd_workspace_size(h)
+        assert need > 2 * 16**3 * 4 + 16**3 * 4
+        assert status_of("fdtd_bind_workspace", h, C.c_void_p(4096), need - 1) == F.ENOMEM
+        assert status_of("fdtd_bind_workspace", h, None, need) == F.EINVAL
+        bad = F.fdtd_evolve_opts(-1, 1, 0, 0, 0, 0.0)
+        assert status_of("fdtd_evolve", h, C.byref(bad), None, None) == F.EINVAL
+        assert status_of("fdtd_set_initial", h, 0, 9, 0, 0, None, 0, 0) == F.EINVAL
+        assert status_of("fdtd_set_initial", h, 0, 0, 0, 3 << 4, None, 0, 0) == F.EINVAL
+        assert status_of("fdtd_set_initial", h, 5, 0, 0, 0, None, 0, 0) == F.EINVAL
+        assert status_of("fdtd_set_potential_analytic", h, 0, 99, None, 0) == F.EINVAL
+        p = (C.c_double * 4)(1, 1, 1, 1)
+        assert status_of("fdtd_set_potential_analytic", h, 0, F.POT_WELLS, p, 4) == F.EINVAL
+        assert status_of("fdtd_energy_grad", h, 0, 1, None, 0, None, 0, None, None, None) == F.EINVAL
+    finally:
+        F.fdtd_destroy(h)
+
+
+def test_tuning_validation_is_host_side():
+    h = F.fdtd_create(cfg(N=18))  # 18 % 4 != 0
+    try:
+        t = F.fdtd_get_tuning(h)
+        assert t.vz == 1  # default falls back to scalar lanes
+        for bad in [F.fdtd_tuning(4, 1, 8, 0, 1), F.fdtd_tuning(1, 3, 8, 0, 1),
+                    F.fdtd_tuning(1, 1, 0, 0, 1), F.fdtd_tuning(1, 1, 8, -1, 1),
+                    F.fdtd_tuning(2, 1, 8, 0, 1)]:
+            assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
+        F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0))
+        assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
+                                                  "xcd_remap": 0}
+    finally:
+        F.fdtd_destroy(h)
+
+
+def test_status_strings_and_null_handles():
+    for s in range(7):
+        assert F.fdtd_status_string(s).startswith("FDTD_")
+    assert status_of("fdtd_destroy", None) == F.OK
+    assert status_of("fdtd_synchronize", None) == F.EINVAL
+    assert status_of("fdtd_create", None, None) == F.EINVAL
+
+
+def test_default_vector_width_follows_dtype():
+    for dt, vz in ((F.F64, 2), (F.F32, 4), (F.BF16, 8)):
+        h = F.fdtd_create(cfg(N=32, dtype=dt))
+        assert F.fdtd_get_tuning(h).vz == vz
+        F.fdtd_destroy(h)
+
+
+def test_product_path_has_no_oracle_dependency():
+    """The package never imports, links or runs the CPU oracle."""
+    root = os.path.dirname(F.__file__)
+    for dirpath, _, files in os.walk(root):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "liboracle" not in text and "fdtd_oracle" not in text, fn
