@@ -75,7 +75,7 @@ enum { FDTD_INIT_UNIFORM = 0, FDTD_INIT_GAUSS = 1, FDTD_INIT_USER = 2 };
 #define FDTD_PARITY(px, py, pz) ((uint32_t)(((px) & 3) | (((py) & 3) << 2) | (((pz) & 3) << 4)))
 
 typedef struct {
-  int32_t n;          /* lattice side N >= 2 (N^3 sites)                       */
+  int32_t n;          /* lattice side, 2 <= N <= 8192 (N^3 sites)              */
   int32_t psi_dtype;  /* fdtd_dtype of the stored wavefunction                 */
   double box_len;     /* L = N a > 0                                           */
   double mass;        /* m > 0                                                 */
@@ -120,8 +120,9 @@ typedef struct {
 /* Launch shape of the fused step kernel (see fdtd_autotune).
  *  vz     sites per lane along z, 1 or the dtype's vector width (F64 2,
  *         F32 4, BF16 8; requires N % vz == 0);
- *  ry     vectors per lane per plane (1, 2 or 4);
- *  xchunk planes streamed per work item (>= 1);
+ *  ry     vectors per lane per plane (1, 2 or 4); vz * ry <= 16 (<= 8 for BF16);
+ *  xchunk planes streamed per work item (>= 1; 0: the longest stream that
+ *         still gives every CU a work item);
  *  grid   work-groups launched (0: one per work item);
  *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles. */
 typedef struct {

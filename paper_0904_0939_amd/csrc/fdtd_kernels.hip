@@ -146,12 +146,243 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
 
 __device__ __forceinline__ bool finite_d(double x) { return !(isnan(x) || isinf(x)); }
 
+// ------------------------------------------------------- buffer access ----
+// Raw buffer loads return 0 and raw buffer stores are dropped for offsets at
+// or beyond the resource's size.  Each x-plane gets its own resource, sized
+// to the plane (or to 0 for the ghost planes x = -1 and x = N), so the
+// Dirichlet ghosts around the lattice, the y = -1 / y = N rows and the
+// ragged tail of a work item cost no branches and no HBM traffic.
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer descriptor
+constexpr unsigned kDeadLane = 1u << 28;  // element offset used by lanes past the plane
+
+// Resource for plane x of a field whose planes are `bytes` long; planes
+// outside [0, N) get an empty resource (every access reads 0 / is dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int x, int N,
+                                                            unsigned bytes) {
+  const bool in = x >= 0 && x < N;
+  char* p = const_cast<char*>(static_cast<const char*>(base)) + (in ? (long long)x * bytes : 0);
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, in ? (int)bytes : 0, kRsrcWord3);
+}
+
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Cache policy bits of buffer accesses: kNT streams past the caches (data
+// used once: V, and the written state); kKeep leaves the default policy
+// (psi, whose lines are re-read as neighbours by adjacent lanes).
+constexpr int kKeep = 0;
+constexpr int kNT = 2;
+
+// Load VZ consecutive elements of S at byte offset `off`, converted to C.
+template <typename S, int VZ, typename C, int AUX = kKeep>
+__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, C (&o)[VZ]) {
+  constexpr int kBytes = (int)sizeof(S) * VZ;
+  if constexpr (kBytes == 16) {
+    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
+    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
+  } else if constexpr (kBytes == 32) {
+    const u32x4 w0 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
+    const u32x4 w1 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off + 16, 0, AUX);
+    const Pack<S, VZ / 2> t0 = __builtin_bit_cast(Pack<S, VZ / 2>, w0);
+    const Pack<S, VZ / 2> t1 = __builtin_bit_cast(Pack<S, VZ / 2>, w1);
+#pragma unroll
+    for (int j = 0; j < VZ / 2; ++j) {
+      o[j] = to_c<S, C>(t0.v[j]);
+      o[j + VZ / 2] = to_c<S, C>(t1.v[j]);
+    }
+  } else if constexpr (kBytes == 8) {
+    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX);
+    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
+  } else if constexpr (kBytes == 4) {
+    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX);
+    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
+  } else {
+    static_assert(kBytes == 2, "unsupported vector width");
+    const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, AUX);
+    o[0] = to_c<S, C>(__builtin_bit_cast(S, w));
+  }
+}
+
+template <typename S, int VZ, int AUX = kKeep>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, const Pack<S, VZ>& t) {
+  constexpr int kBytes = (int)sizeof(S) * VZ;
+  if constexpr (kBytes == 16) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, (int)off, 0, AUX);
+  } else if constexpr (kBytes == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, t), r, (int)off, 0, AUX);
+  } else if constexpr (kBytes == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), r, (int)off, 0, AUX);
+  } else {
+    static_assert(kBytes == 2, "unsupported vector width");
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), r, (int)off, 0, AUX);
+  }
+}
+
+// Stochastic rounding to BF16 (used for the stored state of BF16 lattices):
+// add 16 random bits to the magnitude and truncate.  The result is unbiased,
+// E[round(v)] = v, so increments far below one BF16 ulp still move the state
+// on average instead of being rounded away.  Acts on the magnitude only, so
+// mirror sites given the same random bits round to exactly opposite values.
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t rnd) {
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t mag = u & 0x7fffffffu;
+  if (mag >= 0x7f800000u) return f32_to_bf16(f);  // Inf / NaN
+  return (uint16_t)(((u & 0x80000000u) | (mag + (rnd & 0xffffu))) >> 16);
+}
+
+// 32-bit integer hash (lowbias32, C. Wellons): random bits of the rounding.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 // ------------------------------------------------------- fused step kernel --
+// Per-lane state of one work item: RY vectors of VZ sites at fixed (y, z).
+template <int RY, int VZ, typename C>
+struct Lane {
+  unsigned off[RY];       // byte offset of the vector in a plane (storage dtype)
+  unsigned voff[RY];      // byte offset of the vector in a plane of V
+  unsigned offm[RY];      // y - 1 neighbour vector (may wrap: then out of range)
+  unsigned offp[RY];      // y + 1 neighbour vector (out of range past the plane)
+  float zmask_lo[RY];     // 0 where the vector starts at z = 0 (its z - 1 is a ghost)
+  float zmask_hi[RY];     // 0 where the vector ends at z = N - 1
+  C w2[RY][VZ];           // y^2 + z^2 of each site
+  uint32_t key[RY][VZ];   // mirror-canonical (y, z) index for the rounding hash
+};
+
+// Data of one plane that the update of that plane needs besides the planes
+// x-1, x, x+1 of the lane's own sites: V and the y / z neighbours.
+template <int RY, int VZ, typename C>
+struct PlaneIn {
+  C v[RY][VZ], ym[RY][VZ], yp[RY][VZ], zm[RY], zp[RY];
+};
+
 template <int DT, int VZ, int RY, bool UPD>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+struct StepBody {
   using S = typename Types<DT>::S;
   using TV = typename Types<DT>::V;
   using C = typename Types<DT>::C;
+  static constexpr unsigned kES = sizeof(S);
+
+  struct Ctx {
+    const void* in;
+    void* out;
+    const TV* Vf;
+    unsigned pbytes, vbytes;
+    int N;
+    C c, dt, eps, sc;
+    double ha, cN;
+    uint32_t smix, kN;
+  };
+
+  // Issue the loads plane x needs (V, y and z neighbours).
+  static __device__ __forceinline__ void fetch(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+                                               PlaneIn<RY, VZ, C>& d) {
+    const __amdgpu_buffer_rsrc_t rc = plane_rsrc(k.in, x, k.N, k.pbytes);
+    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, k.N, k.vbytes);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      C zz[1];
+      bload<TV, VZ, C, kNT>(rv, ln.voff[r], d.v[r]);
+      bload<S, VZ, C>(rc, ln.offm[r], d.ym[r]);
+      bload<S, VZ, C>(rc, ln.offp[r], d.yp[r]);
+      bload<S, 1, C>(rc, ln.off[r] - kES, zz);
+      d.zm[r] = zz[0];
+      bload<S, 1, C>(rc, ln.off[r] + VZ * kES, zz);
+      d.zp[r] = zz[0];
+    }
+  }
+
+  static __device__ __forceinline__ void fetch_own(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+                                                   C (&q)[RY][VZ]) {
+    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(k.in, x, k.N, k.pbytes);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) bload<S, VZ, C>(r0, ln.off[r], q[r]);
+  }
+
+  // Update plane x from pm (x-1), pc (x), pn (x+1) and d; accumulate the
+  // reductions of plane x into acc.
+  static __device__ __forceinline__ void update(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+                                                const C (&pm)[RY][VZ], const C (&pc)[RY][VZ],
+                                                const C (&pn)[RY][VZ],
+                                                const PlaneIn<RY, VZ, C>& d, double (&acc)[5]) {
+    const double xc = (2.0 * x - k.cN) * k.ha;
+    const C rx2 = (C)(xc * xc);
+    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(k.out, x, k.N, k.pbytes);
+    const uint32_t kx = (uint32_t)min(x, k.N - 1 - x) * k.kN;
+    C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      Pack<S, VZ> o;
+      const C lo = d.zm[r] * (C)ln.zmask_lo[r];
+      const C hi = d.zp[r] * (C)ln.zmask_hi[r];
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        const C p = pc[r][j];
+        C lft = lo, rgt = hi;
+        if (j > 0) lft = pc[r][j - 1];
+        if (j < VZ - 1) rgt = pc[r][j + 1];
+        // a^2 * Laplacian from neighbour differences, mirror-symmetric pairs
+        const C lap = (((pm[r][j] - p) + (pn[r][j] - p)) + ((d.ym[r][j] - p) + (d.yp[r][j] - p))) +
+                      ((lft - p) + (rgt - p));
+        const C p2 = p * p;
+        s0 += p2;
+        kin += p * lap;
+        pot += d.v[r][j] * p2;
+        r2 += ln.w2[r][j] * p2;
+        if constexpr (UPD) {
+          const C B = rcp_c(C(1) + k.eps * d.v[r][j]);
+          const C nv = k.sc * (p + B * (k.c * lap - k.dt * d.v[r][j] * p));
+          if constexpr (sizeof(S) == 2) {
+            o.v[j] = f32_to_bf16_sr((float)nv, hash32(kx + ln.key[r][j] + k.smix));
+          } else {
+            o.v[j] = (S)nv;
+          }
+          const C od = to_c<S, C>(o.v[j]);
+          s1 += od * od;
+        }
+      }
+      if constexpr (UPD) bstore<S, VZ, kNT>(ro, ln.off[r], o);
+    }
+    acc[0] += (double)s0;
+    acc[1] += (double)kin;
+    acc[2] += (double)pot;
+    acc[3] += (double)r2 + (double)rx2 * (double)s0;
+    acc[4] += (double)s1;
+  }
+
+  // One pipelined stage: issue the loads of plane x + 1 (and of the own
+  // sites of plane x + 2), then update plane x from data fetched one stage
+  // earlier, so the memory latency of the next plane overlaps this plane's
+  // arithmetic.
+  static __device__ __forceinline__ void stage(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+                                               const C (&qm)[RY][VZ], const C (&qc)[RY][VZ],
+                                               const C (&qn)[RY][VZ], C (&qf)[RY][VZ],
+                                               const PlaneIn<RY, VZ, C>& dc,
+                                               PlaneIn<RY, VZ, C>& dn, double (&acc)[5]) {
+    fetch_own(k, ln, x + 2, qf);
+    fetch(k, ln, x + 1, dn);
+    update(k, ln, x, qm, qc, qn, dc, acc);
+  }
+};
+
+template <int DT, int VZ, int RY, bool UPD>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+  using Body = StepBody<DT, VZ, RY, UPD>;
+  using S = typename Body::S;
+  using TV = typename Body::TV;
+  using C = typename Body::C;
+  constexpr unsigned kES = sizeof(S);
   __shared__ double s_red[kBlock / 64][5];
   __shared__ int s_last;
   const int tid = threadIdx.x;
@@ -162,105 +393,82 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     const int m = item.member;
     const MemberDev& M = A.members[m];
     const int N = M.N;
-    const long long P = M.plane;
-    const S* __restrict__ in = static_cast<const S*>(M.psi[A.src]);
-    S* __restrict__ out = static_cast<S*>(M.psi[A.src ^ 1]);
-    const TV* __restrict__ Vp = static_cast<const TV*>(M.V);
+    const unsigned P = (unsigned)M.plane;
+    const void* in = M.psi[A.src];
+    void* out = M.psi[A.src ^ 1];
+    const TV* Vf = static_cast<const TV*>(M.V);
+    const unsigned pbytes = P * kES, vbytes = P * (unsigned)sizeof(TV);
     const C c = (C)M.c;
     const C dt = (C)M.dt;
     const C eps = (C)(0.5 * M.dt);
     const C sc = (C)A.states[m].scale;
+    const uint32_t smix = (uint32_t)A.states[m].step * 0x9E3779B9u;
     const double ha = M.ha;
     const double cN = (double)(N - 1);
 
-    long long f[RY];
-    bool ok[RY], ym_ok[RY], yp_ok[RY], zm_ok[RY], zp_ok[RY];
-    int z0[RY];
-    double ry2[RY];
+    Lane<RY, VZ, C> ln;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      f[r] = (long long)item.f0 + (long long)(r * kBlock + tid) * VZ;
-      ok[r] = f[r] < P;
-      const int y = ok[r] ? (int)(f[r] / N) : 0;
-      z0[r] = ok[r] ? (int)(f[r] - (long long)y * N) : 0;
-      ym_ok[r] = ok[r] && y > 0;
-      yp_ok[r] = ok[r] && y < N - 1;
-      zm_ok[r] = ok[r] && z0[r] > 0;
-      zp_ok[r] = ok[r] && z0[r] + VZ < N;
+      const unsigned f = (unsigned)item.f0 + (unsigned)(r * kBlock + tid) * VZ;
+      const bool ok = f < P;
+      const unsigned fe = ok ? f : kDeadLane;
+      const int y = ok ? (int)(f / (unsigned)N) : 0;
+      const int z0 = ok ? (int)(f - (unsigned)y * N) : 0;
+      ln.off[r] = fe * kES;
+      ln.voff[r] = fe * (unsigned)sizeof(TV);
+      ln.offm[r] = (fe - (unsigned)N) * kES;  // wraps below row 0: out of range
+      ln.offp[r] = (fe + (unsigned)N) * kES;
+      ln.zmask_lo[r] = (ok && z0 > 0) ? 1.f : 0.f;
+      ln.zmask_hi[r] = (ok && z0 + VZ < N) ? 1.f : 0.f;
       const double yc = (2.0 * y - cN) * ha;
-      ry2[r] = yc * yc;
+      const int cy = min(y, N - 1 - y);
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        const double zc = (2.0 * (z0 + j) - cN) * ha;
+        ln.w2[r][j] = (C)(yc * yc + zc * zc);
+        const int z = z0 + j;
+        ln.key[r][j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
+      }
     }
+    const uint32_t kN = (uint32_t)N * (uint32_t)N;
+
+    typename Body::Ctx k;
+    k.in = in;
+    k.out = out;
+    k.Vf = Vf;
+    k.pbytes = pbytes;
+    k.vbytes = vbytes;
+    k.N = N;
+    k.c = c;
+    k.dt = dt;
+    k.eps = eps;
+    k.sc = sc;
+    k.ha = ha;
+    k.cN = cN;
+    k.smix = smix;
+    k.kN = kN;
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    C prev[RY][VZ], cur[RY][VZ], nxt[RY][VZ];
+    // four own-site planes and two neighbour sets in flight, renamed by
+    // unrolling instead of copied
+    C q0[RY][VZ], q1[RY][VZ], q2[RY][VZ], q3[RY][VZ];
+    PlaneIn<RY, VZ, C> d0, d1;
     const int xb = item.xb, xe = item.xe;
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      if (ok[r] && xb > 0) load_vec<S, VZ, C>(in + (long long)(xb - 1) * P + f[r], prev[r]);
-      else zero_vec<C, VZ>(prev[r]);
-      if (ok[r]) load_vec<S, VZ, C>(in + (long long)xb * P + f[r], cur[r]);
-      else zero_vec<C, VZ>(cur[r]);
+    Body::fetch_own(k, ln, xb - 1, q0);
+    Body::fetch_own(k, ln, xb, q1);
+    Body::fetch_own(k, ln, xb + 1, q2);
+    Body::fetch(k, ln, xb, d0);
+    int x = xb;
+    for (; x + 4 <= xe; x += 4) {
+      Body::stage(k, ln, x, q0, q1, q2, q3, d0, d1, acc);
+      Body::stage(k, ln, x + 1, q1, q2, q3, q0, d1, d0, acc);
+      Body::stage(k, ln, x + 2, q2, q3, q0, q1, d0, d1, acc);
+      Body::stage(k, ln, x + 3, q3, q0, q1, q2, d1, d0, acc);
     }
-
-    for (int x = xb; x < xe; ++x) {
-      const long long base = (long long)x * P;
-      const double xc = (2.0 * x - cN) * ha;
-      const double rx2 = xc * xc;
-      const bool has_next = x + 1 < N;
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        if (ok[r] && has_next) load_vec<S, VZ, C>(in + base + P + f[r], nxt[r]);
-        else zero_vec<C, VZ>(nxt[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        if (!ok[r]) continue;
-        const long long g = base + f[r];
-        C v[VZ], ym[VZ], yp[VZ];
-        load_vec<TV, VZ, C>(Vp + g, v);
-        if (ym_ok[r]) load_vec<S, VZ, C>(in + g - N, ym);
-        else zero_vec<C, VZ>(ym);
-        if (yp_ok[r]) load_vec<S, VZ, C>(in + g + N, yp);
-        else zero_vec<C, VZ>(yp);
-        const C zm = zm_ok[r] ? to_c<S, C>(in[g - 1]) : C(0);
-        const C zp = zp_ok[r] ? to_c<S, C>(in[g + VZ]) : C(0);
-        const double rxy2 = rx2 + ry2[r];
-        Pack<S, VZ> o;
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-          const C p = cur[r][j];
-          C lft = zm, rgt = zp;
-          if (j > 0) lft = cur[r][j - 1];
-          if (j < VZ - 1) rgt = cur[r][j + 1];
-          // a^2 * Laplacian from neighbour differences, mirror-symmetric pairs
-          const C lap = (((prev[r][j] - p) + (nxt[r][j] - p)) + ((ym[j] - p) + (yp[j] - p))) +
-                        ((lft - p) + (rgt - p));
-          const double pd = (double)p;
-          const double p2 = pd * pd;
-          acc[0] += p2;
-          acc[1] += pd * (double)lap;
-          acc[2] += (double)v[j] * p2;
-          const double zc = (2.0 * (z0[r] + j) - cN) * ha;
-          acc[3] += (rxy2 + zc * zc) * p2;
-          if constexpr (UPD) {
-            const C B = rcp_c(C(1) + eps * v[j]);
-            const C nv = sc * (p + B * (c * lap - dt * v[j] * p));
-            o.v[j] = from_c<S, C>(nv);
-            const double od = (double)to_c<S, C>(o.v[j]);
-            acc[4] += od * od;
-          }
-        }
-        if constexpr (UPD) store_vec<S, VZ>(out + g, o);
-      }
-#pragma unroll
-      for (int r = 0; r < RY; ++r) {
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-          prev[r][j] = cur[r][j];
-          cur[r][j] = nxt[r][j];
-        }
-      }
-    }
+    const int rem = xe - x;
+    if (rem > 0) Body::stage(k, ln, x, q0, q1, q2, q3, d0, d1, acc);
+    if (rem > 1) Body::stage(k, ln, x + 1, q1, q2, q3, q0, d1, d0, acc);
+    if (rem > 2) Body::stage(k, ln, x + 2, q2, q3, q0, q1, d0, d1, acc);
 
     // ---- per-item partials, then the last work-group of the member sums them
     block_sum<5>(acc, s_red);
@@ -653,15 +861,26 @@ int grid_for(long long n) {
   return (int)g;
 }
 
+// Launch shapes with more sites per lane than the register file holds
+// without spilling are not instantiated (see max_sites_per_lane).
+template <int DT, int VZ, int RY, bool UPD>
+hipError_t step_one(int grid, const StepArgs& a, hipStream_t s) {
+  if constexpr (VZ * RY <= (DT == kBF16 ? 8 : 16)) {
+    hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD>), dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int DT, int VZ, bool UPD>
 hipError_t step_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_step<DT, VZ, 2, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_step<DT, VZ, 4, UPD>), dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 1: return step_one<DT, VZ, 1, UPD>(grid, a, s);
+    case 2: return step_one<DT, VZ, 2, UPD>(grid, a, s);
+    case 4: return step_one<DT, VZ, 4, UPD>(grid, a, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 template <int DT, bool UPD>

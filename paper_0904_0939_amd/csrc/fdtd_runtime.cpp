@@ -141,7 +141,7 @@ void compute_layout(fdtd_ctx* h) {
 }
 
 fdtd_status validate_cfg(const fdtd_config& c, const char* who) {
-  if (c.n < 2 || c.n > 46340) return fail(FDTD_EINVAL, std::string(who) + ": n must be in [2, 46340]");
+  if (c.n < 2 || c.n > 8192) return fail(FDTD_EINVAL, std::string(who) + ": n must be in [2, 8192]");
   if (!(c.box_len > 0) || !std::isfinite(c.box_len)) return fail(FDTD_EINVAL, std::string(who) + ": box_len must be > 0");
   if (!(c.mass > 0) || !std::isfinite(c.mass)) return fail(FDTD_EINVAL, std::string(who) + ": mass must be > 0");
   if (!(c.dt > 0) || !std::isfinite(c.dt)) return fail(FDTD_EINVAL, std::string(who) + ": dt must be > 0");
@@ -195,8 +195,8 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   bool all_div = true;
   for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
   h->tun.vz = all_div ? vw : 1;
-  h->tun.ry = 2;
-  h->tun.xchunk = 32;
+  h->tun.ry = (h->dtype == kBF16 && h->tun.vz == 8) ? 1 : (h->dtype == kF64 ? 4 : 2);
+  h->tun.xchunk = 0;  // automatic: see auto_xchunk
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;
   *out = h;
@@ -270,9 +270,27 @@ void xcd_permute(std::vector<int>& pos, int n) {
   for (int b = 0; b < n; ++b) pos[b] = (b < 8 * q) ? (b % 8) * q + b / 8 : b;
 }
 
+// Longest x-stream (fewest re-read halo planes, least per-item start-up)
+// that still gives each of the 256 CUs a work item (measured at 512^3: one
+// long-streaming work-group per CU beats more, shorter ones).
+int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
+  for (int xc : {256, 128, 64, 32, 16}) {
+    long long items = 0;
+    for (const auto& m : h->mem) {
+      const long long P = (long long)m.N * m.N;
+      const long long F = (long long)kBlock * t.vz * t.ry;
+      const int x = std::min(xc, m.N);
+      items += ((P + F - 1) / F) * ((m.N + x - 1) / x);
+    }
+    if (items >= 256) return xc;
+  }
+  return 8;
+}
+
 fdtd_status build_items(fdtd_ctx* h) {
   if (h->items_valid) return FDTD_OK;
-  const fdtd_tuning& t = h->tun;
+  fdtd_tuning t = h->tun;
+  if (t.xchunk == 0) t.xchunk = auto_xchunk(h, t);
   std::vector<Item> phys;
   for (int i = 0; i < h->count; ++i) {
     MemberHost& m = h->mem[i];
@@ -524,7 +542,9 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   for (auto& m : h->mem)
     if (m.N % t.vz != 0) return fail(FDTD_EINVAL, "tuning: vz must divide every N");
   if (t.ry != 1 && t.ry != 2 && t.ry != 4) return fail(FDTD_EINVAL, "tuning: ry must be 1, 2 or 4");
-  if (t.xchunk < 1) return fail(FDTD_EINVAL, "tuning: xchunk must be >= 1");
+  if (t.vz * t.ry > (h->dtype == kBF16 ? 8 : 16))
+    return fail(FDTD_EINVAL, "tuning: vz * ry must be <= 16 (<= 8 for BF16)");
+  if (t.xchunk < 0) return fail(FDTD_EINVAL, "tuning: xchunk must be >= 0 (0: automatic)");
   if (t.grid < 0) return fail(FDTD_EINVAL, "tuning: grid must be >= 0");
   return FDTD_OK;
 }
@@ -920,9 +940,9 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   if (all_div) vzs.push_back(vw);
   for (int vz : vzs)
     for (int ry : {1, 2, 4})
-      for (int xc : {8, 16, 32, 64, 128})
+      for (int xc : {0, 32, 64, 128, 256})
         for (int remap : {0, 1}) {
-          if (xc > maxN && xc != 8) continue;
+          if (xc > maxN) continue;
           fdtd_tuning t{vz, ry, xc, 0, remap};
           if (validate_tuning(h, t) != FDTD_OK) continue;
           h->tun = t;

@@ -101,7 +101,7 @@ def test_tuning_validation_is_host_side():
         t = F.fdtd_get_tuning(h)
         assert t.vz == 1  # default falls back to scalar lanes
         for bad in [F.fdtd_tuning(4, 1, 8, 0, 1), F.fdtd_tuning(1, 3, 8, 0, 1),
-                    F.fdtd_tuning(1, 1, 0, 0, 1), F.fdtd_tuning(1, 1, 8, -1, 1),
+                    F.fdtd_tuning(1, 1, -1, 0, 1), F.fdtd_tuning(1, 1, 8, -1, 1),
                     F.fdtd_tuning(2, 1, 8, 0, 1)]:
             assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0))
@@ -117,6 +117,15 @@ def test_status_strings_and_null_handles():
     assert status_of("fdtd_destroy", None) == F.OK
     assert status_of("fdtd_synchronize", None) == F.EINVAL
     assert status_of("fdtd_create", None, None) == F.EINVAL
+
+
+def test_tuning_rejects_too_many_sites_per_lane():
+    h = F.fdtd_create(cfg(N=32, dtype=F.BF16))
+    try:
+        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(8, 2, 8, 0, 1))) == F.EINVAL
+        F.fdtd_set_tuning(h, F.fdtd_tuning(8, 1, 8, 0, 1))
+    finally:
+        F.fdtd_destroy(h)
 
 
 def test_default_vector_width_follows_dtype():
