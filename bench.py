@@ -65,6 +65,139 @@ def cpu_baseline(N, L, params, steps):
                       f"({dt:.1f} s; potential and noise set-up untimed)"}
 
 
+def _timer():
+    import torch
+
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000):
+    """Wall time to reach the ground-state energy to 1e-6 relative on the
+    Cornell lattice at 512^3 (L = 30, dt = a^2/8): the plain FP64 path from
+    noise on 512^3, against the multi-resolution chain (BF16 128^3 -> BF16
+    256^3 -> FP32 512^3, trilinear reseeding, graph-captured steps).  The
+    reference E* is the plain FP64 run carried on to a change below 1e-12 per
+    100 steps, then Aitken-extrapolated."""
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    Nf = N_levels[-1]
+    lat = W.cornell(Nf)
+    K = 100
+    # ---- plain FP64 from noise
+    s = Solver(Nf, lat.L, dtype="f64")
+    s.set_potential(F.POT_CORNELL, lat.pot_params)
+    t0 = _timer()
+    s.set_initial(lat.seed)
+    plain = []  # (seconds since start, steps, energy)
+    steps = 0
+    e_prev = None
+    while True:
+        s.evolve(K, check_every=0, use_graph=True)
+        steps += K
+        e = s.history(0, 1)[0]["energy"]
+        plain.append((time.perf_counter() - t0, steps, e))
+        if e_prev is not None and abs(e - e_prev) <= 1e-12 * abs(e):
+            break
+        if time.perf_counter() - t0 > max_plain_s:
+            break
+        e_prev = e
+    E = [p[2] for p in plain[-3:]]
+    den = E[2] - 2 * E[1] + E[0]
+    e_star = E[2] - (E[2] - E[1]) ** 2 / den if den != 0 else E[2]
+    s.close()
+
+    def first_within(rows, tol):
+        for t, n, e in rows:
+            if abs(e - e_star) <= tol * abs(e_star):
+                return t, n
+        return None, None
+
+    t_plain, n_plain = first_within(plain, 1e-6)
+    # ---- multi-resolution chain
+    dtypes = ["bf16"] * (len(N_levels) - 1) + ["f32"]
+    tols = [1e-5] * (len(N_levels) - 1)
+    t0 = _timer()
+    prev = None
+    multi = []
+    level_log = []
+    for i, N in enumerate(N_levels):
+        lv = W.cornell(N)
+        cur = Solver(N, lv.L, dtype=dtypes[i])
+        cur.set_potential(F.POT_CORNELL, lv.pot_params)
+        if prev is None:
+            cur.set_initial(lv.seed)
+        else:
+            F.fdtd_upsample(prev.h, 0, cur.h, 0)
+            prev.close()
+        n = 0
+        if i < len(N_levels) - 1:
+            done, conv = cur.evolve(coarse_max_steps, check_every=K, rel_tol=tols[i],
+                                    use_graph=True)
+            n = done
+        else:
+            e_prev = None
+            while True:
+                cur.evolve(K, check_every=0, use_graph=True)
+                n += K
+                e = cur.history(0, 1)[0]["energy"]
+                multi.append((time.perf_counter() - t0, n, e))
+                if abs(e - e_star) <= 1e-6 * abs(e_star) and len(multi) > 1:
+                    break
+                if time.perf_counter() - t0 > max_plain_s:
+                    break
+        level_log.append({"N": N, "dtype": dtypes[i], "steps": n,
+                          "energy": cur.history(0, 1)[0]["energy"],
+                          "seconds_since_start": round(time.perf_counter() - t0, 3)})
+        prev = cur
+    t_multi, n_multi = first_within(multi, 1e-6)
+    final_e = multi[-1][2] if multi else None
+    prev.close()
+    return {
+        "workload": f"cornell_L30_{'->'.join(str(n) for n in N_levels)}",
+        "e_star": e_star,
+        "plain_fp64_seconds": t_plain, "plain_fp64_steps": n_plain,
+        "plain_fp64_steps_to_1e-12": plain[-1][1],
+        "multires_seconds": t_multi, "multires_final_level_steps": n_multi,
+        "multires_levels": level_log,
+        "multires_final_energy": final_e,
+        "speedup": (t_plain / t_multi) if (t_plain and t_multi) else None,
+    }
+
+
+def batch64(steps=400, warmup=40, autotune=True):
+    """64 random oscillator-plus-wells potentials on lattices of side 48..160,
+    FP32, one launch per step over every member, graph-captured."""
+    import torch
+
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Batch
+
+    lats = W.wells_batch()
+    b = Batch(lats, dtype="f32")
+    for m, l in enumerate(lats):
+        b.set_potential(l.pot_kind, l.pot_params, member=m)
+    b.set_initial(lats[0].seed)
+    tun = b.autotune(10)[0] if autotune else b.tuning()
+    b.evolve(warmup, check_every=0, use_graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.evolve(steps, check_every=0, use_graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sites = sum(l.sites for l in lats)
+    obs = b.observables()
+    b.close()
+    return {"workload": "wells_batch64_f32", "members": len(lats), "sites": sites,
+            "ms_per_step": ms, "site_updates_per_s": sites / (ms * 1e-3),
+            "achieved_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": tun,
+            "energy_range": [min(o["energy"] for o in obs), max(o["energy"] for o in obs)]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +209,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tuning", default="", help="vz,ry,xchunk,grid,xcd_remap,depth")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the time-to-E and batch measurements")
+    ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the lattice "
@@ -88,11 +225,19 @@ def main():
     from paper_0904_0939_amd import workloads as W
     from paper_0904_0939_amd.solver import Solver
 
+    if args.only == "time_to_e":
+        print(json.dumps(time_to_e()), flush=True)
+        return
+    if args.only == "batch64":
+        print(json.dumps(batch64()), flush=True)
+        return
     lat = W.cornell(args.n)
     N, L = lat.N, lat.L
     s = Solver(N, L, dtype=args.dtype)
     s.set_potential(F.POT_CORNELL, lat.pot_params)
     s.set_initial(lat.seed)
+    if args.tuning:
+        s.set_tuning(*[int(v) for v in args.tuning.split(",")])
     if args.autotune:
         s.autotune(10)
     tun = s.tuning()
@@ -142,6 +287,10 @@ def main():
         "energy_after_timed_steps": ob["energy"],
         "wall_s_timed_region": wall,
     }
+    s.close()
+    if not args.no_extras:
+        out["time_to_e_1e-6"] = time_to_e()
+        out["batch64"] = batch64()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, L, lat.pot_params, args.cpu_steps)
     print(json.dumps(out), flush=True)

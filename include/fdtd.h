@@ -120,13 +120,15 @@ typedef struct {
 /* Launch shape of the fused step kernel (see fdtd_autotune).
  *  vz     sites per lane along z, 1 or the dtype's vector width (F64 2,
  *         F32 4, BF16 8; requires N % vz == 0);
- *  ry     vectors per lane per plane (1, 2 or 4); vz * ry <= 16 (<= 8 for BF16);
+ *  ry     vectors per lane per plane (1, 2 or 4); vz * ry <= 8 (<= 4 for F64);
  *  xchunk planes streamed per work item (>= 1; 0: the longest stream that
  *         still gives every CU a work item);
  *  grid   work-groups launched (0: one per work item);
- *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles. */
+ *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles;
+ *  depth  planes of HBM prefetch ahead of the plane being updated (1..3;
+ *         1 for vz = 1). */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/

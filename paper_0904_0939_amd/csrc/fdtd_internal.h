@@ -75,8 +75,9 @@ struct StepArgs {
 enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 
 // Launch the fused step (update = true) or the reduction-only pass.
-hipError_t launch_step(int dtype, int vz, int ry, bool update, int grid, const StepArgs& a,
-                       hipStream_t s);
+// depth: prefetch distance of the HBM streams, in planes (1..3).
+hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid,
+                       const StepArgs& a, hipStream_t s);
 
 // One thread per site, member m only.
 hipError_t launch_potential(int vdtype, void* V, int N, double ha, double a, int kind,

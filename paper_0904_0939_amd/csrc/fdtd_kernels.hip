@@ -264,7 +264,7 @@ struct Lane {
 // x-1, x, x+1 of the lane's own sites: V and the y / z neighbours.
 template <int RY, int VZ, typename C>
 struct PlaneIn {
-  C v[RY][VZ], ym[RY][VZ], yp[RY][VZ], zm[RY], zp[RY];
+  C ym[RY][VZ], yp[RY][VZ], zm[RY], zp[RY];
 };
 
 template <int DT, int VZ, int RY, bool UPD>
@@ -285,15 +285,13 @@ struct StepBody {
     uint32_t smix, kN;
   };
 
-  // Issue the loads plane x needs (V, y and z neighbours).
+  // Issue the loads of the y and z neighbours of plane x.
   static __device__ __forceinline__ void fetch(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                PlaneIn<RY, VZ, C>& d) {
     const __amdgpu_buffer_rsrc_t rc = plane_rsrc(k.in, x, k.N, k.pbytes);
-    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, k.N, k.vbytes);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       C zz[1];
-      bload<TV, VZ, C, kNT>(rv, ln.voff[r], d.v[r]);
       bload<S, VZ, C>(rc, ln.offm[r], d.ym[r]);
       bload<S, VZ, C>(rc, ln.offp[r], d.yp[r]);
       bload<S, 1, C>(rc, ln.off[r] - kES, zz);
@@ -301,6 +299,13 @@ struct StepBody {
       bload<S, 1, C>(rc, ln.off[r] + VZ * kES, zz);
       d.zp[r] = zz[0];
     }
+  }
+
+  static __device__ __forceinline__ void fetch_v(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+                                                 C (&v)[RY][VZ]) {
+    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, k.N, k.vbytes);
+#pragma unroll
+    for (int r = 0; r < RY; ++r) bload<TV, VZ, C, kNT>(rv, ln.voff[r], v[r]);
   }
 
   static __device__ __forceinline__ void fetch_own(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
@@ -314,7 +319,7 @@ struct StepBody {
   // reductions of plane x into acc.
   static __device__ __forceinline__ void update(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                 const C (&pm)[RY][VZ], const C (&pc)[RY][VZ],
-                                                const C (&pn)[RY][VZ],
+                                                const C (&pn)[RY][VZ], const C (&vv)[RY][VZ],
                                                 const PlaneIn<RY, VZ, C>& d, double (&acc)[5]) {
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
@@ -338,11 +343,11 @@ struct StepBody {
         const C p2 = p * p;
         s0 += p2;
         kin += p * lap;
-        pot += d.v[r][j] * p2;
+        pot += vv[r][j] * p2;
         r2 += ln.w2[r][j] * p2;
         if constexpr (UPD) {
-          const C B = rcp_c(C(1) + k.eps * d.v[r][j]);
-          const C nv = k.sc * (p + B * (k.c * lap - k.dt * d.v[r][j] * p));
+          const C B = rcp_c(C(1) + k.eps * vv[r][j]);
+          const C nv = k.sc * (p + B * (k.c * lap - k.dt * vv[r][j] * p));
           if constexpr (sizeof(S) == 2) {
             o.v[j] = f32_to_bf16_sr((float)nv, hash32(kx + ln.key[r][j] + k.smix));
           } else {
@@ -361,22 +366,26 @@ struct StepBody {
     acc[4] += (double)s1;
   }
 
-  // One pipelined stage: issue the loads of plane x + 1 (and of the own
-  // sites of plane x + 2), then update plane x from data fetched one stage
-  // earlier, so the memory latency of the next plane overlaps this plane's
-  // arithmetic.
-  static __device__ __forceinline__ void stage(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
-                                               const C (&qm)[RY][VZ], const C (&qc)[RY][VZ],
-                                               const C (&qn)[RY][VZ], C (&qf)[RY][VZ],
-                                               const PlaneIn<RY, VZ, C>& dc,
-                                               PlaneIn<RY, VZ, C>& dn, double (&acc)[5]) {
-    fetch_own(k, ln, x + 2, qf);
-    fetch(k, ln, x + 1, dn);
-    update(k, ln, x, qm, qc, qn, dc, acc);
+  // Update plane X = xb + 6 i + SL of a work item whose planes live in rings
+  // of six register slots: psi(p) in slot (p - xb + 1) % 6, V(p) and the
+  // neighbour set of p in slot (p - xb) % 6.  The stage first issues every
+  // load D planes ahead (psi(X + 1 + D), V(X + D), neighbours of X + D), then
+  // updates plane X from data fetched D stages earlier.  All streams use the
+  // same distance because the vector-memory counter retires loads in issue
+  // order: a nearer load issued after a farther one would make the wait for
+  // it wait for the farther one too.
+  template <int D, int SL>
+  static __device__ __forceinline__ void stage(const Ctx& k, const Lane<RY, VZ, C>& ln, int X,
+                                               C (&qs)[6][RY][VZ], C (&vs)[6][RY][VZ],
+                                               PlaneIn<RY, VZ, C> (&nb)[6], double (&acc)[5]) {
+    fetch_own(k, ln, X + 1 + D, qs[(SL + 2 + D) % 6]);
+    fetch_v(k, ln, X + D, vs[(SL + D) % 6]);
+    fetch(k, ln, X + D, nb[(SL + D) % 6]);
+    update(k, ln, X, qs[SL % 6], qs[(SL + 1) % 6], qs[(SL + 2) % 6], vs[SL % 6], nb[SL % 6], acc);
   }
 };
 
-template <int DT, int VZ, int RY, bool UPD>
+template <int DT, int VZ, int RY, bool UPD, int D>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   using Body = StepBody<DT, VZ, RY, UPD>;
   using S = typename Body::S;
@@ -449,26 +458,33 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     k.kN = kN;
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    // four own-site planes and two neighbour sets in flight, renamed by
-    // unrolling instead of copied
-    C q0[RY][VZ], q1[RY][VZ], q2[RY][VZ], q3[RY][VZ];
-    PlaneIn<RY, VZ, C> d0, d1;
+    C qs[6][RY][VZ], vs[6][RY][VZ];
+    PlaneIn<RY, VZ, C> nb[6];
     const int xb = item.xb, xe = item.xe;
-    Body::fetch_own(k, ln, xb - 1, q0);
-    Body::fetch_own(k, ln, xb, q1);
-    Body::fetch_own(k, ln, xb + 1, q2);
-    Body::fetch(k, ln, xb, d0);
-    int x = xb;
-    for (; x + 4 <= xe; x += 4) {
-      Body::stage(k, ln, x, q0, q1, q2, q3, d0, d1, acc);
-      Body::stage(k, ln, x + 1, q1, q2, q3, q0, d1, d0, acc);
-      Body::stage(k, ln, x + 2, q2, q3, q0, q1, d0, d1, acc);
-      Body::stage(k, ln, x + 3, q3, q0, q1, q2, d1, d0, acc);
+#pragma unroll
+    for (int i = 0; i < D + 2; ++i) Body::fetch_own(k, ln, xb - 1 + i, qs[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      Body::fetch_v(k, ln, xb + i, vs[i]);
+      Body::fetch(k, ln, xb + i, nb[i]);
     }
-    const int rem = xe - x;
-    if (rem > 0) Body::stage(k, ln, x, q0, q1, q2, q3, d0, d1, acc);
-    if (rem > 1) Body::stage(k, ln, x + 1, q1, q2, q3, q0, d1, d0, acc);
-    if (rem > 2) Body::stage(k, ln, x + 2, q2, q3, q0, q1, d0, d1, acc);
+    // six stages per trip, so the ring slots are compile-time constants;
+    // full trips carry no branches between stages (a join would make the
+    // load-counter waits conservative), the tail of < 6 planes is guarded
+    int x = xb;
+    for (; x + 6 <= xe; x += 6) {
+      Body::template stage<D, 0>(k, ln, x, qs, vs, nb, acc);
+      Body::template stage<D, 1>(k, ln, x + 1, qs, vs, nb, acc);
+      Body::template stage<D, 2>(k, ln, x + 2, qs, vs, nb, acc);
+      Body::template stage<D, 3>(k, ln, x + 3, qs, vs, nb, acc);
+      Body::template stage<D, 4>(k, ln, x + 4, qs, vs, nb, acc);
+      Body::template stage<D, 5>(k, ln, x + 5, qs, vs, nb, acc);
+    }
+    if (x < xe) Body::template stage<D, 0>(k, ln, x, qs, vs, nb, acc);
+    if (x + 1 < xe) Body::template stage<D, 1>(k, ln, x + 1, qs, vs, nb, acc);
+    if (x + 2 < xe) Body::template stage<D, 2>(k, ln, x + 2, qs, vs, nb, acc);
+    if (x + 3 < xe) Body::template stage<D, 3>(k, ln, x + 3, qs, vs, nb, acc);
+    if (x + 4 < xe) Body::template stage<D, 4>(k, ln, x + 4, qs, vs, nb, acc);
 
     // ---- per-item partials, then the last work-group of the member sums them
     block_sum<5>(acc, s_red);
@@ -861,49 +877,64 @@ int grid_for(long long n) {
   return (int)g;
 }
 
-// Launch shapes with more sites per lane than the register file holds
-// without spilling are not instantiated (see max_sites_per_lane).
-template <int DT, int VZ, int RY, bool UPD>
+// Launch shapes holding more than 32 bytes of arithmetic-type state per
+// lane and plane (8 FP32 or 4 FP64 sites) spill registers and are not
+// instantiated; the scalar-lane fallback (VZ = 1) and the reduction-only
+// pass use prefetch distance 1 only.
+template <int DT, int VZ, int RY, bool UPD, int D>
 hipError_t step_one(int grid, const StepArgs& a, hipStream_t s) {
-  if constexpr (VZ * RY <= (DT == kBF16 ? 8 : 16)) {
-    hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD>), dim3(grid), dim3(kBlock), 0, s, a);
+  if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || (UPD && VZ > 1))) {
+    hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
   }
 }
 
-template <int DT, int VZ, bool UPD>
+template <int DT, int VZ, bool UPD, int D>
 hipError_t step_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: return step_one<DT, VZ, 1, UPD>(grid, a, s);
-    case 2: return step_one<DT, VZ, 2, UPD>(grid, a, s);
-    case 4: return step_one<DT, VZ, 4, UPD>(grid, a, s);
+    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, a, s);
+    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, a, s);
+    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int VZ, bool UPD>
+hipError_t step_d(int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+  switch (depth) {
+    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, a, s);
+    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, a, s);
+    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, bool UPD>
-hipError_t step_vz(int vz, int ry, int grid, const StepArgs& a, hipStream_t s) {
-  if (vz == 1) return step_ry<DT, 1, UPD>(ry, grid, a, s);
-  if (vz == Types<DT>::kVec) return step_ry<DT, Types<DT>::kVec, UPD>(ry, grid, a, s);
+hipError_t step_vz(int vz, int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, a, s);
+  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, a, s);
   return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t step_dt(int vz, int ry, bool upd, int grid, const StepArgs& a, hipStream_t s) {
-  return upd ? step_vz<DT, true>(vz, ry, grid, a, s) : step_vz<DT, false>(vz, ry, grid, a, s);
+hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, const StepArgs& a,
+                   hipStream_t s) {
+  return upd ? step_vz<DT, true>(vz, depth, ry, grid, a, s)
+             : step_vz<DT, false>(vz, 1, ry, grid, a, s);
 }
 
 }  // namespace
 
-hipError_t launch_step(int dtype, int vz, int ry, bool update, int grid, const StepArgs& a,
-                       hipStream_t s) {
+hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid,
+                       const StepArgs& a, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
+  if (vz == 1) depth = 1;
   switch (dtype) {
-    case kF64: return step_dt<kF64>(vz, ry, update, grid, a, s);
-    case kF32: return step_dt<kF32>(vz, ry, update, grid, a, s);
-    case kBF16: return step_dt<kBF16>(vz, ry, update, grid, a, s);
+    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, a, s);
+    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, a, s);
+    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, a, s);
     default: return hipErrorInvalidValue;
   }
 }

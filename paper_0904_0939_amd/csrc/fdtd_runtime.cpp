@@ -195,10 +195,11 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   bool all_div = true;
   for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
   h->tun.vz = all_div ? vw : 1;
-  h->tun.ry = (h->dtype == kBF16 && h->tun.vz == 8) ? 1 : (h->dtype == kF64 ? 4 : 2);
+  h->tun.ry = (h->tun.vz == 1) ? 2 : (h->dtype == kF32 ? 2 : 1);
   h->tun.xchunk = 0;  // automatic: see auto_xchunk
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;
+  h->tun.depth = (h->dtype == kBF16 && h->tun.vz > 1) ? 2 : 1;
   *out = h;
   return FDTD_OK;
 }
@@ -274,7 +275,7 @@ void xcd_permute(std::vector<int>& pos, int n) {
 // that still gives each of the 256 CUs a work item (measured at 512^3: one
 // long-streaming work-group per CU beats more, shorter ones).
 int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
-  for (int xc : {256, 128, 64, 32, 16}) {
+  for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;
     for (const auto& m : h->mem) {
       const long long P = (long long)m.N * m.N;
@@ -381,7 +382,7 @@ fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
   }
-  HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, false, launch_grid(h, a.n_items), a, h->stream));
+  HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, 1, false, launch_grid(h, a.n_items), a, h->stream));
   return FDTD_OK;
 }
 
@@ -389,7 +390,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     StepArgs a = base_args(h);
     a.renorm_every = renorm_every;
-    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, true, launch_grid(h, a.n_items), a, s));
+    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, true, launch_grid(h, a.n_items), a, s));
     h->cur ^= 1;
   }
   return FDTD_OK;
@@ -397,7 +398,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
-         a.xcd_remap == b.xcd_remap;
+         a.xcd_remap == b.xcd_remap && a.depth == b.depth;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -542,10 +543,12 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   for (auto& m : h->mem)
     if (m.N % t.vz != 0) return fail(FDTD_EINVAL, "tuning: vz must divide every N");
   if (t.ry != 1 && t.ry != 2 && t.ry != 4) return fail(FDTD_EINVAL, "tuning: ry must be 1, 2 or 4");
-  if (t.vz * t.ry > (h->dtype == kBF16 ? 8 : 16))
-    return fail(FDTD_EINVAL, "tuning: vz * ry must be <= 16 (<= 8 for BF16)");
+  if (t.vz * t.ry > (h->dtype == kF64 ? 4 : 8))
+    return fail(FDTD_EINVAL, "tuning: vz * ry must be <= 8 (<= 4 for F64)");
   if (t.xchunk < 0) return fail(FDTD_EINVAL, "tuning: xchunk must be >= 0 (0: automatic)");
   if (t.grid < 0) return fail(FDTD_EINVAL, "tuning: grid must be >= 0");
+  if (t.depth < 1 || t.depth > 3) return fail(FDTD_EINVAL, "tuning: depth must be 1, 2 or 3");
+  if (t.vz == 1 && t.depth != 1) return fail(FDTD_EINVAL, "tuning: depth must be 1 when vz = 1");
   return FDTD_OK;
 }
 
@@ -774,7 +777,7 @@ fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
     // the reduction needs V only for the energy sums; it is harmless if unset
-    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, false, launch_grid(h, a.n_items), a, h->stream));
+    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, 1, false, launch_grid(h, a.n_items), a, h->stream));
   }
   HIP_TRY(hipMemcpyAsync(h->h_pin, h->d_obs() + (size_t)member * kRec, sizeof(double) * kRec,
                          hipMemcpyDeviceToHost, h->stream));
@@ -941,9 +944,11 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   for (int vz : vzs)
     for (int ry : {1, 2, 4})
       for (int xc : {0, 32, 64, 128, 256})
-        for (int remap : {0, 1}) {
-          if (xc > maxN) continue;
-          fdtd_tuning t{vz, ry, xc, 0, remap};
+        for (int depth : {1, 2, 3})
+          for (int grid : {0, 1024}) {
+          const int remap = 1;
+          if (xc > maxN || (vz == 1 && depth > 1)) continue;
+          fdtd_tuning t{vz, ry, xc, grid, remap, depth};
           if (validate_tuning(h, t) != FDTD_OK) continue;
           h->tun = t;
           h->items_valid = false;
@@ -1114,7 +1119,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
       a.renorm_every = 1;
       a.ring = scratch;  // recompute records are not kept
       a.ring_cap = 1;
-      HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, true, launch_grid(h, a.n_items), a, h->stream));
+      HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, true, launch_grid(h, a.n_items), a, h->stream));
     }
     for (int i = len - 1; i >= 0; --i) {
       AdjArgs a;

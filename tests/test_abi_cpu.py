@@ -100,13 +100,14 @@ def test_tuning_validation_is_host_side():
     try:
         t = F.fdtd_get_tuning(h)
         assert t.vz == 1  # default falls back to scalar lanes
-        for bad in [F.fdtd_tuning(4, 1, 8, 0, 1), F.fdtd_tuning(1, 3, 8, 0, 1),
-                    F.fdtd_tuning(1, 1, -1, 0, 1), F.fdtd_tuning(1, 1, 8, -1, 1),
-                    F.fdtd_tuning(2, 1, 8, 0, 1)]:
+        for bad in [F.fdtd_tuning(4, 1, 8, 0, 1, 1), F.fdtd_tuning(1, 3, 8, 0, 1, 1),
+                    F.fdtd_tuning(1, 1, -1, 0, 1, 1), F.fdtd_tuning(1, 1, 8, -1, 1, 1),
+                    F.fdtd_tuning(2, 1, 8, 0, 1, 1), F.fdtd_tuning(1, 1, 8, 0, 1, 2),
+                    F.fdtd_tuning(1, 1, 8, 0, 1, 0)]:
             assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
-        F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0))
+        F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0, 1))
         assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
-                                                  "xcd_remap": 0}
+                                                  "xcd_remap": 0, "depth": 1}
     finally:
         F.fdtd_destroy(h)
 
@@ -122,8 +123,11 @@ def test_status_strings_and_null_handles():
 def test_tuning_rejects_too_many_sites_per_lane():
     h = F.fdtd_create(cfg(N=32, dtype=F.BF16))
     try:
-        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(8, 2, 8, 0, 1))) == F.EINVAL
-        F.fdtd_set_tuning(h, F.fdtd_tuning(8, 1, 8, 0, 1))
+        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(8, 2, 8, 0, 1, 2))) == F.EINVAL
+        h64 = F.fdtd_create(cfg(N=32, dtype=F.F64))
+        assert status_of("fdtd_set_tuning", h64, C.byref(F.fdtd_tuning(2, 4, 8, 0, 1, 2))) == F.EINVAL
+        F.fdtd_destroy(h64)
+        F.fdtd_set_tuning(h, F.fdtd_tuning(8, 1, 8, 0, 1, 3))
     finally:
         F.fdtd_destroy(h)
 

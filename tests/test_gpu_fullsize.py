@@ -1,0 +1,199 @@
+"""Parity at the full sizes of the benchmark configurations, in the launch
+configuration the benchmark uses.  Where a whole run is out of the oracle's
+reach (20000 steps at 128^3, 4000 steps at 256^3), a short horizon is checked
+against the oracle at full size and the long run against properties that hold
+at any size: bit-exact parity, closed-form hydrogen levels, and the gradient
+against central finite differences of the FP64 GPU path.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle as orc  # noqa: E402
+from paper_0904_0939_amd import fdtd as F  # noqa: E402
+from paper_0904_0939_amd import workloads as W  # noqa: E402
+from paper_0904_0939_amd.solver import Batch, Solver  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    if a @ b < 0:
+        b = -b
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+# ------------------------------------------------------------ 512^3 step ----
+def test_cornell_512_fp32_steps_against_oracle():
+    """Two fused steps on the full 512^3 Cornell lattice (L = 30, dt = a^2/8)
+    from the same noise; the oracle takes the FP32-rounded noise."""
+    say("case: cornell 512^3 fp32, 2 steps")
+    lat = W.cornell(512)
+    s = Solver(lat.N, lat.L, dtype="f32")
+    s.set_potential(F.POT_CORNELL, lat.pot_params)
+    s.set_initial(lat.seed)
+    s.evolve(2)
+    ob = s.observables()[0]
+    g = s.psi(dtype=np.float32)
+    V = orc.potential(orc.POT_CORNELL, lat.pot_params, lat.N, lat.L)
+    psi = f32(orc.initial(lat.N, lat.seed))
+    orc.evolve(psi, V, lat.L, lat.dt, 2)
+    oo = orc.observables(psi, V, lat.L)
+    say(f"E gpu {ob['energy']:.12g} oracle {oo['energy']:.12g}")
+    assert ob["energy"] == pytest.approx(oo["energy"], rel=1e-5)
+    assert ob["r_rms"] == pytest.approx(oo["r_rms"], rel=1e-5)
+    d = np.abs(g - psi)
+    assert d.max() < 2e-5 * np.abs(psi).max()
+
+
+def test_upsample_256_to_512_against_oracle():
+    say("case: upsample 256^3 -> 512^3")
+    L = 30.0
+    c = Solver(256, L, dtype="f32")
+    c.set_potential(F.POT_CORNELL, W.CORNELL_PARAMS)
+    c.set_initial(3)
+    f = Solver(512, L, dtype="f32")
+    f.set_potential(F.POT_CORNELL, W.CORNELL_PARAMS)
+    F.fdtd_upsample(c.h, 0, f.h, 0)
+    c.close()
+    ref = orc.upsample(f32(orc.initial(256, 3)), 512, L)
+    g = f.psi(dtype=np.float32)
+    assert np.abs(g - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+# ------------------------------------------------- Coulomb 128^3, 20000 ----
+@pytest.mark.parametrize("odd", [False, True])
+def test_coulomb_128_even_and_odd_20000_steps(odd):
+    """V = -1/r on 128^3, L = 40 (a = 0.3125, no site at r = 0), FP32 state,
+    FP64 reductions, 20000 steps.  The S_z start relaxes to 1s, the A_z start
+    to 2p_z: E -> -1/2 and -1/8, r_rms -> sqrt(3) and sqrt(30) as a -> 0; at
+    this spacing within a few per cent.  A 40-step prefix is checked against
+    the oracle at full size, the odd parity bit for bit."""
+    lat = W.coulomb_128(odd_z=odd)
+    say(f"case: coulomb 128^3 odd={odd}")
+    s = Solver(lat.N, lat.L, dtype="f32")
+    s.set_potential(F.POT_COULOMB, lat.pot_params)
+    s.set_initial(lat.seed, parity=lat.parity)
+    s.evolve(40)
+    V = orc.potential(orc.POT_COULOMB, lat.pot_params, lat.N, lat.L)
+    psi = orc.initial(lat.N, lat.seed, parity=lat.parity)
+    orc.evolve(psi, V, lat.L, lat.dt, 40)
+    assert s.observables()[0]["energy"] == pytest.approx(orc.observables(psi, V, lat.L)["energy"], rel=1e-5)
+    done, conv = s.evolve(20000 - 40, check_every=100, rel_tol=0.0)
+    ob = s.observables()[0]
+    hist = [h["energy"] for h in s.history(0, 200)]
+    say(f"E = {ob['energy']:.8f} r_rms = {ob['r_rms']:.5f} last dE/100 = {hist[-1] - hist[-101]:.3e}")
+    if odd:
+        assert ob["energy"] == pytest.approx(-0.125, rel=0.01)
+        assert ob["r_rms"] == pytest.approx(math.sqrt(30.0), rel=0.05)
+        v = s.state()
+        assert np.array_equal(v[:, :, ::-1], -v)
+    else:
+        assert ob["energy"] == pytest.approx(-0.5, rel=0.03)
+        assert ob["r_rms"] == pytest.approx(math.sqrt(3.0), rel=0.05)
+    # relaxed: the energy no longer moves at the 1e-6 level per 100 steps
+    assert abs(hist[-1] - hist[-101]) < 1e-6 * abs(hist[-1])
+
+
+# --------------------------------------------------------- batch of 64 -----
+def test_batch64_members_against_oracle():
+    """The 64-member batch (sides 48..160, L = 12, FP32, one launch per step,
+    autotuned shape): one member of each side checked against the oracle
+    after 60 steps."""
+    say("case: batch64")
+    lats = W.wells_batch()
+    b = Batch(lats, dtype="f32")
+    for m, l in enumerate(lats):
+        b.set_potential(l.pot_kind, l.pot_params, member=m)
+    b.set_initial(lats[0].seed)
+    b.autotune(5)
+    b.set_initial(lats[0].seed)
+    b.evolve(60)
+    obs = b.observables()
+    seen = set()
+    for m, l in enumerate(lats):
+        if l.N in seen:
+            continue
+        seen.add(l.N)
+        V = orc.potential(orc.POT_WELLS, l.pot_params, l.N, l.L)
+        psi = orc.initial(l.N, l.seed, member=m)
+        orc.evolve(psi, V, l.L, l.dt, 60)
+        e = orc.observables(psi, V, l.L)["energy"]
+        say(f"member {m} N={l.N}: gpu {obs[m]['energy']:.10f} oracle {e:.10f}")
+        assert obs[m]["energy"] == pytest.approx(e, rel=1e-5)
+        assert rel_l2(b.psi(m), psi) < 1e-5
+    assert seen == set(W.BATCH_SIDES)
+
+
+# -------------------------------------------------- gradient at 256^3 ------
+def test_gradient_256_adjoint_vs_fd_and_hellmann_feynman():
+    """dE/d(A_k, s_k) of the energy after 4000 FP32 steps (checkpoints every
+    100) from a converged, theta-independent start, on the 8-well potential
+    at 256^3, L = 12.  Central differences (h = 1e-3) of the same 4000-step
+    map on the FP64 GPU path must agree to 1e-4 of the largest component; the
+    Hellmann-Feynman integral agrees to O(dt) plus the unrelaxed remainder."""
+    say("case: gradient 256^3")
+    import torch
+
+    lat = W.gradient_wells(256)
+    p = list(lat.pot_params)
+    wrt = W.gradient_param_indices()
+    # converged start: FP32 chain 64 -> 128 -> 256 at the same box
+    prev = None
+    for N in (64, 128, 256):
+        s = Solver(N, lat.L, dtype="f32")
+        s.set_potential(F.POT_WELLS, p)
+        if prev is None:
+            s.set_initial(lat.seed)
+        else:
+            F.fdtd_upsample(prev.h, 0, s.h, 0)
+            prev.close()
+        s.evolve(60000, check_every=100, rel_tol=1e-9)
+        prev = s
+    psi0 = prev.psi_tensor(0, dtype=torch.float32)
+    prev.close()
+    T, k = 4000, 100
+    g32 = Solver(256, lat.L, dtype="f32")
+    g32.set_potential(F.POT_WELLS, p)
+    g32.set_initial_array(psi0)
+    E, grad, _ = g32.energy_grad(T, k, theta=p, wrt=wrt)
+    psiT = g32.psi()
+    g32.close()
+    h = 1e-3
+    f64 = Solver(256, lat.L, dtype="f64")
+    psi0d = psi0.double()
+    fd = []
+    for j in wrt:
+        e = []
+        for sgn in (1, -1):
+            q = list(p)
+            q[j] += sgn * h
+            f64.set_potential(F.POT_WELLS, q)
+            f64.set_initial_array(psi0d)
+            f64.evolve(T)
+            e.append(f64.observables()[0]["energy"])
+        fd.append((e[0] - e[1]) / (2 * h))
+    fd = np.array(fd)
+    grad = np.array(grad)
+    scale = np.abs(fd).max()
+    say("adjoint", grad)
+    say("fd     ", fd)
+    assert np.abs(grad - fd).max() < 1e-4 * scale
+    # Hellmann-Feynman: sum psi^2 dV/dtheta / sum psi^2 on the final state
+    hf = np.array([float(np.sum(psiT * psiT * orc.wells_dv(p, 256, lat.L, j)) / np.sum(psiT * psiT))
+                   for j in wrt])
+    say("hf     ", hf)
+    assert np.abs(hf - fd).max() < 5e-3 * scale

@@ -142,15 +142,16 @@ def test_fp32_coulomb_even_and_odd_starts():
         assert rel_l2(s.psi(), psi_o) < 1e-5
 
 
-@pytest.mark.parametrize("tuning", [(4, 1, 8, 0, 0), (4, 2, 16, 0, 1), (4, 4, 72, 0, 1),
-                                    (1, 1, 13, 0, 0), (1, 4, 5, 37, 1), (4, 2, 7, 64, 1)])
+@pytest.mark.parametrize("tuning", [(4, 1, 8, 0, 0, 1), (4, 2, 16, 0, 1, 2), (4, 2, 72, 0, 1, 3),
+                                    (1, 1, 13, 0, 0, 1), (1, 4, 5, 37, 1, 1), (4, 2, 7, 64, 1, 3),
+                                    (4, 1, 0, 0, 1, 2), (4, 2, 11, 0, 0, 1)])
 def test_fp32_state_is_independent_of_launch_shape(tuning):
     """Without renormalisation the update of a site does not depend on the
     tiling, so every launch shape yields the same bits."""
     say(f"case: fp32 tiling {tuning}")
     N, L = 72, 12.0
     ref, *_ = gpu_run(N, L, "f32", F.POT_WELLS, W.random_wells(np.random.default_rng(1)), 5, 25,
-                      renorm=0, tuning=(4, 2, 32, 0, 1))
+                      renorm=0, tuning=(4, 2, 32, 0, 1, 2))
     s, *_ = gpu_run(N, L, "f32", F.POT_WELLS, W.random_wells(np.random.default_rng(1)), 5, 25,
                     renorm=0, tuning=tuning)
     assert np.array_equal(s.state(), ref.state())
