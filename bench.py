@@ -47,6 +47,60 @@ def measured_traffic(key: str, sites: int):
     return w.get("bytes_per_launch")
 
 
+def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
+    """Per-launch HBM bytes of the fused step kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what
+    the counter reads for the runtime's plain device-to-device copy of the
+    state that the same command performs (bytes known).  Writes
+    profiles/step_traffic.json and prints a markdown summary."""
+    import csv
+    import statistics
+
+    def rows(p):
+        return list(csv.DictReader(open(p)))
+
+    es = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
+    copy_bytes = es * sites
+
+    def per_launch(path):
+        R = rows(path)
+        step = [float(r["Counter_Value"]) for r in R
+                if "k_step<" in r["Kernel_Name"] and ", true," in r["Kernel_Name"]]
+        copy = [float(r["Counter_Value"]) for r in R if "copyBuffer" in r["Kernel_Name"]]
+        return statistics.median(step), max(copy)
+
+    f_step, f_copy = per_launch(fetch_csv)
+    w_step, w_copy = per_launch(write_csv)
+    f_scale = copy_bytes / (f_copy * 1024.0)
+    w_scale = copy_bytes / (w_copy * 1024.0)
+    rd = f_step * 1024.0 * f_scale
+    wr = w_step * 1024.0 * w_scale
+    alg = BYTES_PER_SITE[dtype] * sites
+    avg_ns = None
+    if stats_csv:
+        for r in rows(stats_csv):
+            if "k_step<" in r["Name"] and ", true," in r["Name"]:
+                avg_ns = float(r["AverageNs"])
+    rec = {"kernel_sha": kernel_hash(), "workloads": {}}
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("kernel_sha") != kernel_hash():
+            rec = {"kernel_sha": kernel_hash(), "workloads": {}}
+    except (OSError, ValueError):
+        pass
+    rec["workloads"][key] = {"sites": sites, "bytes_per_launch": rd + wr, "read_bytes": rd,
+                             "write_bytes": wr, "algorithmic_bytes": alg,
+                             "fetch_scale": f_scale, "write_scale": w_scale,
+                             "kernel_avg_ns": avg_ns}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(f"| {key} | read {rd / 2**30:.4f} GiB | write {wr / 2**30:.4f} GiB | "
+          f"algorithmic {alg / 2**30:.4f} GiB | ratio {(rd + wr) / alg:.4f} | "
+          f"FETCH scale {f_scale:.4f} | WRITE scale {w_scale:.4f} | "
+          f"kernel avg {avg_ns / 1e3 if avg_ns else float('nan'):.1f} us |")
+
+
 def cpu_baseline(N, L, params, steps):
     """The FP64 oracle on the same lattice: setup untimed, `steps` steps timed."""
     import oracle as orc
@@ -206,14 +260,21 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tuning", default="", help="vz,ry,xchunk,grid,xcd_remap,depth")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-E and batch measurements")
     ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64"])
+    ap.add_argument("--summarize-rocprof", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV"),
+                    help="turn rocprofv3 counter runs of this bench into profiles/step_traffic.json")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        f, w, st = args.summarize_rocprof
+        summarize_rocprof(f, w, st if st != "-" else None, f"cornell{args.n}_{args.dtype}",
+                          args.n ** 3, args.dtype)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the lattice "
               "fits one MI355X and the multi-GPU slab exchange is not built.", file=sys.stderr)
@@ -261,6 +322,12 @@ def main():
     alg_bytes = BYTES_PER_SITE[args.dtype] * sites
     achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
     ob = s.observables()[0]
+    # a plain device-to-device copy of the state (runtime copy kernel, bytes
+    # known): the calibration point of the HBM byte counters
+    es = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[args.dtype]
+    cal = torch.empty((N, N, N), dtype=es, device="cuda")
+    F.fdtd_get_state(s.h, 0, cal.data_ptr(), 1)
+    del cal
     key = f"cornell{N}_{args.dtype}"
     traffic = measured_traffic(key, sites)
     out = {

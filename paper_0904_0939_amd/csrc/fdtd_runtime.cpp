@@ -195,7 +195,7 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   bool all_div = true;
   for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
   h->tun.vz = all_div ? vw : 1;
-  h->tun.ry = (h->tun.vz == 1) ? 2 : (h->dtype == kF32 ? 2 : 1);
+  h->tun.ry = (h->dtype == kBF16 && h->tun.vz > 1) ? 1 : 2;
   h->tun.xchunk = 0;  // automatic: see auto_xchunk
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;
