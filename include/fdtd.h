@@ -126,9 +126,14 @@ typedef struct {
  *  grid   work-groups launched (0: one per work item);
  *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles;
  *  depth  planes of HBM prefetch ahead of the plane being updated (1..3;
- *         1 for vz = 1). */
+ *         1 for vz = 1);
+ *  variant  0: 256-lane work-groups, y / z neighbours re-read through the
+ *         caches; 2: the same with 512-lane work-groups (ry = 1); 1: large
+ *         work-groups (1024 lanes, 512 for BF16) sharing an LDS copy of each
+ *         plane (needs vz = the vector width, 2N / vz <= the work-group size
+ *         and a tile of at most 64 KiB; ry is ignored). */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap, depth;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/

@@ -76,8 +76,15 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 
 // Launch the fused step (update = true) or the reduction-only pass.
 // depth: prefetch distance of the HBM streams, in planes (1..3).
-hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid,
+// bt: threads per work-group, 256, or 512 for ry = 1.
+hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        const StepArgs& a, hipStream_t s);
+// LDS-tile variant: work-groups of tile_threads(dtype) lanes, one vector of
+// the dtype's width per lane; max_n sizes the LDS tile (two planes of the
+// chunk plus one row above and below).
+int tile_threads(int dtype);
+hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max_n,
+                            const StepArgs& a, hipStream_t s);
 
 // One thread per site, member m only.
 hipError_t launch_potential(int vdtype, void* V, int N, double ha, double a, int kind,

@@ -122,7 +122,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum NV values over the work-group; the result is valid in thread 0.
 // Fixed order: lanes by butterfly, then waves 0..3 left to right.
-template <int NV>
+template <int NV, int NW = kBlock / 64>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
   const int tid = threadIdx.x;
 #pragma unroll
@@ -137,7 +137,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
     for (int k = 0; k < NV; ++k) {
       double t = red[0][k];
 #pragma unroll
-      for (int w = 1; w < kBlock / 64; ++w) t += red[w][k];
+      for (int w = 1; w < NW; ++w) t += red[w][k];
       v[k] = t;
     }
   }
@@ -145,6 +145,21 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
 }
 
 __device__ __forceinline__ bool finite_d(double x) { return !(isnan(x) || isinf(x)); }
+
+// Values the work-group shares (work-item fields, member constants) kept in
+// scalar registers: buffer descriptors built from them must be uniform, or
+// every buffer access becomes a per-lane loop.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uni(unsigned v) {
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
 
 // ------------------------------------------------------- buffer access ----
 // Raw buffer loads return 0 and raw buffer stores are dropped for offsets at
@@ -171,7 +186,19 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // used once: V, and the written state); kKeep leaves the default policy
 // (psi, whose lines are re-read as neighbours by adjacent lanes).
 constexpr int kKeep = 0;
-constexpr int kNT = 2;
+// Build-time choice of the policies of the four streams of the step kernel.
+#ifndef FDTD_AUX_PSI
+#define FDTD_AUX_PSI 0  // own-site psi loads (first touch of each plane)
+#endif
+#ifndef FDTD_AUX_NBR
+#define FDTD_AUX_NBR 0  // y / z neighbour loads (re-reads, meant to hit L2)
+#endif
+#ifndef FDTD_AUX_V
+#define FDTD_AUX_V 2    // V loads (used once): non-temporal
+#endif
+#ifndef FDTD_AUX_OUT
+#define FDTD_AUX_OUT 2  // psi' stores (read back only by the next launch): non-temporal
+#endif
 
 // Load VZ consecutive elements of S at byte offset `off`, converted to C.
 template <typename S, int VZ, typename C, int AUX = kKeep>
@@ -246,6 +273,54 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   return x;
 }
 
+// Last work-group of member m: record the step's sums, set the scale of the
+// next update, advance the step counter, flag non-finite sums, and re-arm
+// the completion counter for the next launch.
+__device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, int m,
+                                      const double (&tot)[5], bool upd) {
+  MemberState& st = A.states[m];
+  const double kin = -M.kin_scale * tot[1];
+  const long long t = st.step;
+  double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, (double)st.scale, 0.0};
+  if (upd) {
+    double* dst = A.ring + ((long long)m * A.ring_cap + (t % A.ring_cap)) * kRec;
+#pragma unroll
+    for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
+    const long long nt = t + 1;
+    const bool renorm = A.renorm_every > 0 && (nt % A.renorm_every) == 0;
+    st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
+    st.step = nt;
+    if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) && !st.bad) {
+      st.bad = 1;
+      st.bad_step = t;
+    }
+  } else {
+    // reduction-only pass: the host inspects the sums itself
+    double* dst = A.obs_out + (long long)m * kRec;
+#pragma unroll
+    for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
+    if (A.set_scale) st.scale = 1.0 / sqrt(M.a3 * tot[0]);
+  }
+  st.counter = 0u;
+}
+
+// Cross-lane read within the wave (ds_bpermute through the LDS crossbar,
+// no memory traffic); src must be in [0, 64) for the lanes whose result is used.
+__device__ __forceinline__ float shfl_c(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute((src & 63) << 2, __float_as_int(v)));
+}
+__device__ __forceinline__ double shfl_c(double v, int src) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)u);
+  const int hi = __builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+#ifndef FDTD_SHUFFLE_Z
+#define FDTD_SHUFFLE_Z 1
+#endif
+constexpr bool kShuffleZ = FDTD_SHUFFLE_Z != 0;
+
 // ------------------------------------------------------- fused step kernel --
 // Per-lane state of one work item: RY vectors of VZ sites at fixed (y, z).
 template <int RY, int VZ, typename C>
@@ -254,6 +329,8 @@ struct Lane {
   unsigned voff[RY];      // byte offset of the vector in a plane of V
   unsigned offm[RY];      // y - 1 neighbour vector (may wrap: then out of range)
   unsigned offp[RY];      // y + 1 neighbour vector (out of range past the plane)
+  unsigned offzm[RY];     // z - 1 site, for the wave's first lane only (else out of range)
+  unsigned offzp[RY];     // z + 1 site, for the wave's last lane only (else out of range)
   float zmask_lo[RY];     // 0 where the vector starts at z = 0 (its z - 1 is a ghost)
   float zmask_hi[RY];     // 0 where the vector ends at z = N - 1
   C w2[RY][VZ];           // y^2 + z^2 of each site
@@ -273,6 +350,9 @@ struct StepBody {
   using TV = typename Types<DT>::V;
   using C = typename Types<DT>::C;
   static constexpr unsigned kES = sizeof(S);
+  // z neighbours across vector boundaries by cross-lane reads (measured
+  // faster for FP32 and FP64; BF16 lanes hold 8 sites and gain nothing)
+  static constexpr bool kSHZ = kShuffleZ && DT != kBF16;
 
   struct Ctx {
     const void* in;
@@ -280,57 +360,75 @@ struct StepBody {
     const TV* Vf;
     unsigned pbytes, vbytes;
     int N;
+    int xe;  // end of the work item: planes the item never reads get empty resources
     C c, dt, eps, sc;
     double ha, cN;
     uint32_t smix, kN;
   };
 
-  // Issue the loads of the y and z neighbours of plane x.
+  // Issue the loads of the y and z neighbours of plane x (needed for x < xe).
   static __device__ __forceinline__ void fetch(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                PlaneIn<RY, VZ, C>& d) {
-    const __amdgpu_buffer_rsrc_t rc = plane_rsrc(k.in, x, k.N, k.pbytes);
+    const __amdgpu_buffer_rsrc_t rc = plane_rsrc(k.in, x, min(k.N, k.xe), k.pbytes);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       C zz[1];
-      bload<S, VZ, C>(rc, ln.offm[r], d.ym[r]);
-      bload<S, VZ, C>(rc, ln.offp[r], d.yp[r]);
-      bload<S, 1, C>(rc, ln.off[r] - kES, zz);
+      bload<S, VZ, C, FDTD_AUX_NBR>(rc, ln.offm[r], d.ym[r]);
+      bload<S, VZ, C, FDTD_AUX_NBR>(rc, ln.offp[r], d.yp[r]);
+      bload<S, 1, C, FDTD_AUX_NBR>(rc, ln.offzm[r], zz);
       d.zm[r] = zz[0];
-      bload<S, 1, C>(rc, ln.off[r] + VZ * kES, zz);
+      bload<S, 1, C, FDTD_AUX_NBR>(rc, ln.offzp[r], zz);
       d.zp[r] = zz[0];
     }
   }
 
   static __device__ __forceinline__ void fetch_v(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                  C (&v)[RY][VZ]) {
-    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, k.N, k.vbytes);
+    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) bload<TV, VZ, C, kNT>(rv, ln.voff[r], v[r]);
+    for (int r = 0; r < RY; ++r) bload<TV, VZ, C, FDTD_AUX_V>(rv, ln.voff[r], v[r]);
   }
 
+  // Own sites of plane x (needed for x <= xe).
   static __device__ __forceinline__ void fetch_own(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                    C (&q)[RY][VZ]) {
-    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(k.in, x, k.N, k.pbytes);
+    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(k.in, x, min(k.N, k.xe + 1), k.pbytes);
 #pragma unroll
-    for (int r = 0; r < RY; ++r) bload<S, VZ, C>(r0, ln.off[r], q[r]);
+    for (int r = 0; r < RY; ++r) bload<S, VZ, C, FDTD_AUX_PSI>(r0, ln.off[r], q[r]);
   }
 
   // Update plane x from pm (x-1), pc (x), pn (x+1) and d; accumulate the
-  // reductions of plane x into acc.
+  // reductions of plane x into acc.  SHZ: the z neighbours across a vector
+  // boundary come from the adjacent lanes, d.zm / d.zp hold them for the
+  // wave's edge lanes only; otherwise d.zm / d.zp hold them for every lane.
+  template <bool SHZ = kSHZ>
   static __device__ __forceinline__ void update(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                 const C (&pm)[RY][VZ], const C (&pc)[RY][VZ],
                                                 const C (&pn)[RY][VZ], const C (&vv)[RY][VZ],
-                                                const PlaneIn<RY, VZ, C>& d, double (&acc)[5]) {
+                                                const PlaneIn<RY, VZ, C>& d, double (&acc)[5],
+                                                bool live = true) {
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
     const __amdgpu_buffer_rsrc_t ro = plane_rsrc(k.out, x, k.N, k.pbytes);
     const uint32_t kx = (uint32_t)min(x, k.N - 1 - x) * k.kN;
     C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
+    const int lane = __lane_id();
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       Pack<S, VZ> o;
-      const C lo = d.zm[r] * (C)ln.zmask_lo[r];
-      const C hi = d.zp[r] * (C)ln.zmask_hi[r];
+      // z - 1 of the first site and z + 1 of the last come from the adjacent
+      // lanes (consecutive lanes hold consecutive vectors of the flattened
+      // plane); only the wave's edge lanes took them from memory
+      C lo, hi;
+      if constexpr (SHZ) {
+        const C fl = shfl_c(pc[r][VZ - 1], lane - 1);
+        const C fr = shfl_c(pc[r][0], lane + 1);
+        lo = (lane == 0 ? d.zm[r] : fl) * (C)ln.zmask_lo[r];
+        hi = (lane == 63 ? d.zp[r] : fr) * (C)ln.zmask_hi[r];
+      } else {
+        lo = d.zm[r] * (C)ln.zmask_lo[r];
+        hi = d.zp[r] * (C)ln.zmask_hi[r];
+      }
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         const C p = pc[r][j];
@@ -354,10 +452,10 @@ struct StepBody {
             o.v[j] = (S)nv;
           }
           const C od = to_c<S, C>(o.v[j]);
-          s1 += od * od;
+          s1 += live ? od * od : C(0);
         }
       }
-      if constexpr (UPD) bstore<S, VZ, kNT>(ro, ln.off[r], o);
+      if constexpr (UPD) bstore<S, VZ, FDTD_AUX_OUT>(ro, ln.off[r], o);
     }
     acc[0] += (double)s0;
     acc[1] += (double)kin;
@@ -385,14 +483,18 @@ struct StepBody {
   }
 };
 
-template <int DT, int VZ, int RY, bool UPD, int D>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+#ifndef FDTD_STEP_MIN_WAVES
+#define FDTD_STEP_MIN_WAVES 1  // waves per SIMD the register budget must allow
+#endif
+
+template <int DT, int VZ, int RY, bool UPD, int D, int BT>
+__global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
   using Body = StepBody<DT, VZ, RY, UPD>;
   using S = typename Body::S;
   using TV = typename Body::TV;
   using C = typename Body::C;
   constexpr unsigned kES = sizeof(S);
-  __shared__ double s_red[kBlock / 64][5];
+  __shared__ double s_red[BT / 64][5];
   __shared__ int s_last;
   const int tid = threadIdx.x;
 
@@ -418,7 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     Lane<RY, VZ, C> ln;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      const unsigned f = (unsigned)item.f0 + (unsigned)(r * kBlock + tid) * VZ;
+      const unsigned f = (unsigned)item.f0 + (unsigned)(r * BT + tid) * VZ;
       const bool ok = f < P;
       const unsigned fe = ok ? f : kDeadLane;
       const int y = ok ? (int)(f / (unsigned)N) : 0;
@@ -427,6 +529,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
       ln.voff[r] = fe * (unsigned)sizeof(TV);
       ln.offm[r] = (fe - (unsigned)N) * kES;  // wraps below row 0: out of range
       ln.offp[r] = (fe + (unsigned)N) * kES;
+      const int lane = __lane_id();
+      if constexpr (Body::kSHZ) {
+        ln.offzm[r] = (ok && lane == 0 && z0 > 0) ? (f - 1u) * kES : kDeadLane * kES;
+        ln.offzp[r] = (ok && lane == 63 && z0 + VZ < N) ? (f + VZ) * kES : kDeadLane * kES;
+      } else {
+        ln.offzm[r] = fe * kES - kES;
+        ln.offzp[r] = fe * kES + VZ * kES;
+      }
       ln.zmask_lo[r] = (ok && z0 > 0) ? 1.f : 0.f;
       ln.zmask_hi[r] = (ok && z0 + VZ < N) ? 1.f : 0.f;
       const double yc = (2.0 * y - cN) * ha;
@@ -456,6 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     k.cN = cN;
     k.smix = smix;
     k.kN = kN;
+    k.xe = item.xe;
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     C qs[6][RY][VZ], vs[6][RY][VZ];
@@ -487,7 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     if (x + 4 < xe) Body::template stage<D, 4>(k, ln, x + 4, qs, vs, nb, acc);
 
     // ---- per-item partials, then the last work-group of the member sums them
-    block_sum<5>(acc, s_red);
+    block_sum<5, BT / 64>(acc, s_red);
     if (tid == 0) {
       double* part = A.partials + (long long)it * kRec;
 #pragma unroll
@@ -500,39 +611,231 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     if (s_last) {
       __threadfence();
       double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int i = M.item_begin + tid; i < M.item_end; i += kBlock) {
+      for (int i = M.item_begin + tid; i < M.item_end; i += BT) {
         const double* part = A.partials + (long long)i * kRec;
 #pragma unroll
         for (int k = 0; k < 5; ++k) tot[k] += part[k];
       }
-      block_sum<5>(tot, s_red);
-      if (tid == 0) {
-        MemberState& st = A.states[m];
-        const double kin = -M.kin_scale * tot[1];
-        const long long t = st.step;
-        double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, (double)st.scale, 0.0};
-        if (UPD) {
-          double* dst = A.ring + ((long long)m * A.ring_cap + (t % A.ring_cap)) * kRec;
+      block_sum<5, BT / 64>(tot, s_red);
+      if (tid == 0) finalize(A, M, m, tot, UPD);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------- fused step, LDS plane tiles ----
+// Variant of k_step for large work-groups: each lane owns one vector of VZ
+// sites, the work-group a chunk of kTB * VZ consecutive sites of the
+// flattened (y, z) plane.  Planes stream along x as before (own sites of
+// x-1, x, x+1 in a register ring, loads D planes ahead), but the y and z
+// neighbours come from an LDS copy of plane x: the chunk plus one row above
+// and below it (the halo rows, loaded by the first 2N/VZ lanes).  Two LDS
+// buffers alternate between planes; one work-group barrier per plane, fenced
+// on LDS only so the prefetched global loads stay in flight.  Per lane and
+// plane this issues 2 (+1 halo) vector loads instead of 6, and keeps no
+// neighbour registers, so 16 waves fit on a CU.
+template <int DT>
+struct TileShape {
+  static constexpr int kTB = DT == kBF16 ? 512 : 1024;  // threads per work-group
+};
+
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int DT, int VZ, bool UPD, int D>
+struct TileBody {
+  using Body = StepBody<DT, VZ, 1, UPD>;
+  using S = typename Body::S;
+  using C = typename Body::C;
+  using Ctx = typename Body::Ctx;
+
+  static __device__ __forceinline__ void fetch_halo(const Ctx& k, int x, unsigned hoff,
+                                                    C (&h)[VZ]) {
+    const __amdgpu_buffer_rsrc_t r = plane_rsrc(k.in, x, min(k.N, k.xe + 1), k.pbytes);
+    bload<S, VZ, C, FDTD_AUX_PSI>(r, hoff, h);
+  }
+
+  static __device__ __forceinline__ void put(C* tile, unsigned TS, int b, unsigned rel,
+                                             bool has_halo, unsigned hidx, const C (&q)[1][VZ],
+                                             const C (&h)[VZ]) {
+    C* t = tile + (unsigned)b * TS;
+    Pack<C, VZ> pq, ph;
 #pragma unroll
-          for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
-          const long long nt = t + 1;
-          const bool renorm = A.renorm_every > 0 && (nt % A.renorm_every) == 0;
-          st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
-          st.step = nt;
-          if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) &&
-              !st.bad) {
-            st.bad = 1;
-            st.bad_step = t;
-          }
-        } else {
-          // reduction-only pass: the host inspects the sums itself
-          double* dst = A.obs_out + (long long)m * kRec;
+    for (int j = 0; j < VZ; ++j) {
+      pq.v[j] = q[0][j];
+      ph.v[j] = h[j];
+    }
+    *reinterpret_cast<Pack<C, VZ>*>(t + rel) = pq;
+    if (has_halo) *reinterpret_cast<Pack<C, VZ>*>(t + hidx) = ph;
+  }
+
+  // Update plane X from LDS buffer SL & 1, then stage plane X + 1 into the
+  // other buffer.
+  template <int SL>
+  static __device__ __forceinline__ void stage(const Ctx& k, const Lane<1, VZ, C>& ln, int X,
+                                               C* tile, unsigned TS, unsigned rel, bool has_halo,
+                                               unsigned hidx, unsigned hoff, bool ok,
+                                               C (&qs)[6][1][VZ], C (&vs)[6][1][VZ],
+                                               C (&hs)[6][VZ], double (&acc)[5]) {
+    constexpr int b = SL & 1;
+    Body::fetch_own(k, ln, X + 1 + D, qs[(SL + 2 + D) % 6]);
+    Body::fetch_v(k, ln, X + D, vs[(SL + D) % 6]);
+    fetch_halo(k, X + 1 + D, hoff, hs[(SL + 2 + D) % 6]);
+    PlaneIn<1, VZ, C> nb;
+    const C* t = tile + (unsigned)b * TS;
+    const unsigned N = (unsigned)k.N;
+    const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(t + rel - N);
+    const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(t + rel + N);
 #pragma unroll
-          for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
-          if (A.set_scale) st.scale = 1.0 / sqrt(M.a3 * tot[0]);
-        }
-        st.counter = 0u;
+    for (int j = 0; j < VZ; ++j) {
+      nb.ym[0][j] = pm.v[j];
+      nb.yp[0][j] = pp.v[j];
+    }
+    nb.zm[0] = t[rel - 1];
+    nb.zp[0] = t[rel + VZ];
+    Body::template update<false>(k, ln, X, qs[SL % 6], qs[(SL + 1) % 6], qs[(SL + 2) % 6],
+                                 vs[SL % 6], nb, acc, ok);
+    put(tile, TS, b ^ 1, rel, has_halo, hidx, qs[(SL + 2) % 6], hs[(SL + 2) % 6]);
+    lds_barrier();
+  }
+};
+
+template <int DT, int VZ, bool UPD, int D>
+__global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
+  using Body = StepBody<DT, VZ, 1, UPD>;
+  using S = typename Body::S;
+  using TV = typename Body::TV;
+  using C = typename Body::C;
+  constexpr int kTB = TileShape<DT>::kTB;
+  constexpr unsigned kES = sizeof(S);
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[kTB / 64][5];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+
+  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
+    const int it = A.item_offset + li;
+    const Item item0 = A.items[it];
+    Item item;
+    item.member = uni(item0.member);
+    item.f0 = uni(item0.f0);
+    item.xb = uni(item0.xb);
+    item.xe = uni(item0.xe);
+    const int m = item.member;
+    const MemberDev& M = A.members[m];
+    const int N = uni(M.N);
+    const unsigned P = uni((unsigned)M.plane);
+    const unsigned F = (unsigned)kTB * VZ;
+    const unsigned TS = F + 2u * (unsigned)N;  // tile elements per buffer
+    C* tile = reinterpret_cast<C*>(smem);       // [2][TS]
+
+    typename Body::Ctx k;
+    k.in = uni(M.psi[A.src]);
+    k.out = uni(M.psi[A.src ^ 1]);
+    k.Vf = uni(static_cast<const TV*>(M.V));
+    k.pbytes = P * kES;
+    k.vbytes = P * (unsigned)sizeof(TV);
+    k.N = N;
+    k.c = (C)M.c;
+    k.dt = (C)M.dt;
+    k.eps = (C)(0.5 * M.dt);
+    k.sc = (C)A.states[m].scale;
+    k.ha = M.ha;
+    k.cN = (double)(N - 1);
+    k.smix = (uint32_t)A.states[m].step * 0x9E3779B9u;
+    k.kN = (uint32_t)N * (uint32_t)N;
+    k.xe = item.xe;
+
+    // own vector
+    Lane<1, VZ, C> ln;
+    const unsigned f = (unsigned)item.f0 + (unsigned)tid * VZ;
+    const bool ok = f < P;
+    {
+      const unsigned fe = ok ? f : kDeadLane;
+      const int y = ok ? (int)(f / (unsigned)N) : 0;
+      const int z0 = ok ? (int)(f - (unsigned)y * N) : 0;
+      ln.off[0] = fe * kES;
+      ln.voff[0] = fe * (unsigned)sizeof(TV);
+      ln.offm[0] = 0;
+      ln.offp[0] = 0;
+      ln.zmask_lo[0] = (ok && z0 > 0) ? 1.f : 0.f;
+      ln.zmask_hi[0] = (ok && z0 + VZ < N) ? 1.f : 0.f;
+      const double yc = (2.0 * y - k.cN) * k.ha;
+      const int cy = min(y, N - 1 - y);
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        const double zc = (2.0 * (z0 + j) - k.cN) * k.ha;
+        ln.w2[0][j] = (C)(yc * yc + zc * zc);
+        const int z = z0 + j;
+        ln.key[0][j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
       }
+    }
+    const unsigned rel = (unsigned)tid * VZ + (unsigned)N;  // own vector in the tile
+    // halo: lanes below 2N/VZ fetch one vector of the row above / below the chunk
+    const unsigned nh = 2u * (unsigned)N / VZ;
+    const bool has_halo = (unsigned)tid < nh;
+    unsigned hoff = kDeadLane * kES, hidx = 0;
+    if (has_halo) {
+      const unsigned half = (unsigned)N / VZ;
+      const bool above = (unsigned)tid < half;
+      const unsigned t = above ? (unsigned)tid : (unsigned)tid - half;
+      const unsigned hf = above ? (unsigned)item.f0 - (unsigned)N + t * VZ
+                                : (unsigned)item.f0 + F + t * VZ;  // may wrap: out of range
+      hoff = hf * kES;
+      hidx = above ? t * VZ : F + (unsigned)N + t * VZ;
+    }
+
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    C qs[6][1][VZ], vs[6][1][VZ], hs[6][VZ];
+    const int xb = item.xb, xe = item.xe;
+    using TB = TileBody<DT, VZ, UPD, D>;
+#pragma unroll
+    for (int i = 0; i < D + 2; ++i) Body::fetch_own(k, ln, xb - 1 + i, qs[i]);
+#pragma unroll
+    for (int i = 1; i < D + 2; ++i) TB::fetch_halo(k, xb - 1 + i, hoff, hs[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) Body::fetch_v(k, ln, xb + i, vs[i]);
+    TB::put(tile, TS, 0, rel, has_halo, hidx, qs[1], hs[1]);
+    lds_barrier();
+    int x = xb;
+    for (; x + 6 <= xe; x += 6) {
+      TB::template stage<0>(k, ln, x, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+      TB::template stage<1>(k, ln, x + 1, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+      TB::template stage<2>(k, ln, x + 2, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+      TB::template stage<3>(k, ln, x + 3, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+      TB::template stage<4>(k, ln, x + 4, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+      TB::template stage<5>(k, ln, x + 5, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+    }
+    // tail: x is uniform, so every lane takes the same branches (barriers)
+    if (x < xe) TB::template stage<0>(k, ln, x, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+    if (x + 1 < xe) TB::template stage<1>(k, ln, x + 1, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+    if (x + 2 < xe) TB::template stage<2>(k, ln, x + 2, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+    if (x + 3 < xe) TB::template stage<3>(k, ln, x + 3, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+    if (x + 4 < xe) TB::template stage<4>(k, ln, x + 4, tile, TS, rel, has_halo, hidx, hoff, ok, qs, vs, hs, acc);
+
+    block_sum<5, kTB / 64>(acc, s_red);
+    if (tid == 0) {
+      double* part = A.partials + (long long)it * kRec;
+#pragma unroll
+      for (int kk = 0; kk < 5; ++kk) part[kk] = acc[kk];
+      __threadfence();
+      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+      s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = M.item_begin + tid; i < M.item_end; i += kTB) {
+        const double* part = A.partials + (long long)i * kRec;
+#pragma unroll
+        for (int kk = 0; kk < 5; ++kk) tot[kk] += part[kk];
+      }
+      block_sum<5, kTB / 64>(tot, s_red);
+      if (tid == 0) finalize(A, M, m, tot, UPD);
     }
     __syncthreads();
   }
@@ -882,59 +1185,106 @@ int grid_for(long long n) {
 // instantiated; the scalar-lane fallback (VZ = 1) and the reduction-only
 // pass use prefetch distance 1 only.
 template <int DT, int VZ, int RY, bool UPD, int D>
-hipError_t step_one(int grid, const StepArgs& a, hipStream_t s) {
+hipError_t step_one(int grid, int bt, const StepArgs& a, hipStream_t s) {
   if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || (UPD && VZ > 1))) {
-    hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D>), dim3(grid), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    if (bt == 256) {
+      hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256>), dim3(grid), dim3(256), 0, s, a);
+      return hipGetLastError();
+    }
+    // 512-lane groups cap registers at 256: one vector of <= 16 bytes of
+    // arithmetic-type state per lane, and no deep prefetch for FP64
+    if constexpr (RY == 1 && VZ * sizeof(typename Types<DT>::C) <= 16 &&
+                  (D == 1 || sizeof(typename Types<DT>::C) == 4)) {
+      if (bt == 512) {
+        hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD, D, 512>), dim3(grid), dim3(512), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    return hipErrorInvalidValue;
   } else {
     return hipErrorInvalidValue;
   }
 }
 
 template <int DT, int VZ, bool UPD, int D>
-hipError_t step_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
+hipError_t step_ry(int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, a, s);
-    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, a, s);
-    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, a, s);
+    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, bt, a, s);
+    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, bt, a, s);
+    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, bt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, int VZ, bool UPD>
-hipError_t step_d(int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+hipError_t step_d(int depth, int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
   switch (depth) {
-    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, a, s);
-    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, a, s);
-    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, a, s);
+    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, bt, a, s);
+    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, bt, a, s);
+    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, bt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, bool UPD>
-hipError_t step_vz(int vz, int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
-  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, a, s);
-  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, a, s);
+hipError_t step_vz(int vz, int depth, int ry, int grid, int bt, const StepArgs& a,
+                   hipStream_t s) {
+  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, bt, a, s);
+  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, bt, a, s);
   return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, const StepArgs& a,
+hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, int bt, const StepArgs& a,
                    hipStream_t s) {
-  return upd ? step_vz<DT, true>(vz, depth, ry, grid, a, s)
-             : step_vz<DT, false>(vz, 1, ry, grid, a, s);
+  return upd ? step_vz<DT, true>(vz, depth, ry, grid, bt, a, s)
+             : step_vz<DT, false>(vz, 1, ry, grid, bt, a, s);
+}
+
+template <int DT, bool UPD, int D>
+hipError_t tile_d(int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
+  constexpr int VZ = Types<DT>::kVec;
+  hipLaunchKernelGGL((k_step_tile<DT, VZ, UPD, D>), dim3(grid), dim3(TileShape<DT>::kTB), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t tile_dt(int depth, bool upd, int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
+  if (!upd) return tile_d<DT, false, 1>(grid, lds, a, s);
+  switch (depth) {
+    case 1: return tile_d<DT, true, 1>(grid, lds, a, s);
+    case 2: return tile_d<DT, true, 2>(grid, lds, a, s);
+    case 3: return tile_d<DT, true, 3>(grid, lds, a, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid,
+int tile_threads(int dtype) { return dtype == kBF16 ? 512 : 1024; }
+
+hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max_n,
+                            const StepArgs& a, hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
+  const unsigned vz = dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8);
+  const unsigned cs = dtype == kF64 ? 8 : 4;
+  const unsigned lds = 2u * ((unsigned)tile_threads(dtype) * vz + 2u * (unsigned)max_n) * cs;
+  switch (dtype) {
+    case kF64: return tile_dt<kF64>(depth, update, grid, lds, a, s);
+    case kF32: return tile_dt<kF32>(depth, update, grid, lds, a, s);
+    case kBF16: return tile_dt<kBF16>(depth, update, grid, lds, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        const StepArgs& a, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
   if (vz == 1) depth = 1;
   switch (dtype) {
-    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, a, s);
-    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, a, s);
-    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, a, s);
+    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, bt, a, s);
+    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, bt, a, s);
+    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -200,6 +200,7 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;
   h->tun.depth = (h->dtype == kBF16 && h->tun.vz > 1) ? 2 : 1;
+  h->tun.variant = 0;
   *out = h;
   return FDTD_OK;
 }
@@ -271,6 +272,12 @@ void xcd_permute(std::vector<int>& pos, int n) {
   for (int b = 0; b < n; ++b) pos[b] = (b < 8 * q) ? (b % 8) * q + b / 8 : b;
 }
 
+// Sites of a plane that one work item covers.
+long long chunk_sites(const fdtd_ctx* h, const fdtd_tuning& t) {
+  if (t.variant == 1) return (long long)tile_threads(h->dtype) * vec_width(h->dtype);
+  return (long long)(t.variant == 2 ? 512 : kBlock) * t.vz * t.ry;
+}
+
 // Longest x-stream (fewest re-read halo planes, least per-item start-up)
 // that still gives each of the 256 CUs a work item (measured at 512^3: one
 // long-streaming work-group per CU beats more, shorter ones).
@@ -279,7 +286,7 @@ int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
     long long items = 0;
     for (const auto& m : h->mem) {
       const long long P = (long long)m.N * m.N;
-      const long long F = (long long)kBlock * t.vz * t.ry;
+      const long long F = chunk_sites(h, t);
       const int x = std::min(xc, m.N);
       items += ((P + F - 1) / F) * ((m.N + x - 1) / x);
     }
@@ -296,7 +303,7 @@ fdtd_status build_items(fdtd_ctx* h) {
   for (int i = 0; i < h->count; ++i) {
     MemberHost& m = h->mem[i];
     const long long P = (long long)m.N * m.N;
-    const long long F = (long long)kBlock * t.vz * t.ry;
+    const long long F = chunk_sites(h, t);
     const int nchunk = (int)((P + F - 1) / F);
     const int xc = std::max(1, std::min(t.xchunk, m.N));
     const int nx = (m.N + xc - 1) / xc;
@@ -356,6 +363,22 @@ int launch_grid(const fdtd_ctx* h, int n_items) {
   return n_items;
 }
 
+int max_n(const fdtd_ctx* h) {
+  int n = 0;
+  for (const auto& m : h->mem) n = std::max(n, m.N);
+  return n;
+}
+
+// Launch the fused step (update) or the reduction-only pass with the
+// handle's launch shape.
+hipError_t launch_kernel(const fdtd_ctx* h, bool update, int grid, const StepArgs& a,
+                         hipStream_t s) {
+  if (h->tun.variant == 1)
+    return launch_step_tile(h->dtype, update ? h->tun.depth : 1, update, grid, max_n(h), a, s);
+  return launch_step(h->dtype, h->tun.vz, h->tun.ry, update ? h->tun.depth : 1, update, grid,
+                     h->tun.variant == 2 ? 512 : 256, a, s);
+}
+
 StepArgs base_args(fdtd_ctx* h) {
   StepArgs a;
   memset(&a, 0, sizeof a);
@@ -382,7 +405,7 @@ fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
   }
-  HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, 1, false, launch_grid(h, a.n_items), a, h->stream));
+  HIP_TRY(launch_kernel(h, false, launch_grid(h, a.n_items), a, h->stream));
   return FDTD_OK;
 }
 
@@ -390,7 +413,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
   for (int k = 0; k < n; ++k) {
     StepArgs a = base_args(h);
     a.renorm_every = renorm_every;
-    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, true, launch_grid(h, a.n_items), a, s));
+    HIP_TRY(launch_kernel(h, true, launch_grid(h, a.n_items), a, s));
     h->cur ^= 1;
   }
   return FDTD_OK;
@@ -398,7 +421,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
-         a.xcd_remap == b.xcd_remap && a.depth == b.depth;
+         a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -549,6 +572,21 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   if (t.grid < 0) return fail(FDTD_EINVAL, "tuning: grid must be >= 0");
   if (t.depth < 1 || t.depth > 3) return fail(FDTD_EINVAL, "tuning: depth must be 1, 2 or 3");
   if (t.vz == 1 && t.depth != 1) return fail(FDTD_EINVAL, "tuning: depth must be 1 when vz = 1");
+  if (t.variant < 0 || t.variant > 2) return fail(FDTD_EINVAL, "tuning: variant must be 0, 1 or 2");
+  if (t.variant == 2) {
+    if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");
+    if (h->dtype == kBF16 && t.vz > 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs vz = 1 for BF16");
+    if (h->dtype == kF64 && t.depth > 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs depth = 1 for F64");
+  }
+  if (t.variant == 1) {
+    const int vw = vec_width(h->dtype);
+    if (t.vz != vw) return fail(FDTD_EINVAL, "tuning: the LDS-tile variant needs vz = the dtype's vector width");
+    const long long tb = tile_threads(h->dtype), cs = h->dtype == kF64 ? 8 : 4;
+    for (auto& m : h->mem) {
+      if (2LL * m.N / vw > tb) return fail(FDTD_EINVAL, "tuning: the LDS-tile variant needs 2N / vz <= its work-group size");
+      if (2LL * (tb * vw + 2LL * m.N) * cs > 65536) return fail(FDTD_EINVAL, "tuning: the LDS tile would exceed 64 KiB");
+    }
+  }
   return FDTD_OK;
 }
 
@@ -777,7 +815,7 @@ fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
     // the reduction needs V only for the energy sums; it is harmless if unset
-    HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, 1, false, launch_grid(h, a.n_items), a, h->stream));
+    HIP_TRY(launch_kernel(h, false, launch_grid(h, a.n_items), a, h->stream));
   }
   HIP_TRY(hipMemcpyAsync(h->h_pin, h->d_obs() + (size_t)member * kRec, sizeof(double) * kRec,
                          hipMemcpyDeviceToHost, h->stream));
@@ -945,10 +983,10 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     for (int ry : {1, 2, 4})
       for (int xc : {0, 32, 64, 128, 256})
         for (int depth : {1, 2, 3})
-          for (int grid : {0, 1024}) {
+          for (int variant : {0, 2}) {
           const int remap = 1;
           if (xc > maxN || (vz == 1 && depth > 1)) continue;
-          fdtd_tuning t{vz, ry, xc, grid, remap, depth};
+          fdtd_tuning t{vz, ry, xc, 0, remap, depth, variant};
           if (validate_tuning(h, t) != FDTD_OK) continue;
           h->tun = t;
           h->items_valid = false;
@@ -969,6 +1007,31 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
             best = t;
           }
         }
+  // LDS-tile variant
+  for (int xc : {0, 64, 128, 256})
+    for (int depth : {1, 2, 3}) {
+      if (xc > maxN) continue;
+      fdtd_tuning t{vw, 1, xc, 0, 1, depth, 1};
+      if (!all_div || validate_tuning(h, t) != FDTD_OK) continue;
+      h->tun = t;
+      h->items_valid = false;
+      if ((st = build_items(h)) != FDTD_OK) goto done;
+      if ((st = launch_steps(h, 1, 1, h->stream)) != FDTD_OK) goto done;
+      (void)hipEventRecord(e0, h->stream);
+      if ((st = launch_steps(h, steps_per_trial, 1, h->stream)) != FDTD_OK) goto done;
+      (void)hipEventRecord(e1, h->stream);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+        st = hip_fail(e, "autotune timing");
+        goto done;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      const double per = ms / steps_per_trial;
+      if (per < best_t) {
+        best_t = per;
+        best = t;
+      }
+    }
 done:
   // restore
   h->cur = cur0;
@@ -1119,7 +1182,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
       a.renorm_every = 1;
       a.ring = scratch;  // recompute records are not kept
       a.ring_cap = 1;
-      HIP_TRY(launch_step(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, true, launch_grid(h, a.n_items), a, h->stream));
+      HIP_TRY(launch_kernel(h, true, launch_grid(h, a.n_items), a, h->stream));
     }
     for (int i = len - 1; i >= 0; --i) {
       AdjArgs a;

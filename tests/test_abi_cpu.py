@@ -107,7 +107,9 @@ def test_tuning_validation_is_host_side():
             assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0, 1))
         assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
-                                                  "xcd_remap": 0, "depth": 1}
+                                                  "xcd_remap": 0, "depth": 1, "variant": 0}
+        # the LDS-tile variant needs full-width vectors
+        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(1, 1, 8, 0, 1, 1, 1))) == F.EINVAL
     finally:
         F.fdtd_destroy(h)
 
@@ -124,6 +126,11 @@ def test_tuning_rejects_too_many_sites_per_lane():
     h = F.fdtd_create(cfg(N=32, dtype=F.BF16))
     try:
         assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(8, 2, 8, 0, 1, 2))) == F.EINVAL
+        F.fdtd_set_tuning(h, F.fdtd_tuning(8, 1, 8, 0, 1, 1, 1))
+        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(8, 1, 8, 0, 1, 1, 2))) == F.EINVAL
+        big = F.fdtd_create(cfg(N=2200, L=2200.0, dtype=F.F32))
+        assert status_of("fdtd_set_tuning", big, C.byref(F.fdtd_tuning(4, 1, 8, 0, 1, 1, 1))) == F.EINVAL
+        F.fdtd_destroy(big)
         h64 = F.fdtd_create(cfg(N=32, dtype=F.F64))
         assert status_of("fdtd_set_tuning", h64, C.byref(F.fdtd_tuning(2, 4, 8, 0, 1, 2))) == F.EINVAL
         F.fdtd_destroy(h64)

@@ -144,7 +144,9 @@ def test_fp32_coulomb_even_and_odd_starts():
 
 @pytest.mark.parametrize("tuning", [(4, 1, 8, 0, 0, 1), (4, 2, 16, 0, 1, 2), (4, 2, 72, 0, 1, 3),
                                     (1, 1, 13, 0, 0, 1), (1, 4, 5, 37, 1, 1), (4, 2, 7, 64, 1, 3),
-                                    (4, 1, 0, 0, 1, 2), (4, 2, 11, 0, 0, 1)])
+                                    (4, 1, 0, 0, 1, 2), (4, 2, 11, 0, 0, 1),
+                                    (4, 1, 0, 0, 1, 1, 1), (4, 1, 7, 0, 1, 2, 1), (4, 1, 13, 3, 1, 3, 1),
+                                    (4, 1, 9, 0, 1, 3, 2), (1, 1, 10, 0, 1, 1, 2)])
 def test_fp32_state_is_independent_of_launch_shape(tuning):
     """Without renormalisation the update of a site does not depend on the
     tiling, so every launch shape yields the same bits."""
@@ -155,6 +157,26 @@ def test_fp32_state_is_independent_of_launch_shape(tuning):
     s, *_ = gpu_run(N, L, "f32", F.POT_WELLS, W.random_wells(np.random.default_rng(1)), 5, 25,
                     renorm=0, tuning=tuning)
     assert np.array_equal(s.state(), ref.state())
+
+
+@pytest.mark.parametrize("dtype,variant", [("f64", 1), ("f64", 2), ("bf16", 1), ("f32", 1)])
+def test_large_group_variants_against_oracle(dtype, variant):
+    """The LDS-tile and 512-lane variants of the fused step against the oracle
+    (N = 104: several chunks, ragged tail, halo rows crossing chunks)."""
+    say(f"case: variant {variant} {dtype}")
+    N, L, T = 104, 20.0, 200
+    vz = {"f64": 2, "f32": 4, "bf16": 8}[dtype]
+    tun = (vz, 1, 0, 0, 1, 1, variant)
+    s, *_ = gpu_run(N, L, dtype, F.POT_CORNELL, W.CORNELL_PARAMS, 5, T, tuning=tun,
+                    parity=W.parity_word(z=2))
+    psi_o, V, *_ = oracle_run(N, L, orc.POT_CORNELL, W.CORNELL_PARAMS, 5, T,
+                              parity=orc.parity_word(z=2))
+    e = orc.observables(psi_o, V, L)["energy"]
+    tol = {"f64": 1e-10, "f32": 1e-5, "bf16": 5e-3}[dtype]
+    assert s.observables()[0]["energy"] == pytest.approx(e, rel=tol)
+    v = s.state()
+    v = bf16_bits_to_f64(v) if dtype == "bf16" else v
+    assert np.array_equal(v[:, :, ::-1], -v)
 
 
 def test_graph_replay_equals_direct_launches():
