@@ -64,10 +64,9 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_floa
 // Round to nearest even; NaN stays a (quiet) NaN.  Acts on the magnitude
 // bits only, so it commutes with negation.
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(f);
+  const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40u) : rne);  // quiet NaN
 }
 
 template <typename S, typename C>
@@ -256,14 +255,22 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, c
 // E[round(v)] = v, so increments far below one BF16 ulp still move the state
 // on average instead of being rounded away.  Acts on the magnitude only, so
 // mirror sites given the same random bits round to exactly opposite values.
-__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t rnd) {
+// Branch-free: Inf keeps its all-zero low half, so adding r16 < 2^16 leaves
+// it Inf; a NaN magnitude is first replaced by the quiet NaN 0x7fc00000,
+// which the addition cannot carry out of the NaN range.
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16) {
   const uint32_t u = __float_as_uint(f);
-  const uint32_t mag = u & 0x7fffffffu;
-  if (mag >= 0x7f800000u) return f32_to_bf16(f);  // Inf / NaN
-  return (uint16_t)(((u & 0x80000000u) | (mag + (rnd & 0xffffu))) >> 16);
+  const uint32_t mag = min(u & 0x7fffffffu, 0x7fc00000u);
+  return (uint16_t)(((u & 0x80000000u) | (mag + r16)) >> 16);
 }
 
 // 32-bit integer hash (lowbias32, C. Wellons): random bits of the rounding.
+// On lattices of even side one hash serves two sites: a site with
+// mirror-canonical index k takes half k & 1 of the hash of k >> 1.  The
+// z-pair {2i, 2i+1} always shares k >> 1 (on one side of the centre the two
+// indices differ in the last bit only; a pair across the centre is one
+// canonical site).  A site's bits depend on its canonical (x, y, z) and the
+// step only, never on the launch shape; mirror sites share them.
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -272,6 +279,7 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
+__device__ __forceinline__ uint32_t half16(uint32_t h, bool hi) { return hi ? h >> 16 : h & 0xffffu; }
 
 // Last work-group of member m: record the step's sums, set the scale of the
 // next update, advance the step counter, flag non-finite sums, and re-arm
@@ -429,15 +437,45 @@ struct StepBody {
         lo = d.zm[r] * (C)ln.zmask_lo[r];
         hi = d.zp[r] * (C)ln.zmask_hi[r];
       }
+      uint32_t rb[VZ];  // 16 random bits per site (BF16 stores)
+      if constexpr (UPD && sizeof(S) == 2) {
+        if constexpr (VZ % 2 == 0) {  // N % VZ == 0, so N is even
+#pragma unroll
+          for (int j = 0; j < VZ; j += 2) {
+            const uint32_t k0 = kx + ln.key[r][j];  // the pair {j, j + 1} shares k0 >> 1
+            const uint32_t h = hash32((k0 >> 1) + k.smix);
+            rb[j] = half16(h, k0 & 1u);
+            rb[j + 1] = half16(h, ln.key[r][j + 1] & 1u);  // kx is even
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < VZ; ++j) {
+            const uint32_t k0 = kx + ln.key[r][j];
+            rb[j] = (k.N & 1) ? hash32(k0 + k.smix) & 0xffffu
+                              : half16(hash32((k0 >> 1) + k.smix), k0 & 1u);
+          }
+        }
+      }
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         const C p = pc[r][j];
         C lft = lo, rgt = hi;
         if (j > 0) lft = pc[r][j - 1];
         if (j < VZ - 1) rgt = pc[r][j + 1];
-        // a^2 * Laplacian from neighbour differences, mirror-symmetric pairs
-        const C lap = (((pm[r][j] - p) + (pn[r][j] - p)) + ((d.ym[r][j] - p) + (d.yp[r][j] - p))) +
-                      ((lft - p) + (rgt - p));
+        // a^2 * Laplacian, neighbours summed in mirror-symmetric pairs so a
+        // mirrored or negated state gives the mirrored or negated result bit
+        // for bit.  FP32/FP64 states: from neighbour differences (no
+        // cancellation against 6 p).  BF16 states: 8-bit significands, so the
+        // pair sums and the subtraction of 6 p are exact in FP32 whenever
+        // the seven values lie within a factor 2^12 of each other, and the
+        // plain sum equals the difference form with five fewer operations.
+        C lap;
+        if constexpr (sizeof(S) == 2) {
+          lap = __builtin_fmaf(-6.f, p, ((pm[r][j] + pn[r][j]) + (d.ym[r][j] + d.yp[r][j])) + (lft + rgt));
+        } else {
+          lap = (((pm[r][j] - p) + (pn[r][j] - p)) + ((d.ym[r][j] - p) + (d.yp[r][j] - p))) +
+                ((lft - p) + (rgt - p));
+        }
         const C p2 = p * p;
         s0 += p2;
         kin += p * lap;
@@ -447,7 +485,7 @@ struct StepBody {
           const C B = rcp_c(C(1) + k.eps * vv[r][j]);
           const C nv = k.sc * (p + B * (k.c * lap - k.dt * vv[r][j] * p));
           if constexpr (sizeof(S) == 2) {
-            o.v[j] = f32_to_bf16_sr((float)nv, hash32(kx + ln.key[r][j] + k.smix));
+            o.v[j] = f32_to_bf16_sr((float)nv, rb[j]);
           } else {
             o.v[j] = (S)nv;
           }

@@ -199,7 +199,7 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   h->tun.xchunk = 0;  // automatic: see auto_xchunk
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;
-  h->tun.depth = (h->dtype == kBF16 && h->tun.vz > 1) ? 2 : 1;
+  h->tun.depth = 1;
   h->tun.variant = 0;
   *out = h;
   return FDTD_OK;

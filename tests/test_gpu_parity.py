@@ -159,6 +159,35 @@ def test_fp32_state_is_independent_of_launch_shape(tuning):
     assert np.array_equal(s.state(), ref.state())
 
 
+@pytest.mark.parametrize("N,tunings", [
+    (40, [(8, 1, 0, 0, 1, 2), (8, 1, 5, 0, 0, 1), (8, 1, 3, 0, 1, 3), (1, 4, 9, 0, 1, 1),
+          (1, 1, 0, 0, 1, 1), (8, 1, 0, 0, 1, 1, 1), (1, 1, 7, 0, 1, 1, 2)]),
+    (42, [(1, 1, 0, 0, 1, 1), (1, 4, 0, 0, 1, 1), (1, 2, 3, 0, 0, 1)]),
+    (45, [(1, 1, 0, 0, 1, 1), (1, 2, 4, 0, 1, 1), (1, 4, 0, 11, 0, 1)])])
+def test_bf16_state_is_independent_of_launch_shape_and_keeps_parity(N, tunings):
+    """The stochastic rounding of a BF16 store draws its bits from the site's
+    mirror-canonical index and the step only: without renormalisation (whose
+    FP64 sums are grouped by the tiling) every launch shape stores the same
+    bits, and an odd start stays odd bit for bit.  N = 42 puts a z-pair of
+    the shared hash across the centre; N = 45 takes one hash per site."""
+    say(f"case: bf16 tiling N={N}")
+    L = 12.0
+    par = W.parity_word(z=2, y=1)
+    # odd N puts a site at r = 0, where the Cornell potential is infinite
+    kind, params = (F.POT_CORNELL, W.CORNELL_PARAMS) if N % 2 == 0 else (F.POT_HO, [1, 1.2, 0.8])
+    states = []
+    for t in tunings:
+        s, *_ = gpu_run(N, L, "bf16", kind, params, 9, 40, tuning=t, parity=par, renorm=0)
+        states.append(s.state())
+        s.close()
+    v = bf16_bits_to_f64(states[0])
+    assert np.abs(v).max() > 0
+    assert np.array_equal(v[:, :, ::-1], -v)
+    assert np.array_equal(v[:, ::-1, :], v)
+    for t, st in zip(tunings[1:], states[1:]):
+        assert np.array_equal(st, states[0]), t
+
+
 @pytest.mark.parametrize("dtype,variant", [("f64", 1), ("f64", 2), ("bf16", 1), ("f32", 1)])
 def test_large_group_variants_against_oracle(dtype, variant):
     """The LDS-tile and 512-lane variants of the fused step against the oracle
