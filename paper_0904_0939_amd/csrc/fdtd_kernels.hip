@@ -265,12 +265,16 @@ __device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16) {
 }
 
 // 32-bit integer hash (lowbias32, C. Wellons): random bits of the rounding.
-// On lattices of even side one hash serves two sites: a site with
-// mirror-canonical index k takes half k & 1 of the hash of k >> 1.  The
-// z-pair {2i, 2i+1} always shares k >> 1 (on one side of the centre the two
-// indices differ in the last bit only; a pair across the centre is one
-// canonical site).  A site's bits depend on its canonical (x, y, z) and the
-// step only, never on the launch shape; mirror sites share them.
+// The 32 bits of a site are hash32(q ^ kSaltYZ) ^ hash32(cx + hash32(step)),
+// with cx = min(x, N - 1 - x) and q its mirror-canonical (y, z) index k
+// (odd N) or k >> 1 (even N).  The first factor is fixed per lane for a whole
+// work item, the second is uniform over the work-group (scalar unit), so a
+// site costs one XOR.  On even N one 32-bit draw serves two sites: the site
+// takes half k & 1; the z-pair {2i, 2i+1} always shares k >> 1 (on one side
+// of the centre the two indices differ in the last bit only; a pair across
+// the centre is one canonical site).  The bits depend on the canonical
+// (x, y, z) and the step only, never on the launch shape, and mirror sites
+// share them.
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -279,7 +283,7 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
-__device__ __forceinline__ uint32_t half16(uint32_t h, bool hi) { return hi ? h >> 16 : h & 0xffffu; }
+constexpr uint32_t kSaltYZ = 0x68e31da4u;
 
 // Last work-group of member m: record the step's sums, set the scale of the
 // next update, advance the step counter, flag non-finite sums, and re-arm
@@ -342,7 +346,8 @@ struct Lane {
   float zmask_lo[RY];     // 0 where the vector starts at z = 0 (its z - 1 is a ghost)
   float zmask_hi[RY];     // 0 where the vector ends at z = N - 1
   C w2[RY][VZ];           // y^2 + z^2 of each site
-  uint32_t key[RY][VZ];   // mirror-canonical (y, z) index for the rounding hash
+  uint32_t hk[RY][VZ > 1 ? VZ / 2 : 1];  // (y, z) part of the rounding bits (BF16)
+  uint32_t hsh[RY][VZ];   // which half of the 32 bits a site takes: 0 or 16
 };
 
 // Data of one plane that the update of that plane needs besides the planes
@@ -371,8 +376,23 @@ struct StepBody {
     int xe;  // end of the work item: planes the item never reads get empty resources
     C c, dt, eps, sc;
     double ha, cN;
-    uint32_t smix, kN;
+    uint32_t smix;  // hash32(step): the step's part of the rounding bits
   };
+
+  // The (y, z) part of the rounding bits of vector r (BF16 stores only),
+  // from the mirror-canonical (y, z) index of each of its sites.
+  static __device__ __forceinline__ void hash_lane(Lane<RY, VZ, C>& ln, int r, int N,
+                                                   const uint32_t (&key)[VZ]) {
+    if constexpr (sizeof(S) == 2) {
+#pragma unroll
+      for (int j = 0; j < VZ; j += 2) {
+        const uint32_t q = (N & 1) ? key[j] : key[j] >> 1;
+        ln.hk[r][j / 2] = hash32(q ^ kSaltYZ);
+      }
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) ln.hsh[r][j] = (N & 1) ? 0u : (key[j] & 1u) << 4;
+    }
+  }
 
   // Issue the loads of the y and z neighbours of plane x (needed for x < xe).
   static __device__ __forceinline__ void fetch(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
@@ -418,7 +438,7 @@ struct StepBody {
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
     const __amdgpu_buffer_rsrc_t ro = plane_rsrc(k.out, x, k.N, k.pbytes);
-    const uint32_t kx = (uint32_t)min(x, k.N - 1 - x) * k.kN;
+    const uint32_t hx = hash32((uint32_t)min(x, k.N - 1 - x) + k.smix);  // uniform
     C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
     const int lane = __lane_id();
 #pragma unroll
@@ -439,21 +459,10 @@ struct StepBody {
       }
       uint32_t rb[VZ];  // 16 random bits per site (BF16 stores)
       if constexpr (UPD && sizeof(S) == 2) {
-        if constexpr (VZ % 2 == 0) {  // N % VZ == 0, so N is even
 #pragma unroll
-          for (int j = 0; j < VZ; j += 2) {
-            const uint32_t k0 = kx + ln.key[r][j];  // the pair {j, j + 1} shares k0 >> 1
-            const uint32_t h = hash32((k0 >> 1) + k.smix);
-            rb[j] = half16(h, k0 & 1u);
-            rb[j + 1] = half16(h, ln.key[r][j + 1] & 1u);  // kx is even
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < VZ; ++j) {
-            const uint32_t k0 = kx + ln.key[r][j];
-            rb[j] = (k.N & 1) ? hash32(k0 + k.smix) & 0xffffu
-                              : half16(hash32((k0 >> 1) + k.smix), k0 & 1u);
-          }
+        for (int j = 0; j < VZ; ++j) {
+          const uint32_t h = ln.hk[r][j / 2] ^ hx;  // the pair {2i, 2i+1} shares h
+          rb[j] = __builtin_amdgcn_ubfe(h, ln.hsh[r][j], 16);
         }
       }
 #pragma unroll
@@ -551,7 +560,7 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
     const C dt = (C)M.dt;
     const C eps = (C)(0.5 * M.dt);
     const C sc = (C)A.states[m].scale;
-    const uint32_t smix = (uint32_t)A.states[m].step * 0x9E3779B9u;
+    const uint32_t smix = hash32((uint32_t)A.states[m].step);
     const double ha = M.ha;
     const double cN = (double)(N - 1);
 
@@ -579,15 +588,16 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
       ln.zmask_hi[r] = (ok && z0 + VZ < N) ? 1.f : 0.f;
       const double yc = (2.0 * y - cN) * ha;
       const int cy = min(y, N - 1 - y);
+      uint32_t key[VZ];  // mirror-canonical (y, z) index
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         const double zc = (2.0 * (z0 + j) - cN) * ha;
         ln.w2[r][j] = (C)(yc * yc + zc * zc);
         const int z = z0 + j;
-        ln.key[r][j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
+        key[j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
       }
+      Body::hash_lane(ln, r, N, key);
     }
-    const uint32_t kN = (uint32_t)N * (uint32_t)N;
 
     typename Body::Ctx k;
     k.in = in;
@@ -603,7 +613,6 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
     k.ha = ha;
     k.cN = cN;
     k.smix = smix;
-    k.kN = kN;
     k.xe = item.xe;
 
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -783,8 +792,7 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
     k.sc = (C)A.states[m].scale;
     k.ha = M.ha;
     k.cN = (double)(N - 1);
-    k.smix = (uint32_t)A.states[m].step * 0x9E3779B9u;
-    k.kN = (uint32_t)N * (uint32_t)N;
+    k.smix = hash32((uint32_t)A.states[m].step);
     k.xe = item.xe;
 
     // own vector
@@ -803,13 +811,15 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
       ln.zmask_hi[0] = (ok && z0 + VZ < N) ? 1.f : 0.f;
       const double yc = (2.0 * y - k.cN) * k.ha;
       const int cy = min(y, N - 1 - y);
+      uint32_t key[VZ];  // mirror-canonical (y, z) index
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         const double zc = (2.0 * (z0 + j) - k.cN) * k.ha;
         ln.w2[0][j] = (C)(yc * yc + zc * zc);
         const int z = z0 + j;
-        ln.key[0][j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
+        key[j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
       }
+      Body::hash_lane(ln, 0, N, key);
     }
     const unsigned rel = (unsigned)tid * VZ + (unsigned)N;  // own vector in the tile
     // halo: lanes below 2N/VZ fetch one vector of the row above / below the chunk
