@@ -256,11 +256,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
+    # evolve() replays 64-step HIP graphs; a warm-up of at least 64 steps
+    # captures the graph outside the timed region
+    ap.add_argument("--warmup", type=int, default=64)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tuning", default="", help="vz,ry,xchunk,grid,xcd_remap,depth")

@@ -121,8 +121,10 @@ typedef struct {
  *  vz     sites per lane along z, 1 or the dtype's vector width (F64 2,
  *         F32 4, BF16 8; requires N % vz == 0);
  *  ry     vectors per lane per plane (1, 2 or 4); vz * ry <= 8 (<= 4 for F64);
- *  xchunk planes streamed per work item (>= 1; 0: the longest stream that
- *         still gives every CU a work item);
+ *  xchunk at most this many planes streamed per work item: a lattice's N
+ *         planes split into ceil(N / xchunk) near-equal x-ranges (>= 1; 0:
+ *         the longest stream that still gives every CU a work item); on a
+ *         batch, work items run longest first;
  *  grid   work-groups launched (0: one per work item);
  *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles;
  *  depth  planes of HBM prefetch ahead of the plane being updated (1..3;

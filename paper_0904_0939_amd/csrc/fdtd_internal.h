@@ -49,12 +49,14 @@ struct MemberState {
 };
 
 // One work item: a chunk of a member's flattened (y, z) plane, for planes
-// x in [xb, xe).
+// x in [xb, xe).  slot: where the item's partial sums go; a member's slots
+// are [item_begin, item_end), whatever order the items are processed in.
 struct Item {
   int member;
   int f0;
   int xb;
   int xe;
+  int slot;
 };
 
 struct StepArgs {
@@ -66,7 +68,7 @@ struct StepArgs {
   int src;              // input buffer index (0 / 1); the output is src ^ 1
   int renorm_every;     // > 0: rescale after every k-th step
   int set_scale;        // observe mode: set scale = 1 / sqrt(a^3 S0)
-  double* partials;     // n_items * kRec
+  double* partials;     // kRec doubles per item slot
   double* ring;         // history: n_members * ring_cap * kRec
   int ring_cap;
   double* obs_out;      // observe mode: n_members * kRec

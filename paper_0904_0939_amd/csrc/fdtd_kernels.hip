@@ -546,8 +546,7 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
   const int tid = threadIdx.x;
 
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
-    const int it = A.item_offset + li;  // position of the item: also its partial slot
-    const Item item = A.items[it];
+    const Item item = A.items[A.item_offset + li];
     const int m = item.member;
     const MemberDev& M = A.members[m];
     const int N = M.N;
@@ -647,7 +646,7 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
     // ---- per-item partials, then the last work-group of the member sums them
     block_sum<5, BT / 64>(acc, s_red);
     if (tid == 0) {
-      double* part = A.partials + (long long)it * kRec;
+      double* part = A.partials + (long long)item.slot * kRec;
 #pragma unroll
       for (int k = 0; k < 5; ++k) part[k] = acc[k];
       __threadfence();
@@ -771,6 +770,7 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
     item.f0 = uni(item0.f0);
     item.xb = uni(item0.xb);
     item.xe = uni(item0.xe);
+    item.slot = uni(item0.slot);
     const int m = item.member;
     const MemberDev& M = A.members[m];
     const int N = uni(M.N);
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
 
     block_sum<5, kTB / 64>(acc, s_red);
     if (tid == 0) {
-      double* part = A.partials + (long long)it * kRec;
+      double* part = A.partials + (long long)item.slot * kRec;
 #pragma unroll
       for (int kk = 0; kk < 5; ++kk) part[kk] = acc[kk];
       __threadfence();

@@ -86,8 +86,12 @@ struct fdtd_ctx {
   size_t off_members = 0, off_states = 0, off_ring = 0, off_obs = 0, off_params = 0;
   size_t need_bytes = 0;
 
-  // work items (library-allocated, depend on the tuning)
+  // work items (library-allocated, depend on the tuning): d_items in member
+  // order (a member's items at [item_begin, item_end), for per-member
+  // launches), d_order the same items in the order whole-batch launches
+  // process them; both live in one allocation of 2 * items_cap
   Item* d_items = nullptr;
+  Item* d_order = nullptr;
   double* d_partials = nullptr;
   int n_items = 0;
   int items_cap = 0;
@@ -278,18 +282,20 @@ long long chunk_sites(const fdtd_ctx* h, const fdtd_tuning& t) {
   return (long long)(t.variant == 2 ? 512 : kBlock) * t.vz * t.ry;
 }
 
+// Near-equal split of a member's N planes into ceil(N / xc) x-ranges.
+int x_parts(int N, int xc) { return (N + std::max(1, std::min(xc, N)) - 1) / std::max(1, std::min(xc, N)); }
+int x_bound(int N, int nx, int b) { return (int)(((long long)b * N) / nx); }
+
 // Longest x-stream (fewest re-read halo planes, least per-item start-up)
-// that still gives each of the 256 CUs a work item (measured at 512^3: one
-// long-streaming work-group per CU beats more, shorter ones).
+// that still gives each of the 256 CUs a work item.  Measured: at 512^3 one
+// long-streaming work-group per CU beats more, shorter ones; on the batch of
+// 64 lattices of side 48..160, whole-N items handed out longest first beat
+// every shorter split (item start-up outweighs the better balance).
 int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
+  const long long F = chunk_sites(h, t);
   for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;
-    for (const auto& m : h->mem) {
-      const long long P = (long long)m.N * m.N;
-      const long long F = chunk_sites(h, t);
-      const int x = std::min(xc, m.N);
-      items += ((P + F - 1) / F) * ((m.N + x - 1) / x);
-    }
+    for (const auto& m : h->mem) items += (((long long)m.N * m.N + F - 1) / F) * x_parts(m.N, xc);
     if (items >= 256) return xc;
   }
   return 8;
@@ -305,24 +311,25 @@ fdtd_status build_items(fdtd_ctx* h) {
     const long long P = (long long)m.N * m.N;
     const long long F = chunk_sites(h, t);
     const int nchunk = (int)((P + F - 1) / F);
-    const int xc = std::max(1, std::min(t.xchunk, m.N));
-    const int nx = (m.N + xc - 1) / xc;
+    const int nx = x_parts(m.N, t.xchunk);
     m.item_begin = (int)phys.size();
     for (int bx = 0; bx < nx; ++bx)
       for (int ch = 0; ch < nchunk; ++ch) {
         Item it;
         it.member = i;
         it.f0 = (int)(ch * F);
-        it.xb = bx * xc;
-        it.xe = std::min(m.N, (bx + 1) * xc);
+        it.xb = x_bound(m.N, nx, bx);
+        it.xe = x_bound(m.N, nx, bx + 1);
+        it.slot = (int)phys.size();
         phys.push_back(it);
       }
     m.item_end = (int)phys.size();
   }
   const int n = (int)phys.size();
-  // Processing order: within each member (items stay member-contiguous, so a
-  // member's partial slots are its position range), optionally permuted so
-  // that the work-groups one XCD runs take neighbouring tiles.
+  // Processing order: each member's items optionally permuted so that the
+  // work-groups one XCD runs take neighbouring tiles; on a batch, longest
+  // items first (stable, so the permutation survives among equal lengths),
+  // which keeps the slots busy to the end of the launch.
   std::vector<Item> order;
   order.reserve(n);
   for (int i = 0; i < h->count; ++i) {
@@ -336,13 +343,17 @@ fdtd_status build_items(fdtd_ctx* h) {
     }
     for (int b = 0; b < cnt; ++b) order.push_back(phys[m.item_begin + p[b]]);
   }
+  if (h->count > 1)
+    std::stable_sort(order.begin(), order.end(),
+                     [](const Item& a, const Item& b) { return a.xe - a.xb > b.xe - b.xb; });
   if (n > h->items_cap) {
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_partials) (void)hipFree(h->d_partials);
     h->d_items = nullptr;
+    h->d_order = nullptr;
     h->d_partials = nullptr;
     h->items_cap = 0;
-    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * n);
+    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * 2 * (size_t)n);
     hipError_t e2 = hipMalloc((void**)&h->d_partials, sizeof(double) * kRec * n);
     if (e1 != hipSuccess || e2 != hipSuccess) {
       (void)hipGetLastError();
@@ -350,7 +361,9 @@ fdtd_status build_items(fdtd_ctx* h) {
     }
     h->items_cap = n;
   }
-  HIP_TRY(hipMemcpyAsync(h->d_items, order.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
+  h->d_order = h->d_items + h->items_cap;
+  HIP_TRY(hipMemcpyAsync(h->d_items, phys.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->d_order, order.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->n_items = n;
   ST_TRY(upload_members(h));
@@ -384,7 +397,7 @@ StepArgs base_args(fdtd_ctx* h) {
   memset(&a, 0, sizeof a);
   a.members = h->d_members();
   a.states = h->d_states();
-  a.items = h->d_items;
+  a.items = h->d_order;
   a.n_items = h->n_items;
   a.item_offset = 0;
   a.src = h->cur;
@@ -402,6 +415,7 @@ fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
   StepArgs a = base_args(h);
   a.set_scale = set_scale ? 1 : 0;
   if (member >= 0) {
+    a.items = h->d_items;
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
   }
@@ -812,6 +826,7 @@ fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int
   // norm of the stored state from a reduction pass
   {
     StepArgs a = base_args(h);
+    a.items = h->d_items;
     a.item_offset = h->mem[member].item_begin;
     a.n_items = h->mem[member].item_end - h->mem[member].item_begin;
     // the reduction needs V only for the energy sums; it is harmless if unset
@@ -979,50 +994,20 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   bool all_div = true;
   for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
   if (all_div) vzs.push_back(vw);
-  for (int vz : vzs)
-    for (int ry : {1, 2, 4})
-      for (int xc : {0, 32, 64, 128, 256})
-        for (int depth : {1, 2, 3})
-          for (int variant : {0, 2}) {
-          const int remap = 1;
-          if (xc > maxN || (vz == 1 && depth > 1)) continue;
-          fdtd_tuning t{vz, ry, xc, 0, remap, depth, variant};
-          if (validate_tuning(h, t) != FDTD_OK) continue;
-          h->tun = t;
-          h->items_valid = false;
-          if ((st = build_items(h)) != FDTD_OK) goto done;
-          if ((st = launch_steps(h, 1, 1, h->stream)) != FDTD_OK) goto done;  // warm-up
-          (void)hipEventRecord(e0, h->stream);
-          if ((st = launch_steps(h, steps_per_trial, 1, h->stream)) != FDTD_OK) goto done;
-          (void)hipEventRecord(e1, h->stream);
-          if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-            st = hip_fail(e, "autotune timing");
-            goto done;
-          }
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          const double per = ms / steps_per_trial;
-          if (per < best_t) {
-            best_t = per;
-            best = t;
-          }
-        }
-  // LDS-tile variant
-  for (int xc : {0, 64, 128, 256})
-    for (int depth : {1, 2, 3}) {
-      if (xc > maxN) continue;
-      fdtd_tuning t{vw, 1, xc, 0, 1, depth, 1};
-      if (!all_div || validate_tuning(h, t) != FDTD_OK) continue;
+  {
+    // time one candidate; false stops the search (st holds the error)
+    auto trial = [&](const fdtd_tuning& t) -> bool {
+      if (validate_tuning(h, t) != FDTD_OK) return true;
       h->tun = t;
       h->items_valid = false;
-      if ((st = build_items(h)) != FDTD_OK) goto done;
-      if ((st = launch_steps(h, 1, 1, h->stream)) != FDTD_OK) goto done;
+      if ((st = build_items(h)) != FDTD_OK) return false;
+      if ((st = launch_steps(h, 1, 1, h->stream)) != FDTD_OK) return false;  // warm-up
       (void)hipEventRecord(e0, h->stream);
-      if ((st = launch_steps(h, steps_per_trial, 1, h->stream)) != FDTD_OK) goto done;
+      if ((st = launch_steps(h, steps_per_trial, 1, h->stream)) != FDTD_OK) return false;
       (void)hipEventRecord(e1, h->stream);
       if ((e = hipEventSynchronize(e1)) != hipSuccess) {
         st = hip_fail(e, "autotune timing");
-        goto done;
+        return false;
       }
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, e0, e1);
@@ -1031,8 +1016,24 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
         best_t = per;
         best = t;
       }
-    }
-done:
+      return true;
+    };
+    bool go = true;
+    for (int vz : vzs)
+      for (int ry : {1, 2, 4})
+        for (int xc : {0, 32, 64, 128, 256})
+          for (int depth : {1, 2, 3})
+            for (int variant : {0, 2}) {
+              if (!go || xc > maxN || (vz == 1 && depth > 1)) continue;
+              go = trial(fdtd_tuning{vz, ry, xc, 0, 1, depth, variant});
+            }
+    // LDS-tile variant
+    for (int xc : {0, 64, 128, 256})
+      for (int depth : {1, 2, 3}) {
+        if (!go || xc > maxN || !all_div) continue;
+        go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 1});
+      }
+  }
   // restore
   h->cur = cur0;
   off = 0;
