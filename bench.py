@@ -221,7 +221,7 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000
     }
 
 
-def batch64(steps=400, warmup=40, autotune=True):
+def batch64(steps=400, warmup=64, autotune=True):
     """64 random oscillator-plus-wells potentials on lattices of side 48..160,
     FP32, one launch per step over every member, graph-captured."""
     import torch
