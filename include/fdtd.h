@@ -237,10 +237,12 @@ fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,
 fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out);
 fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
 
-/* Time every valid launch shape of the step kernel on this handle (its state
- * is saved and restored) with HIP events, keep the fastest, and cache it per
- * (device, dtype, lattice sizes) for later handles of this process.
- * chosen (optional) receives it; best_ms (optional) its time per step. */
+/* Time every valid launch shape of the step kernel on this handle with HIP
+ * events, keep the fastest, and cache it per (device, dtype, lattice sizes)
+ * for later handles of this process.  The state, step counters and history
+ * are saved first and restored after (the trials step the lattice).  A shape
+ * found in the cache is set without timing; best_ms then receives -1.
+ * chosen (optional) receives the shape; best_ms (optional) its time per step. */
 fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen,
                           double* best_ms);
 

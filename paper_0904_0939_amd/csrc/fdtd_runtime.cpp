@@ -962,11 +962,13 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
       return FDTD_OK;
     }
   }
-  // save the state: both buffers, the member states
+  // save what the trial steps overwrite: the current field of every member,
+  // the member states and the history ring
   size_t field_bytes = 0;
   for (auto& m : h->mem) field_bytes += elem_size(h->dtype) * (size_t)m.n3;
+  const size_t ring_bytes = sizeof(double) * kRec * (size_t)h->ring_cap * h->count;
   char* save = nullptr;
-  hipError_t e = hipMalloc((void**)&save, field_bytes + sizeof(MemberState) * h->count);
+  hipError_t e = hipMalloc((void**)&save, field_bytes + sizeof(MemberState) * h->count + ring_bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(FDTD_ENOMEM, "autotune: no memory to save the state");
@@ -979,6 +981,8 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     off += b;
   }
   (void)hipMemcpyAsync(save + off, h->d_states(), sizeof(MemberState) * h->count, hipMemcpyDeviceToDevice, h->stream);
+  (void)hipMemcpyAsync(save + off + sizeof(MemberState) * h->count, h->d_ring(), ring_bytes,
+                       hipMemcpyDeviceToDevice, h->stream);
 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
@@ -1043,6 +1047,8 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     off += b;
   }
   (void)hipMemcpyAsync(h->d_states(), save + off, sizeof(MemberState) * h->count, hipMemcpyDeviceToDevice, h->stream);
+  (void)hipMemcpyAsync(h->d_ring(), save + off + sizeof(MemberState) * h->count, ring_bytes,
+                       hipMemcpyDeviceToDevice, h->stream);
   (void)hipStreamSynchronize(h->stream);
   (void)hipFree(save);
   (void)hipEventDestroy(e0);

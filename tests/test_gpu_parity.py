@@ -331,9 +331,9 @@ def test_batch_of_uneven_lattices_fp64():
 
 
 def test_batch_fp32_matches_single_lattice_runs_bitwise():
-    """Members of a batch step exactly as they would alone (renorm off): the
-    single runs start from the oracle's copy of the member's noise, which the
-    GPU generator reproduces bit for bit."""
+    """Members of a batch step exactly as they would alone (renorm off).  The
+    batch's noise is the oracle's, member by member, bit for bit (FP32
+    storage); each single run starts from a copy of its member's GPU start."""
     say("case: batch fp32 vs singles")
     rng = np.random.default_rng(5)
     lats = [W.Lattice(N, 12.0, W.POT_WELLS, W.random_wells(rng), seed=4) for N in (48, 64, 96, 32)]
@@ -341,12 +341,15 @@ def test_batch_fp32_matches_single_lattice_runs_bitwise():
     for m, l in enumerate(lats):
         b.set_potential(l.pot_kind, l.pot_params, member=m)
     b.set_initial(4)
+    starts = [b.state(m) for m in range(len(lats))]
+    for m, l in enumerate(lats):
+        assert np.array_equal(starts[m], orc.initial(l.N, 4, member=m).astype(np.float32)), m
     b.evolve(40, renorm_every=0)
     obs = b.observables()
     for m, l in enumerate(lats):
         s = Solver(l.N, l.L, dtype="f32")
         s.set_potential(l.pot_kind, l.pot_params)
-        s.set_initial_array(orc.initial(l.N, 4, member=m))
+        s.set_initial_array(starts[m])
         s.evolve(40, renorm_every=0)
         assert np.array_equal(s.state(), b.state(m)), m
         V = orc.potential(orc.POT_WELLS, l.pot_params, l.N, l.L)
