@@ -126,56 +126,57 @@ def _timer():
     return time.perf_counter()
 
 
-def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000):
-    """Wall time to reach the ground-state energy to 1e-6 relative on the
-    Cornell lattice at 512^3 (L = 30, dt = a^2/8): the plain FP64 path from
-    noise on 512^3, against the multi-resolution chain (BF16 128^3 -> BF16
-    256^3 -> FP32 512^3, trilinear reseeding, graph-captured steps).  The
-    reference E* is the plain FP64 run carried on to a change below 1e-12 per
-    100 steps, then Aitken-extrapolated."""
+def plain_fp64_to_e(N=512, max_s=75.0):
+    """The plain FP64 path on the Cornell lattice from noise, checked every 100
+    steps, carried on to a change below 1e-12 per 100 steps.  Returns the
+    (seconds since start, steps, energy) rows and E*, Aitken-extrapolated from
+    the last three checks."""
     from paper_0904_0939_amd import fdtd as F
     from paper_0904_0939_amd import workloads as W
     from paper_0904_0939_amd.solver import Solver
 
-    Nf = N_levels[-1]
-    lat = W.cornell(Nf)
+    lat = W.cornell(N)
     K = 100
-    # ---- plain FP64 from noise
-    s = Solver(Nf, lat.L, dtype="f64")
+    s = Solver(N, lat.L, dtype="f64")
     s.set_potential(F.POT_CORNELL, lat.pot_params)
     t0 = _timer()
     s.set_initial(lat.seed)
-    plain = []  # (seconds since start, steps, energy)
+    rows = []
     steps = 0
     e_prev = None
     while True:
         s.evolve(K, check_every=0, use_graph=True)
         steps += K
         e = s.history(0, 1)[0]["energy"]
-        plain.append((time.perf_counter() - t0, steps, e))
+        rows.append((time.perf_counter() - t0, steps, e))
         if e_prev is not None and abs(e - e_prev) <= 1e-12 * abs(e):
             break
-        if time.perf_counter() - t0 > max_plain_s:
+        if time.perf_counter() - t0 > max_s:
             break
         e_prev = e
-    E = [p[2] for p in plain[-3:]]
+    E = [p[2] for p in rows[-3:]]
     den = E[2] - 2 * E[1] + E[0]
     e_star = E[2] - (E[2] - E[1]) ** 2 / den if den != 0 else E[2]
     s.close()
+    return rows, e_star
 
-    def first_within(rows, tol):
-        for t, n, e in rows:
-            if abs(e - e_star) <= tol * abs(e_star):
-                return t, n
-        return None, None
 
-    t_plain, n_plain = first_within(plain, 1e-6)
-    # ---- multi-resolution chain
+def multires_to_e(e_star, N_levels=(128, 256, 512), coarse_tol=1e-5, coarse_max_steps=20000,
+                  max_s=75.0):
+    """The multi-resolution chain on the Cornell lattice: BF16 storage on the
+    coarse levels, each relaxed until E changes by less than coarse_tol
+    relative per 100 steps, trilinear reseeding, FP32 on the finest level, run
+    until E is within 1e-6 of e_star.  Returns the finest level's rows and a
+    per-level log."""
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    K = 100
     dtypes = ["bf16"] * (len(N_levels) - 1) + ["f32"]
-    tols = [1e-5] * (len(N_levels) - 1)
     t0 = _timer()
     prev = None
-    multi = []
+    rows = []
     level_log = []
     for i, N in enumerate(N_levels):
         lv = W.cornell(N)
@@ -188,42 +189,61 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000
             prev.close()
         n = 0
         if i < len(N_levels) - 1:
-            done, conv = cur.evolve(coarse_max_steps, check_every=K, rel_tol=tols[i],
-                                    use_graph=True)
-            n = done
+            n, _ = cur.evolve(coarse_max_steps, check_every=K, rel_tol=coarse_tol, use_graph=True)
         else:
-            e_prev = None
             while True:
                 cur.evolve(K, check_every=0, use_graph=True)
                 n += K
                 e = cur.history(0, 1)[0]["energy"]
-                multi.append((time.perf_counter() - t0, n, e))
-                if abs(e - e_star) <= 1e-6 * abs(e_star) and len(multi) > 1:
+                rows.append((time.perf_counter() - t0, n, e))
+                if abs(e - e_star) <= 1e-6 * abs(e_star) and len(rows) > 1:
                     break
-                if time.perf_counter() - t0 > max_plain_s:
+                if time.perf_counter() - t0 > max_s:
                     break
         level_log.append({"N": N, "dtype": dtypes[i], "steps": n,
                           "energy": cur.history(0, 1)[0]["energy"],
                           "seconds_since_start": round(time.perf_counter() - t0, 3)})
         prev = cur
-    t_multi, n_multi = first_within(multi, 1e-6)
-    final_e = multi[-1][2] if multi else None
     prev.close()
+    return rows, level_log
+
+
+def _first_within(rows, e_star, tol):
+    for t, n, e in rows:
+        if abs(e - e_star) <= tol * abs(e_star):
+            return t, n
+    return None, None
+
+
+def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000, coarse_tol=1e-5):
+    """Wall time to reach the ground-state energy to 1e-6 relative on the
+    Cornell lattice at 512^3 (L = 30, dt = a^2/8): the plain FP64 path from
+    noise on 512^3, against the multi-resolution chain (BF16 128^3 -> BF16
+    256^3 -> FP32 512^3, trilinear reseeding, graph-captured steps).  The
+    reference E* is the plain FP64 run carried on to a change below 1e-12 per
+    100 steps, then Aitken-extrapolated."""
+    plain, e_star = plain_fp64_to_e(N_levels[-1], max_plain_s)
+    t_plain, n_plain = _first_within(plain, e_star, 1e-6)
+    multi, level_log = multires_to_e(e_star, N_levels, coarse_tol, coarse_max_steps, max_plain_s)
+    t_multi, n_multi = _first_within(multi, e_star, 1e-6)
     return {
         "workload": f"cornell_L30_{'->'.join(str(n) for n in N_levels)}",
         "e_star": e_star,
         "plain_fp64_seconds": t_plain, "plain_fp64_steps": n_plain,
         "plain_fp64_steps_to_1e-12": plain[-1][1],
+        "coarse_tol_per_100_steps": coarse_tol,
         "multires_seconds": t_multi, "multires_final_level_steps": n_multi,
         "multires_levels": level_log,
-        "multires_final_energy": final_e,
+        "multires_final_energy": multi[-1][2] if multi else None,
         "speedup": (t_plain / t_multi) if (t_plain and t_multi) else None,
     }
 
 
-def batch64(steps=400, warmup=64, autotune=True):
+def batch64(loop=4000, autotune=True):
     """64 random oscillator-plus-wells potentials on lattices of side 48..160,
-    FP32, one launch per step over every member, graph-captured."""
+    FP32, one launch per step over every member, the step loop captured as
+    one HIP graph of `loop` launches (warm-up: one untimed loop, which also
+    captures the graph), then one timed loop."""
     import torch
 
     from paper_0904_0939_amd import workloads as W
@@ -235,19 +255,22 @@ def batch64(steps=400, warmup=64, autotune=True):
         b.set_potential(l.pot_kind, l.pot_params, member=m)
     b.set_initial(lats[0].seed)
     tun = b.autotune(10)[0] if autotune else b.tuning()
-    b.evolve(warmup, check_every=0, use_graph=True)
+    # check_every = loop: evolve() captures `loop` steps as one graph; with
+    # rel_tol 0 the one check at the end never stops the run
+    b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    b.evolve(steps, check_every=0, use_graph=True)
-    e1.record()
+    e0.record(stream)
+    b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
+    e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms = e0.elapsed_time(e1) / loop
     sites = sum(l.sites for l in lats)
     obs = b.observables()
     b.close()
     return {"workload": "wells_batch64_f32", "members": len(lats), "sites": sites,
-            "ms_per_step": ms, "site_updates_per_s": sites / (ms * 1e-3),
+            "graph_steps": loop, "ms_per_step": ms, "site_updates_per_s": sites / (ms * 1e-3),
             "achieved_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": tun,
             "energy_range": [min(o["energy"] for o in obs), max(o["energy"] for o in obs)]}
 
