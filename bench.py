@@ -241,9 +241,10 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_max_steps=20000
 
 def batch64(loop=4000, autotune=True):
     """64 random oscillator-plus-wells potentials on lattices of side 48..160,
-    FP32, one launch per step over every member, the step loop captured as
-    one HIP graph of `loop` launches (warm-up: one untimed loop, which also
-    captures the graph), then one timed loop."""
+    FP32, the autotuned shape; with a persistent shape the `loop` steps of
+    every member run as one persistent launch, captured as one HIP graph
+    (warm-up: one untimed loop, which also captures the graph), then one timed
+    loop."""
     import torch
 
     from paper_0904_0939_amd import workloads as W
@@ -255,6 +256,11 @@ def batch64(loop=4000, autotune=True):
         b.set_potential(l.pot_kind, l.pot_params, member=m)
     b.set_initial(lats[0].seed)
     tun = b.autotune(10)[0] if autotune else b.tuning()
+    if tun["persist"] > 0:
+        # the whole loop as one persistent launch (measured equal to 64-step
+        # launches; the graph then holds one reset and one step kernel)
+        tun["persist"] = loop
+        b.set_tuning(**tun)
     # check_every = loop: evolve() captures `loop` steps as one graph; with
     # rel_tol 0 the one check at the end never stops the run
     b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)

@@ -133,9 +133,19 @@ typedef struct {
  *         caches; 2: the same with 512-lane work-groups (ry = 1); 1: large
  *         work-groups (1024 lanes, 512 for BF16) sharing an LDS copy of each
  *         plane (needs vz = the vector width, 2N / vz <= the work-group size
- *         and a tile of at most 64 KiB; ry is ignored). */
+ *         and a tile of at most 64 KiB; ry is ignored);
+ *  persist  0: one launch per step; n > 0: one persistent launch advances
+ *         every member up to n steps (variant 0 only).  Its work-groups (grid,
+ *         0: one per CU) take (step, work item) tickets in order; a work item
+ *         of step t first waits until its own lattice has finished step t - 1,
+ *         so the end of one step overlaps the start of the next on a batch.
+ *         Results are bit-identical to per-step launches of the same shape.
+ *         A wait is bounded (environment FDTD_PERSIST_SPIN_LIMIT polls,
+ *         default 2^22); past it the launch drains and evolve returns
+ *         FDTD_EHIP with the state invalid.  Default: 64 for a batch, 0 for
+ *         a single lattice. */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/

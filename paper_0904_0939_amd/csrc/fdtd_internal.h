@@ -45,7 +45,17 @@ struct MemberState {
   unsigned int counter; // work items finished in the current launch
   int bad;              // a reduction went non-finite
   long long bad_step;
-  double spare[3];
+  unsigned int fin;     // steps finalised since the last persistent-launch reset
+  unsigned int pad0;
+  double spare[2];
+};
+
+// Work dispenser of the persistent step kernel (in the workspace): tickets
+// t * n_items + i hand out item i of step t in increasing order.
+struct Control {
+  unsigned int ticket;  // next ticket
+  int abort;            // a dependency wait exceeded its bound: results invalid
+  unsigned int pad[62];
 };
 
 // One work item: a chunk of a member's flattened (y, z) plane, for planes
@@ -72,6 +82,10 @@ struct StepArgs {
   double* ring;         // history: n_members * ring_cap * kRec
   int ring_cap;
   double* obs_out;      // observe mode: n_members * kRec
+  // persistent launches only
+  int steps;            // steps this launch advances every member
+  unsigned int spin_limit;  // polls of a dependency wait before it gives up
+  Control* ctrl;
 };
 
 enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
@@ -81,6 +95,14 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // bt: threads per work-group, 256, or 512 for ry = 1.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        const StepArgs& a, hipStream_t s);
+// Persistent form of launch_step (update only): `grid` work-groups take
+// (step, item) tickets in order and advance every member a.steps steps; an
+// item of step t waits until its member has finalised step t - 1.
+// launch_persist_reset must run first on the same stream.
+hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, const StepArgs& a,
+                               hipStream_t s);
+hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, hipStream_t s);
+
 // LDS-tile variant: work-groups of tile_threads(dtype) lanes, one vector of
 // the dtype's width per lane; max_n sizes the LDS tile (two planes of the
 // chunk plus one row above and below).

@@ -285,15 +285,22 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 }
 constexpr uint32_t kSaltYZ = 0x68e31da4u;
 
+// Device-scope relaxed load of member state that other work-groups of the
+// same launch may have written (a vector load, never the scalar cache).
+template <typename T>
+__device__ __forceinline__ T ld_agent(const T& x) {
+  return __hip_atomic_load(const_cast<T*>(&x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Last work-group of member m: record the step's sums, set the scale of the
-// next update, advance the step counter, flag non-finite sums, and re-arm
-// the completion counter for the next launch.
+// next update, advance the step counter, flag non-finite sums, re-arm the
+// completion counter and, last, publish the step as finalised (release).
 __device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, int m,
                                       const double (&tot)[5], bool upd) {
   MemberState& st = A.states[m];
   const double kin = -M.kin_scale * tot[1];
-  const long long t = st.step;
-  double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, (double)st.scale, 0.0};
+  const long long t = ld_agent(st.step);
+  double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, ld_agent(st.scale), 0.0};
   if (upd) {
     double* dst = A.ring + ((long long)m * A.ring_cap + (t % A.ring_cap)) * kRec;
 #pragma unroll
@@ -302,7 +309,8 @@ __device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, 
     const bool renorm = A.renorm_every > 0 && (nt % A.renorm_every) == 0;
     st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
     st.step = nt;
-    if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) && !st.bad) {
+    if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) &&
+        !ld_agent(st.bad)) {
       st.bad = 1;
       st.bad_step = t;
     }
@@ -314,6 +322,7 @@ __device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, 
     if (A.set_scale) st.scale = 1.0 / sqrt(M.a3 * tot[0]);
   }
   st.counter = 0u;
+  if (upd) __hip_atomic_fetch_add(&st.fin, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Cross-lane read within the wave (ds_bpermute through the LDS crossbar,
@@ -534,32 +543,34 @@ struct StepBody {
 #define FDTD_STEP_MIN_WAVES 1  // waves per SIMD the register budget must allow
 #endif
 
+// One work item of the fused step: update (UPD) the item's sites of the
+// member's buffer src into src ^ 1, reduce, and let the member's last
+// work-group finalise the step.  Member state is read with atomic loads: in
+// the persistent kernel another work-group may have changed it since this
+// one last looked, and the loads must not come from a stale scalar cache.
 template <int DT, int VZ, int RY, bool UPD, int D, int BT>
-__global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
+__device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, int src,
+                                         double (&s_red)[BT / 64][5], int& s_last) {
   using Body = StepBody<DT, VZ, RY, UPD>;
   using S = typename Body::S;
   using TV = typename Body::TV;
   using C = typename Body::C;
   constexpr unsigned kES = sizeof(S);
-  __shared__ double s_red[BT / 64][5];
-  __shared__ int s_last;
   const int tid = threadIdx.x;
-
-  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
-    const Item item = A.items[A.item_offset + li];
+  {
     const int m = item.member;
     const MemberDev& M = A.members[m];
     const int N = M.N;
     const unsigned P = (unsigned)M.plane;
-    const void* in = M.psi[A.src];
-    void* out = M.psi[A.src ^ 1];
+    const void* in = M.psi[src];
+    void* out = M.psi[src ^ 1];
     const TV* Vf = static_cast<const TV*>(M.V);
     const unsigned pbytes = P * kES, vbytes = P * (unsigned)sizeof(TV);
     const C c = (C)M.c;
     const C dt = (C)M.dt;
     const C eps = (C)(0.5 * M.dt);
-    const C sc = (C)A.states[m].scale;
-    const uint32_t smix = hash32((uint32_t)A.states[m].step);
+    const C sc = (C)ld_agent(A.states[m].scale);
+    const uint32_t smix = hash32((uint32_t)ld_agent(A.states[m].step));
     const double ha = M.ha;
     const double cN = (double)(N - 1);
 
@@ -666,6 +677,59 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
       if (tid == 0) finalize(A, M, m, tot, UPD);
     }
     __syncthreads();
+  }
+}
+
+template <int DT, int VZ, int RY, bool UPD, int D, int BT>
+__global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
+  __shared__ double s_red[BT / 64][5];
+  __shared__ int s_last;
+  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
+    run_item<DT, VZ, RY, UPD, D, BT>(A, A.items[A.item_offset + li], A.src, s_red, s_last);
+}
+
+// Persistent fused step: A.steps steps of every member in one launch.  Each
+// work-group takes tickets k = t * n_items + i in increasing order (item i in
+// processing order, step t; buffers alternate with t).  Before item i of
+// step t, thread 0 polls until the item's member has finalised step t - 1
+// (its `fin` counter, reset to 0 before the launch), which the member's last
+// work-group of that step raises after the step's data, scale and record.
+// Every wait ends: the items waited on hold smaller tickets, taken by running
+// work-groups, and the smallest unfinished ticket never waits on anything
+// unfinished.  As a guard the poll gives up after A.spin_limit rounds,
+// raising ctrl->abort, which every work-group checks: the launch then drains
+// and the host reports the results invalid.
+template <int DT, int VZ, int RY, int D, int BT>
+__global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepArgs A) {
+  __shared__ double s_red[BT / 64][5];
+  __shared__ int s_last;
+  __shared__ int s_tk;
+  const int tid = threadIdx.x;
+  const int total = A.steps * A.n_items;
+  for (;;) {
+    if (tid == 0) {
+      int tk = (int)atomicAdd(&A.ctrl->ticket, 1u);
+      if (tk < total) {
+        const unsigned need = (unsigned)(tk / A.n_items);
+        unsigned int* fin = &A.states[A.items[tk % A.n_items].member].fin;
+        unsigned polls = 0;
+        while (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (__hip_atomic_load(&A.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+              ++polls > A.spin_limit) {
+            __hip_atomic_store(&A.ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tk = total;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+      }
+      s_tk = tk;
+    }
+    __syncthreads();
+    const int tk = s_tk;
+    if (tk >= total) break;
+    const int t = tk / A.n_items;
+    run_item<DT, VZ, RY, true, D, BT>(A, A.items[tk % A.n_items], A.src ^ (t & 1), s_red, s_last);
   }
 }
 
@@ -1264,6 +1328,52 @@ hipError_t step_ry(int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
   }
 }
 
+template <int DT, int VZ, int RY, int D>
+hipError_t persist_one(int grid, const StepArgs& a, hipStream_t s) {
+  if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || VZ > 1)) {
+    hipLaunchKernelGGL((k_step_persist<DT, VZ, RY, D, 256>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int VZ, int D>
+hipError_t persist_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
+  switch (ry) {
+    case 1: return persist_one<DT, VZ, 1, D>(grid, a, s);
+    case 2: return persist_one<DT, VZ, 2, D>(grid, a, s);
+    case 4: return persist_one<DT, VZ, 4, D>(grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int VZ>
+hipError_t persist_d(int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+  switch (depth) {
+    case 1: return persist_ry<DT, VZ, 1>(ry, grid, a, s);
+    case 2: return persist_ry<DT, VZ, 2>(ry, grid, a, s);
+    case 3: return persist_ry<DT, VZ, 3>(ry, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT>
+hipError_t persist_dt(int vz, int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+  if (vz == 1) return persist_d<DT, 1>(1, ry, grid, a, s);
+  if (vz == Types<DT>::kVec) return persist_d<DT, Types<DT>::kVec>(depth, ry, grid, a, s);
+  return hipErrorInvalidValue;
+}
+
+__global__ void k_persist_reset(Control* ctrl, MemberState* states, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) states[i].fin = 0u;
+  if (i == 0) {
+    ctrl->ticket = 0u;
+    ctrl->abort = 0;
+  }
+}
+
 template <int DT, int VZ, bool UPD>
 hipError_t step_d(int depth, int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
   switch (depth) {
@@ -1323,6 +1433,22 @@ hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max
     case kBF16: return tile_dt<kBF16>(depth, update, grid, lds, a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, const StepArgs& a,
+                               hipStream_t s) {
+  if (grid < 1 || a.steps < 1 || !a.ctrl) return hipErrorInvalidValue;
+  switch (dtype) {
+    case kF64: return persist_dt<kF64>(vz, depth, ry, grid, a, s);
+    case kF32: return persist_dt<kF32>(vz, depth, ry, grid, a, s);
+    case kBF16: return persist_dt<kBF16>(vz, depth, ry, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_persist_reset, dim3((count + 255) / 256), dim3(256), 0, s, ctrl, states, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -83,7 +84,7 @@ struct fdtd_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool ws_owned = false;
-  size_t off_members = 0, off_states = 0, off_ring = 0, off_obs = 0, off_params = 0;
+  size_t off_members = 0, off_states = 0, off_ring = 0, off_obs = 0, off_params = 0, off_ctrl = 0;
   size_t need_bytes = 0;
 
   // work items (library-allocated, depend on the tuning): d_items in member
@@ -100,6 +101,8 @@ struct fdtd_ctx {
   int cur = 0;  // buffer holding the current state (all members)
   fdtd_tuning tun{};
   bool tuned = false;
+  int n_cu = 256;  // compute units of the device: work-groups of a persistent launch
+  unsigned spin_limit = 1u << 22;  // polls of a persistent dependency wait
 
   // pinned host staging for small readbacks
   double* h_pin = nullptr;
@@ -112,6 +115,7 @@ struct fdtd_ctx {
   double* d_ring() { return reinterpret_cast<double*>(ws + off_ring); }
   double* d_obs() { return reinterpret_cast<double*>(ws + off_obs); }
   double* d_params() { return reinterpret_cast<double*>(ws + off_params); }
+  Control* d_ctrl() { return reinterpret_cast<Control*>(ws + off_ctrl); }
   void* psi(int m, int b) { return ws + mem[m].off_psi[b]; }
   void* V(int m) { return ws + mem[m].off_V; }
 };
@@ -141,6 +145,8 @@ void compute_layout(fdtd_ctx* h) {
   off = align256(off + sizeof(double) * kRec * h->count);
   h->off_params = off;
   off = align256(off + sizeof(double) * (kMaxParams + 64));
+  h->off_ctrl = off;
+  off = align256(off + sizeof(Control));
   h->need_bytes = off;
 }
 
@@ -205,6 +211,14 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   h->tun.xcd_remap = 1;
   h->tun.depth = 1;
   h->tun.variant = 0;
+  // batches: one persistent launch per 64 steps lets the next step of a
+  // finished lattice fill the end of the current one (measured on 64 lattices
+  // of side 48..160: 299 -> 257 us per step); a single lattice keeps one
+  // launch per step, whose fixed XCD-local tile order the dynamic tickets lose
+  h->tun.persist = h->count > 1 ? 64 : 0;
+  // test hook: a small bound makes a persistent launch give up its first
+  // unmet dependency wait (and drain), so the error path can be exercised
+  if (const char* e = std::getenv("FDTD_PERSIST_SPIN_LIMIT")) h->spin_limit = (unsigned)std::strtoul(e, nullptr, 10);
   *out = h;
   return FDTD_OK;
 }
@@ -215,6 +229,9 @@ fdtd_status set_device(fdtd_ctx* h) {
   if (e != hipSuccess || n == 0) return fail(FDTD_EHIP, "no HIP device available (the library has no CPU fallback)");
   if (h->device < 0 || h->device >= n) return fail(FDTD_EINVAL, "device ordinal out of range");
   HIP_TRY(hipSetDevice(h->device));
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cu > 0)
+    h->n_cu = cu;
   return FDTD_OK;
 }
 
@@ -260,6 +277,7 @@ fdtd_status ensure_memory(fdtd_ctx* h) {
     h->ws_bytes = h->need_bytes;
     h->ws_owned = true;
     for (int m = 0; m < h->count; ++m) HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
+    HIP_TRY(launch_persist_reset(h->d_ctrl(), h->d_states(), h->count, h->stream));
   }
   if (!h->h_pin) {
     h->h_pin_doubles = (size_t)kRec * (h->count + 8) + 4096;
@@ -423,7 +441,26 @@ fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
   return FDTD_OK;
 }
 
+// n steps: one launch per step, or with tun.persist > 0 persistent launches
+// of up to tun.persist steps each (a reset kernel before each).
 fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
+  if (h->tun.persist > 0) {
+    for (int done = 0; done < n;) {
+      // tickets (steps x items) stay below 2^30
+      const int k = std::min({h->tun.persist, n - done, std::max(1, (1 << 30) / std::max(1, h->n_items))});
+      StepArgs a = base_args(h);
+      a.renorm_every = renorm_every;
+      a.steps = k;
+      a.spin_limit = h->spin_limit;
+      a.ctrl = h->d_ctrl();
+      const int grid = h->tun.grid > 0 ? h->tun.grid : h->n_cu;
+      HIP_TRY(launch_persist_reset(a.ctrl, a.states, h->count, s));
+      HIP_TRY(launch_step_persist(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, grid, a, s));
+      if (k & 1) h->cur ^= 1;
+      done += k;
+    }
+    return FDTD_OK;
+  }
   for (int k = 0; k < n; ++k) {
     StepArgs a = base_args(h);
     a.renorm_every = renorm_every;
@@ -435,7 +472,8 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
-         a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant;
+         a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant &&
+         a.persist == b.persist;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -489,12 +527,17 @@ fdtd_status require_ready(fdtd_ctx* h) {
   return FDTD_OK;
 }
 
-// Copy member states (device) to host pinned staging.
+// Copy member states (device) to the host; fails if a persistent launch
+// gave up a dependency wait (its results are then invalid).
 fdtd_status read_states(fdtd_ctx* h, std::vector<MemberState>& out) {
   out.resize(h->count);
+  Control c;
   HIP_TRY(hipMemcpyAsync(out.data(), h->d_states(), sizeof(MemberState) * h->count,
                          hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&c, h->d_ctrl(), sizeof c, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  if (c.abort)
+    return fail(FDTD_EHIP, "persistent step: a dependency wait exceeded its bound; the state is invalid");
   return FDTD_OK;
 }
 
@@ -587,6 +630,8 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   if (t.depth < 1 || t.depth > 3) return fail(FDTD_EINVAL, "tuning: depth must be 1, 2 or 3");
   if (t.vz == 1 && t.depth != 1) return fail(FDTD_EINVAL, "tuning: depth must be 1 when vz = 1");
   if (t.variant < 0 || t.variant > 2) return fail(FDTD_EINVAL, "tuning: variant must be 0, 1 or 2");
+  if (t.persist < 0 || t.persist > 65536) return fail(FDTD_EINVAL, "tuning: persist must be in [0, 65536]");
+  if (t.persist > 0 && t.variant != 0) return fail(FDTD_EINVAL, "tuning: persistent launches need variant 0");
   if (t.variant == 2) {
     if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");
     if (h->dtype == kBF16 && t.vz > 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs vz = 1 for BF16");
@@ -631,6 +676,7 @@ fdtd_status fdtd_bind_workspace(fdtd_t h, void* dev_ptr, size_t bytes) {
   h->ws_bytes = bytes;
   h->ws_owned = false;
   for (int m = 0; m < h->count; ++m) HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
+  HIP_TRY(launch_persist_reset(h->d_ctrl(), h->d_states(), h->count, h->stream));
   return FDTD_OK;
 }
 
@@ -1023,14 +1069,17 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
       return true;
     };
     bool go = true;
+    std::vector<int> persists = {0};
+    if (h->count > 1) persists.push_back(64);
     for (int vz : vzs)
       for (int ry : {1, 2, 4})
         for (int xc : {0, 32, 64, 128, 256})
           for (int depth : {1, 2, 3})
-            for (int variant : {0, 2}) {
-              if (!go || xc > maxN || (vz == 1 && depth > 1)) continue;
-              go = trial(fdtd_tuning{vz, ry, xc, 0, 1, depth, variant});
-            }
+            for (int variant : {0, 2})
+              for (int persist : persists) {
+                if (!go || xc > maxN || (vz == 1 && depth > 1) || (persist && variant)) continue;
+                go = trial(fdtd_tuning{vz, ry, xc, 0, 1, depth, variant, persist});
+              }
     // LDS-tile variant
     for (int xc : {0, 64, 128, 256})
       for (int depth : {1, 2, 3}) {
