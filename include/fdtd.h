@@ -143,9 +143,16 @@ typedef struct {
  *         A wait is bounded (environment FDTD_PERSIST_SPIN_LIMIT polls,
  *         default 2^22); past it the launch drains and evolve returns
  *         FDTD_EHIP with the state invalid.  Default: 64 for a batch, 0 for
- *         a single lattice. */
+ *         a single lattice;
+ *  vfuse  1 (default): on F32 / BF16 lattices whose potentials all came from
+ *         fdtd_set_potential_analytic with kinds CONST..CORNELL, the step
+ *         evaluates V from the site coordinates in FP32 (hardware 1/sqrt(r^2))
+ *         instead of streaming the V table from HBM (12 -> 8 bytes per site for
+ *         F32, 8 -> 4 for BF16); variant 0 (per-step or persistent) only, and
+ *         not inside fdtd_energy_grad.  V then differs from the table (V computed
+ *         in FP64, rounded once) by a few FP32 ulps.  0: always read the table. */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/

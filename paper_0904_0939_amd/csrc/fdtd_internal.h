@@ -36,6 +36,10 @@ struct MemberDev {
   double dt;
   double kin_scale;   // 1 / (2 m a^2)
   double a3;          // a^3
+  double a;           // lattice spacing
+  double vp[3];       // parameters of an analytic potential (kind vkind)
+  int vkind;          // analytic kind 0..4 the step may evaluate itself; -1: table only
+  int pad1;
 };
 
 // Mutable per-member state, resident on the device.
@@ -93,14 +97,16 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // Launch the fused step (update = true) or the reduction-only pass.
 // depth: prefetch distance of the HBM streams, in planes (1..3).
 // bt: threads per work-group, 256, or 512 for ry = 1.
+// fv: evaluate the members' analytic potentials in the kernel (F32 / BF16,
+// bt = 256; every member's vkind must be >= 0) instead of reading V.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
-                       const StepArgs& a, hipStream_t s);
+                       bool fv, const StepArgs& a, hipStream_t s);
 // Persistent form of launch_step (update only): `grid` work-groups take
 // (step, item) tickets in order and advance every member a.steps steps; an
 // item of step t waits until its member has finalised step t - 1.
 // launch_persist_reset must run first on the same stream.
-hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, const StepArgs& a,
-                               hipStream_t s);
+hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, bool fv,
+                               const StepArgs& a, hipStream_t s);
 hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, hipStream_t s);
 
 // LDS-tile variant: work-groups of tile_threads(dtype) lanes, one vector of

@@ -357,6 +357,7 @@ struct Lane {
   C w2[RY][VZ];           // y^2 + z^2 of each site
   uint32_t hk[RY][VZ > 1 ? VZ / 2 : 1];  // (y, z) part of the rounding bits (BF16)
   uint32_t hsh[RY][VZ];   // which half of the 32 bits a site takes: 0 or 16
+  C vl[RY][VZ];           // (y, z) part of a potential evaluated in the kernel
 };
 
 // Data of one plane that the update of that plane needs besides the planes
@@ -366,7 +367,13 @@ struct PlaneIn {
   C ym[RY][VZ], yp[RY][VZ], zm[RY], zp[RY];
 };
 
-template <int DT, int VZ, int RY, bool UPD>
+// Analytic potentials the step can evaluate itself (FP32 arithmetic) instead
+// of streaming V from HBM; the numbering is that of the C ABI.
+enum VKind { kVConst = 0, kVHO = 1, kVCoulomb = 2, kVCoulombReg = 3, kVCornell = 4 };
+
+// FV: the potential is evaluated in the kernel from the site coordinates
+// (member kinds kVConst..kVCornell) instead of read from the V table.
+template <int DT, int VZ, int RY, bool UPD, bool FV = false>
 struct StepBody {
   using S = typename Types<DT>::S;
   using TV = typename Types<DT>::V;
@@ -386,7 +393,41 @@ struct StepBody {
     C c, dt, eps, sc;
     double ha, cN;
     uint32_t smix;  // hash32(step): the step's part of the rounding bits
+    // FV only: one branch-free form for every analytic kind,
+    //   V = q1 / r + q2 r + hx x^2 + vl(y, z),  0 where r < va,
+    // with 1/r taken of r^2 + ve (ve = 1 for kinds without 1/r, so r = 0
+    // gives 0 * finite there; ve = 0 keeps Coulomb's singularity):
+    //   CONST       vl = p0
+    //   HO          hx = p0^2 / 2, vl = (p1^2 y^2 + p2^2 z^2) / 2
+    //   COULOMB     q1 = -p0
+    //   COULOMB_REG q1 = -p0, vl = p0 / a, va = a
+    //   CORNELL     q1 = -p0, q2 = p1, vl = p2 z^2
+    C q1, q2, hx, ve, va;
   };
+
+  // Per-kind coefficients of the in-kernel potential (FV).
+  static __device__ __forceinline__ void vcoef(Ctx& k, int kind, const double* vp, double a) {
+    k.q1 = (kind == kVCoulomb || kind == kVCoulombReg || kind == kVCornell) ? (C)(-vp[0]) : C(0);
+    k.q2 = kind == kVCornell ? (C)vp[1] : C(0);
+    k.hx = kind == kVHO ? (C)(0.5 * vp[0] * vp[0]) : C(0);
+    k.ve = (kind == kVCoulomb || kind == kVCoulombReg || kind == kVCornell) ? C(0) : C(1);
+    k.va = kind == kVCoulombReg ? (C)a : C(0);
+  }
+
+  // (y, z) part vl of the in-kernel potential of site j of vector r, from
+  // its mirror-exact coordinates yc, zc.
+  static __device__ __forceinline__ void vlane(Lane<RY, VZ, C>& ln, int r, int j, int kind,
+                                               const double* vp, double a, double yc,
+                                               double zc) {
+    if constexpr (FV) {
+      double v = 0.0;
+      if (kind == kVConst) v = vp[0];
+      else if (kind == kVHO) v = 0.5 * (vp[1] * vp[1] * yc * yc + vp[2] * vp[2] * zc * zc);
+      else if (kind == kVCoulombReg) v = vp[0] / a;
+      else if (kind == kVCornell) v = vp[2] * zc * zc;
+      ln.vl[r][j] = (C)v;
+    }
+  }
 
   // The (y, z) part of the rounding bits of vector r (BF16 stores only),
   // from the mirror-canonical (y, z) index of each of its sites.
@@ -419,11 +460,30 @@ struct StepBody {
     }
   }
 
+  // V of the lane's sites of plane x (needed for x < xe): loaded from the
+  // table, or (FV) evaluated from the coordinates.  r^2 = x^2 + (y^2 + z^2)
+  // and the other terms are mirror-symmetric bit for bit, as in the table.
   static __device__ __forceinline__ void fetch_v(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                  C (&v)[RY][VZ]) {
-    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
+    if constexpr (FV) {
+      const double xd = (2.0 * x - k.cN) * k.ha;
+      const C x2 = (C)(xd * xd);
+      const C vx = k.hx * x2;
 #pragma unroll
-    for (int r = 0; r < RY; ++r) bload<TV, VZ, C, FDTD_AUX_V>(rv, ln.voff[r], v[r]);
+      for (int r = 0; r < RY; ++r)
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          const C r2 = x2 + ln.w2[r][j];
+          const C inv = __builtin_amdgcn_rsqf(r2 + k.ve);  // 1/r, hardware (~1 ulp)
+          const C rr = r2 * inv;
+          const C vv = __builtin_fmaf(k.q1, inv, __builtin_fmaf(k.q2, rr, vx + ln.vl[r][j]));
+          v[r][j] = rr < k.va ? C(0) : vv;
+        }
+    } else {
+      const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
+#pragma unroll
+      for (int r = 0; r < RY; ++r) bload<TV, VZ, C, FDTD_AUX_V>(rv, ln.voff[r], v[r]);
+    }
   }
 
   // Own sites of plane x (needed for x <= xe).
@@ -548,10 +608,10 @@ struct StepBody {
 // work-group finalise the step.  Member state is read with atomic loads: in
 // the persistent kernel another work-group may have changed it since this
 // one last looked, and the loads must not come from a stale scalar cache.
-template <int DT, int VZ, int RY, bool UPD, int D, int BT>
+template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false>
 __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, int src,
                                          double (&s_red)[BT / 64][5], int& s_last) {
-  using Body = StepBody<DT, VZ, RY, UPD>;
+  using Body = StepBody<DT, VZ, RY, UPD, FV>;
   using S = typename Body::S;
   using TV = typename Body::TV;
   using C = typename Body::C;
@@ -603,6 +663,7 @@ __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, in
       for (int j = 0; j < VZ; ++j) {
         const double zc = (2.0 * (z0 + j) - cN) * ha;
         ln.w2[r][j] = (C)(yc * yc + zc * zc);
+        Body::vlane(ln, r, j, M.vkind, M.vp, M.a, yc, zc);
         const int z = z0 + j;
         key[j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
       }
@@ -610,6 +671,7 @@ __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, in
     }
 
     typename Body::Ctx k;
+    if constexpr (FV) Body::vcoef(k, M.vkind, M.vp, M.a);
     k.in = in;
     k.out = out;
     k.Vf = Vf;
@@ -680,12 +742,12 @@ __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, in
   }
 }
 
-template <int DT, int VZ, int RY, bool UPD, int D, int BT>
+template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV>
 __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
   __shared__ double s_red[BT / 64][5];
   __shared__ int s_last;
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
-    run_item<DT, VZ, RY, UPD, D, BT>(A, A.items[A.item_offset + li], A.src, s_red, s_last);
+    run_item<DT, VZ, RY, UPD, D, BT, FV>(A, A.items[A.item_offset + li], A.src, s_red, s_last);
 }
 
 // Persistent fused step: A.steps steps of every member in one launch.  Each
@@ -699,7 +761,7 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
 // unfinished.  As a guard the poll gives up after A.spin_limit rounds,
 // raising ctrl->abort, which every work-group checks: the launch then drains
 // and the host reports the results invalid.
-template <int DT, int VZ, int RY, int D, int BT>
+template <int DT, int VZ, int RY, int D, int BT, bool FV>
 __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepArgs A) {
   __shared__ double s_red[BT / 64][5];
   __shared__ int s_last;
@@ -729,7 +791,8 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepAr
     const int tk = s_tk;
     if (tk >= total) break;
     const int t = tk / A.n_items;
-    run_item<DT, VZ, RY, true, D, BT>(A, A.items[tk % A.n_items], A.src ^ (t & 1), s_red, s_last);
+    run_item<DT, VZ, RY, true, D, BT, FV>(A, A.items[tk % A.n_items], A.src ^ (t & 1), s_red,
+                                          s_last);
   }
 }
 
@@ -1297,10 +1360,20 @@ int grid_for(long long n) {
 // instantiated; the scalar-lane fallback (VZ = 1) and the reduction-only
 // pass use prefetch distance 1 only.
 template <int DT, int VZ, int RY, bool UPD, int D>
-hipError_t step_one(int grid, int bt, const StepArgs& a, hipStream_t s) {
+hipError_t step_one(int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
   if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || (UPD && VZ > 1))) {
+    if (fv) {
+      // in-kernel potential: FP32 arithmetic lattices, 256-lane work-groups
+      if constexpr (DT != kF64) {
+        if (bt == 256) {
+          hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256, true>), dim3(grid), dim3(256), 0, s, a);
+          return hipGetLastError();
+        }
+      }
+      return hipErrorInvalidValue;
+    }
     if (bt == 256) {
-      hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256>), dim3(grid), dim3(256), 0, s, a);
+      hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256, false>), dim3(grid), dim3(256), 0, s, a);
       return hipGetLastError();
     }
     // 512-lane groups cap registers at 256: one vector of <= 16 bytes of
@@ -1308,7 +1381,7 @@ hipError_t step_one(int grid, int bt, const StepArgs& a, hipStream_t s) {
     if constexpr (RY == 1 && VZ * sizeof(typename Types<DT>::C) <= 16 &&
                   (D == 1 || sizeof(typename Types<DT>::C) == 4)) {
       if (bt == 512) {
-        hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD, D, 512>), dim3(grid), dim3(512), 0, s, a);
+        hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD, D, 512, false>), dim3(grid), dim3(512), 0, s, a);
         return hipGetLastError();
       }
     }
@@ -1319,19 +1392,26 @@ hipError_t step_one(int grid, int bt, const StepArgs& a, hipStream_t s) {
 }
 
 template <int DT, int VZ, bool UPD, int D>
-hipError_t step_ry(int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
+hipError_t step_ry(int ry, int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, bt, a, s);
-    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, bt, a, s);
-    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, bt, a, s);
+    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, bt, fv, a, s);
+    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, bt, fv, a, s);
+    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, bt, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, int VZ, int RY, int D>
-hipError_t persist_one(int grid, const StepArgs& a, hipStream_t s) {
+hipError_t persist_one(int grid, bool fv, const StepArgs& a, hipStream_t s) {
   if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || VZ > 1)) {
-    hipLaunchKernelGGL((k_step_persist<DT, VZ, RY, D, 256>), dim3(grid), dim3(256), 0, s, a);
+    if (fv) {
+      if constexpr (DT != kF64) {
+        hipLaunchKernelGGL((k_step_persist<DT, VZ, RY, D, 256, true>), dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_step_persist<DT, VZ, RY, D, 256, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -1339,29 +1419,30 @@ hipError_t persist_one(int grid, const StepArgs& a, hipStream_t s) {
 }
 
 template <int DT, int VZ, int D>
-hipError_t persist_ry(int ry, int grid, const StepArgs& a, hipStream_t s) {
+hipError_t persist_ry(int ry, int grid, bool fv, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: return persist_one<DT, VZ, 1, D>(grid, a, s);
-    case 2: return persist_one<DT, VZ, 2, D>(grid, a, s);
-    case 4: return persist_one<DT, VZ, 4, D>(grid, a, s);
+    case 1: return persist_one<DT, VZ, 1, D>(grid, fv, a, s);
+    case 2: return persist_one<DT, VZ, 2, D>(grid, fv, a, s);
+    case 4: return persist_one<DT, VZ, 4, D>(grid, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, int VZ>
-hipError_t persist_d(int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
+hipError_t persist_d(int depth, int ry, int grid, bool fv, const StepArgs& a, hipStream_t s) {
   switch (depth) {
-    case 1: return persist_ry<DT, VZ, 1>(ry, grid, a, s);
-    case 2: return persist_ry<DT, VZ, 2>(ry, grid, a, s);
-    case 3: return persist_ry<DT, VZ, 3>(ry, grid, a, s);
+    case 1: return persist_ry<DT, VZ, 1>(ry, grid, fv, a, s);
+    case 2: return persist_ry<DT, VZ, 2>(ry, grid, fv, a, s);
+    case 3: return persist_ry<DT, VZ, 3>(ry, grid, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT>
-hipError_t persist_dt(int vz, int depth, int ry, int grid, const StepArgs& a, hipStream_t s) {
-  if (vz == 1) return persist_d<DT, 1>(1, ry, grid, a, s);
-  if (vz == Types<DT>::kVec) return persist_d<DT, Types<DT>::kVec>(depth, ry, grid, a, s);
+hipError_t persist_dt(int vz, int depth, int ry, int grid, bool fv, const StepArgs& a,
+                      hipStream_t s) {
+  if (vz == 1) return persist_d<DT, 1>(1, ry, grid, fv, a, s);
+  if (vz == Types<DT>::kVec) return persist_d<DT, Types<DT>::kVec>(depth, ry, grid, fv, a, s);
   return hipErrorInvalidValue;
 }
 
@@ -1375,28 +1456,28 @@ __global__ void k_persist_reset(Control* ctrl, MemberState* states, int count) {
 }
 
 template <int DT, int VZ, bool UPD>
-hipError_t step_d(int depth, int ry, int grid, int bt, const StepArgs& a, hipStream_t s) {
+hipError_t step_d(int depth, int ry, int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
   switch (depth) {
-    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, bt, a, s);
-    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, bt, a, s);
-    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, bt, a, s);
+    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, bt, fv, a, s);
+    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, bt, fv, a, s);
+    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, bt, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, bool UPD>
-hipError_t step_vz(int vz, int depth, int ry, int grid, int bt, const StepArgs& a,
+hipError_t step_vz(int vz, int depth, int ry, int grid, int bt, bool fv, const StepArgs& a,
                    hipStream_t s) {
-  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, bt, a, s);
-  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, bt, a, s);
+  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, bt, fv, a, s);
+  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, bt, fv, a, s);
   return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, int bt, const StepArgs& a,
-                   hipStream_t s) {
-  return upd ? step_vz<DT, true>(vz, depth, ry, grid, bt, a, s)
-             : step_vz<DT, false>(vz, 1, ry, grid, bt, a, s);
+hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, int bt, bool fv,
+                   const StepArgs& a, hipStream_t s) {
+  return upd ? step_vz<DT, true>(vz, depth, ry, grid, bt, fv, a, s)
+             : step_vz<DT, false>(vz, 1, ry, grid, bt, fv, a, s);
 }
 
 template <int DT, bool UPD, int D>
@@ -1435,13 +1516,13 @@ hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max
   }
 }
 
-hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, const StepArgs& a,
-                               hipStream_t s) {
+hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, bool fv,
+                               const StepArgs& a, hipStream_t s) {
   if (grid < 1 || a.steps < 1 || !a.ctrl) return hipErrorInvalidValue;
   switch (dtype) {
-    case kF64: return persist_dt<kF64>(vz, depth, ry, grid, a, s);
-    case kF32: return persist_dt<kF32>(vz, depth, ry, grid, a, s);
-    case kBF16: return persist_dt<kBF16>(vz, depth, ry, grid, a, s);
+    case kF64: return persist_dt<kF64>(vz, depth, ry, grid, fv, a, s);
+    case kF32: return persist_dt<kF32>(vz, depth, ry, grid, fv, a, s);
+    case kBF16: return persist_dt<kBF16>(vz, depth, ry, grid, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1452,13 +1533,13 @@ hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, h
 }
 
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
-                       const StepArgs& a, hipStream_t s) {
+                       bool fv, const StepArgs& a, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
   if (vz == 1) depth = 1;
   switch (dtype) {
-    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, bt, a, s);
-    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, bt, a, s);
-    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, a, s);
+    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, bt, fv, a, s);
+    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, bt, fv, a, s);
+    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, fv, a, s);
     default: return hipErrorInvalidValue;
   }
 }

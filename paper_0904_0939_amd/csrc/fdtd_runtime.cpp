@@ -60,6 +60,8 @@ struct MemberHost {
   bool pot_set = false, init_set = false;
   uint32_t parity = 0;
   int item_begin = 0, item_end = 0;
+  int vkind = -1;  // analytic kind the step may evaluate itself (0..4), -1: table only
+  double vp[3] = {0, 0, 0};
 };
 
 struct GraphEntry {
@@ -101,6 +103,7 @@ struct fdtd_ctx {
   int cur = 0;  // buffer holding the current state (all members)
   fdtd_tuning tun{};
   bool tuned = false;
+  bool table_v_only = false;  // set while the gradient driver recomputes the forward
   int n_cu = 256;  // compute units of the device: work-groups of a persistent launch
   unsigned spin_limit = 1u << 22;  // polls of a persistent dependency wait
 
@@ -216,6 +219,7 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   // of side 48..160: 299 -> 257 us per step); a single lattice keeps one
   // launch per step, whose fixed XCD-local tile order the dynamic tickets lose
   h->tun.persist = h->count > 1 ? 64 : 0;
+  h->tun.vfuse = 1;
   // test hook: a small bound makes a persistent launch give up its first
   // unmet dependency wait (and drain), so the error path can be exercised
   if (const char* e = std::getenv("FDTD_PERSIST_SPIN_LIMIT")) h->spin_limit = (unsigned)std::strtoul(e, nullptr, 10);
@@ -251,6 +255,9 @@ MemberDev member_dev(fdtd_ctx* h, int i) {
   d.dt = m.dt;
   d.kin_scale = m.kin_scale;
   d.a3 = m.a3;
+  d.a = m.a;
+  d.vkind = m.vkind;
+  for (int k = 0; k < 3; ++k) d.vp[k] = m.vp[k];
   return d;
 }
 
@@ -402,12 +409,21 @@ int max_n(const fdtd_ctx* h) {
 
 // Launch the fused step (update) or the reduction-only pass with the
 // handle's launch shape.
+// The step evaluates the potential itself: FP32 / BF16 lattices, variant 0,
+// every member's potential one of the analytic kinds 0..4, tun.vfuse set.
+bool use_fv(const fdtd_ctx* h) {
+  if (!h->tun.vfuse || h->dtype == kF64 || h->tun.variant != 0 || h->table_v_only) return false;
+  for (const auto& m : h->mem)
+    if (m.vkind < 0) return false;
+  return true;
+}
+
 hipError_t launch_kernel(const fdtd_ctx* h, bool update, int grid, const StepArgs& a,
                          hipStream_t s) {
   if (h->tun.variant == 1)
     return launch_step_tile(h->dtype, update ? h->tun.depth : 1, update, grid, max_n(h), a, s);
   return launch_step(h->dtype, h->tun.vz, h->tun.ry, update ? h->tun.depth : 1, update, grid,
-                     h->tun.variant == 2 ? 512 : 256, a, s);
+                     h->tun.variant == 2 ? 512 : 256, use_fv(h), a, s);
 }
 
 StepArgs base_args(fdtd_ctx* h) {
@@ -455,7 +471,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
       a.ctrl = h->d_ctrl();
       const int grid = h->tun.grid > 0 ? h->tun.grid : h->n_cu;
       HIP_TRY(launch_persist_reset(a.ctrl, a.states, h->count, s));
-      HIP_TRY(launch_step_persist(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, grid, a, s));
+      HIP_TRY(launch_step_persist(h->dtype, h->tun.vz, h->tun.ry, h->tun.depth, grid, use_fv(h), a, s));
       if (k & 1) h->cur ^= 1;
       done += k;
     }
@@ -473,7 +489,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
          a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant &&
-         a.persist == b.persist;
+         a.persist == b.persist && a.vfuse == b.vfuse;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -632,6 +648,7 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   if (t.variant < 0 || t.variant > 2) return fail(FDTD_EINVAL, "tuning: variant must be 0, 1 or 2");
   if (t.persist < 0 || t.persist > 65536) return fail(FDTD_EINVAL, "tuning: persist must be in [0, 65536]");
   if (t.persist > 0 && t.variant != 0) return fail(FDTD_EINVAL, "tuning: persistent launches need variant 0");
+  if (t.vfuse != 0 && t.vfuse != 1) return fail(FDTD_EINVAL, "tuning: vfuse must be 0 or 1");
   if (t.variant == 2) {
     if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");
     if (h->dtype == kBF16 && t.vz > 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs vz = 1 for BF16");
@@ -704,6 +721,8 @@ fdtd_status fdtd_set_potential(fdtd_t h, int32_t member, const void* v, int32_t 
   ST_TRY(ensure_memory(h));
   ST_TRY(copy_in_field(h, v, dtype, on_device, h->vdtype, h->V(member), h->mem[member].n3));
   h->mem[member].pot_set = true;
+  h->mem[member].vkind = -1;
+  h->items_valid = false;  // re-upload the member table
   drop_graphs(h);
   return FDTD_OK;
 }
@@ -726,8 +745,12 @@ fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, 
     const MemberHost& mh = h->mem[m];
     HIP_TRY(launch_potential(h->vdtype, h->V(m), mh.N, mh.ha, mh.a, kind, h->d_params(), np, h->stream));
     h->mem[m].pot_set = true;
+    // the table is always filled; kinds 0..4 may also be evaluated in the step
+    h->mem[m].vkind = kind <= FDTD_POT_CORNELL ? kind : -1;
+    for (int k = 0; k < 3; ++k) h->mem[m].vp[k] = k < np ? p[k] : 0.0;
   }
   HIP_TRY(hipStreamSynchronize(h->stream));  // p is the caller's host memory
+  h->items_valid = false;  // re-upload the member table
   drop_graphs(h);
   return FDTD_OK;
 }
@@ -1046,7 +1069,8 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   if (all_div) vzs.push_back(vw);
   {
     // time one candidate; false stops the search (st holds the error)
-    auto trial = [&](const fdtd_tuning& t) -> bool {
+    auto trial = [&](fdtd_tuning t) -> bool {
+      t.vfuse = orig.vfuse;
       if (validate_tuning(h, t) != FDTD_OK) return true;
       h->tun = t;
       h->items_valid = false;
@@ -1137,6 +1161,13 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
   ST_TRY(require_ready(h));
   ST_TRY(ensure_memory(h));
   ST_TRY(build_items(h));
+  // the adjoint reads the V table: the forward and its recompute read it too,
+  // so all three see the same potential to the last bit
+  struct TableV {
+    fdtd_ctx* h;
+    ~TableV() { h->table_v_only = false; }
+  } table_v{h};
+  h->table_v_only = true;
   const MemberHost& m = h->mem[0];
   const size_t es = elem_size(h->dtype);
   const size_t fb = align256(es * (size_t)m.n3);

@@ -108,13 +108,14 @@ def test_tuning_validation_is_host_side():
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0, 1))
         assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
                                                   "xcd_remap": 0, "depth": 1, "variant": 0,
-                                                  "persist": 0}
+                                                  "persist": 0, "vfuse": 0}
         # persistent launches: variant 0 only, bounded step count
         for bad in [F.fdtd_tuning(1, 1, 8, 0, 1, 1, 2, 8), F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, -1),
                     F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, 65537)]:
             assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 2, 0, 0, 1, 1, 0, 64))
         assert F.fdtd_get_tuning(h).persist == 64
+        assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(1, 2, 0, 0, 1, 1, 0, 0, 2))) == F.EINVAL
         # the LDS-tile variant needs full-width vectors
         assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(1, 1, 8, 0, 1, 1, 1))) == F.EINVAL
     finally:
@@ -151,6 +152,7 @@ def test_default_vector_width_follows_dtype():
         h = F.fdtd_create(cfg(N=32, dtype=dt))
         assert F.fdtd_get_tuning(h).vz == vz
         assert F.fdtd_get_tuning(h).persist == 0
+        assert F.fdtd_get_tuning(h).vfuse == 1
         F.fdtd_destroy(h)
 
 

@@ -177,6 +177,8 @@ def test_bf16_state_is_independent_of_launch_shape_and_keeps_parity(N, tunings):
     kind, params = (F.POT_CORNELL, W.CORNELL_PARAMS) if N % 2 == 0 else (F.POT_HO, [1, 1.2, 0.8])
     states = []
     for t in tunings:
+        # the V table for every shape: the LDS-tile and 512-lane variants read it
+        t = tuple(t) + (0,) * (7 - len(t)) + (0, 0)
         s, *_ = gpu_run(N, L, "bf16", kind, params, 9, 40, tuning=t, parity=par, renorm=0)
         states.append(s.state())
         s.close()
