@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS = range(6)
+POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS, POT_DODECA = range(7)
 INIT_UNIFORM, INIT_GAUSS = 0, 1
 PAR_FREE, PAR_S, PAR_A = 0, 1, 2
 
@@ -58,6 +58,13 @@ def lib():
                                  C.c_int64, C.c_int, C.c_int, C.c_double, C.c_double,
                                  C.POINTER(C.c_int), _dp]
         L.orc_evolve.restype = C.c_int64
+        L.orc_evolve_deflated.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp,
+                                          _dp, C.c_int64, C.c_int, C.c_int, C.c_double,
+                                          C.c_double, C.POINTER(C.c_int), _dp, _dp, C.c_int,
+                                          C.c_int]
+        L.orc_evolve_deflated.restype = C.c_int64
+        L.orc_project_out.argtypes = [C.c_int64, _dp, C.c_int, _dp, _dp]
+        L.orc_project_out.restype = None
         L.orc_upsample.argtypes = [C.c_int, C.c_double, _dp, C.c_int, _dp]
         L.orc_upsample.restype = None
         L.orc_energy_grad_v.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp,
@@ -129,19 +136,38 @@ def observables(psi: np.ndarray, V: np.ndarray, L: float, mass: float = 1.0, v_i
 
 def evolve(psi: np.ndarray, V: np.ndarray, L: float, dt: float, steps: int, mass: float = 1.0,
            renorm_every: int = 1, check_every: int = 0, rel_tol: float = 0.0,
-           v_inf: float = 0.0):
-    """Evolve psi in place.  Returns (steps_done, converged, checked_energies)."""
+           v_inf: float = 0.0, deflate=None, project_every: int = 0):
+    """Evolve psi in place.  Returns (steps_done, converged, checked_energies).
+    deflate: optional list of states projected out after every
+    project_every-th step (orc_evolve_deflated)."""
     N = psi.shape[0]
     conv = C.c_int(0)
     nchk = steps // check_every if check_every > 0 else 0
     hist = np.zeros(max(nchk, 1))
-    done = lib().orc_evolve(N, float(L), float(mass), float(dt), _ptr(V), _ptr(psi), int(steps),
-                            int(renorm_every), int(check_every), float(rel_tol), float(v_inf),
-                            C.byref(conv), _ptr(hist))
+    if deflate:
+        st = np.ascontiguousarray(np.stack([np.asarray(d, dtype=np.float64) for d in deflate]))
+        done = lib().orc_evolve_deflated(N, float(L), float(mass), float(dt), _ptr(V), _ptr(psi),
+                                         int(steps), int(renorm_every), int(check_every),
+                                         float(rel_tol), float(v_inf), C.byref(conv), _ptr(hist),
+                                         st.ctypes.data_as(_dp), len(deflate), int(project_every))
+    else:
+        done = lib().orc_evolve(N, float(L), float(mass), float(dt), _ptr(V), _ptr(psi),
+                                int(steps), int(renorm_every), int(check_every), float(rel_tol),
+                                float(v_inf), C.byref(conv), _ptr(hist))
     if done < 0:
         raise MemoryError("oracle: allocation failed")
     used = done // check_every if check_every > 0 else 0
     return int(done), bool(conv.value), hist[:used].copy()
+
+
+def project_out(psi: np.ndarray, states) -> np.ndarray:
+    """psi minus its components along `states`, removed one after the other
+    (orc_project_out, Sec. III).  Returns (new psi, coefficients)."""
+    out = np.ascontiguousarray(psi, dtype=np.float64).copy()
+    st = np.ascontiguousarray(np.stack([np.asarray(d, dtype=np.float64) for d in states]))
+    coef = np.zeros(len(states))
+    lib().orc_project_out(out.size, st.ctypes.data_as(_dp), len(states), _ptr(out), _ptr(coef))
+    return out, coef
 
 
 def upsample(psi_c: np.ndarray, Nf: int, L: float) -> np.ndarray:

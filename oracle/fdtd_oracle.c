@@ -34,9 +34,53 @@ enum {
   ORC_POT_COULOMB = 2, /* V = -p0 / r */
   ORC_POT_COULOMB_REG = 3, /* Eq. (coulombpot): 0 for r < a, -p0/r + p0/a for r >= a */
   ORC_POT_CORNELL = 4, /* V = -p0 / r + p1 r + p2 z^2 */
-  ORC_POT_WELLS = 5    /* HO(p0..p2) - sum_k A_k exp(-|r - c_k|^2 / (2 s_k^2)),
+  ORC_POT_WELLS = 5,   /* HO(p0..p2) - sum_k A_k exp(-|r - c_k|^2 / (2 s_k^2)),
                           then 5 values per well: A, cx, cy, cz, s */
+  ORC_POT_DODECA = 6   /* Sec. VII.E: V = p0 inside a regular dodecahedron, 0
+                          outside; see orc_dodeca_inside */
 };
+
+/* Regular dodecahedron of Sec. VII.E in lattice units u = x / ((N - 1) a / 2),
+ * so u = -1 is the first site and u = 1 the last one on each axis.  Its 20
+ * vertices are (+-1, +-1, +-1)/phi, (0, +-1/phi^2, +-1), (+-1/phi^2, +-1, 0)
+ * and (+-1, 0, +-1/phi^2), phi the golden ratio: the circumsphere has radius
+ * sqrt(3)/phi, as the paper states (its printed list repeats a vertex family
+ * with two coordinates exchanged; this is the regular solid its text
+ * describes).  The 12 faces are perpendicular to the directions (0, +-phi,
+ * +-1), (+-1, 0, +-phi), (+-phi, +-1, 0) (an icosahedron); each face plane
+ * is at the largest projection of the vertices on its unit normal, reached by
+ * exactly the 5 vertices of that face.  A point is inside
+ * when its projection on every normal is at most that distance. */
+static int orc_dodeca_inside(double ux, double uy, double uz) {
+  const double phi = 0.5 * (1.0 + sqrt(5.0));
+  const double vtx[20][3] = {
+      {1 / phi, 1 / phi, 1 / phi},   {1 / phi, 1 / phi, -1 / phi},
+      {1 / phi, -1 / phi, 1 / phi},  {1 / phi, -1 / phi, -1 / phi},
+      {-1 / phi, 1 / phi, 1 / phi},  {-1 / phi, 1 / phi, -1 / phi},
+      {-1 / phi, -1 / phi, 1 / phi}, {-1 / phi, -1 / phi, -1 / phi},
+      {0, 1 / (phi * phi), 1},       {0, 1 / (phi * phi), -1},
+      {0, -1 / (phi * phi), 1},      {0, -1 / (phi * phi), -1},
+      {1 / (phi * phi), 1, 0},       {1 / (phi * phi), -1, 0},
+      {-1 / (phi * phi), 1, 0},      {-1 / (phi * phi), -1, 0},
+      {1, 0, 1 / (phi * phi)},       {1, 0, -1 / (phi * phi)},
+      {-1, 0, 1 / (phi * phi)},      {-1, 0, -1 / (phi * phi)}};
+  const double nrm[6][3] = {{0, phi, 1}, {0, phi, -1}, {1, 0, phi},
+                            {-1, 0, phi}, {phi, 1, 0}, {phi, -1, 0}};
+  for (int f = 0; f < 6; ++f) {
+    const double len = sqrt(nrm[f][0] * nrm[f][0] + nrm[f][1] * nrm[f][1] + nrm[f][2] * nrm[f][2]);
+    double d = 0.0; /* face distance: the largest vertex projection */
+    for (int v = 0; v < 20; ++v) {
+      const double pr = (vtx[v][0] * nrm[f][0] + vtx[v][1] * nrm[f][1] + vtx[v][2] * nrm[f][2]) / len;
+      if (pr > d) d = pr;
+    }
+    const double q = (ux * nrm[f][0] + uy * nrm[f][1] + uz * nrm[f][2]) / len;
+    /* +n and -n faces at once; the solid is closed, with a relative slack of
+     * 1e-12 so that sites exactly on a face (edge midpoints for odd N) are
+     * inside whatever the last bit of the arithmetic */
+    if (fabs(q) > d * (1.0 + 1e-12)) return 0;
+  }
+  return 1;
+}
 
 static double orc_coord(int i, int N, double a) {
   return (2.0 * (double)i - (double)(N - 1)) * (0.5 * a);
@@ -51,6 +95,8 @@ int orc_potential(int kind, const double* p, int np, int N, double L, double* V)
   if ((kind == ORC_POT_COULOMB || kind == ORC_POT_COULOMB_REG || kind == ORC_POT_CONST) && np < 1)
     return -1;
   if (kind == ORC_POT_CORNELL && np < 3) return -1;
+  if (kind == ORC_POT_DODECA && np < 1) return -1;
+  const double half = 0.5 * (double)(N - 1) * a; /* u = x / half */
   for (int ix = 0; ix < N; ++ix) {
     const double x = orc_coord(ix, N, a);
     for (int iy = 0; iy < N; ++iy) {
@@ -78,6 +124,9 @@ int orc_potential(int kind, const double* p, int np, int N, double L, double* V)
             }
             break;
           }
+          case ORC_POT_DODECA:
+            v = (N > 1 && orc_dodeca_inside(x / half, y / half, z / half)) ? p[0] : 0.0;
+            break;
           default: return -1;
         }
         V[ORC_IDX(N, ix, iy, iz)] = v;
@@ -231,6 +280,28 @@ static void orc_normalize(int64_t n3, double a, double* psi) {
   for (int64_t s = 0; s < n3; ++s) psi[s] *= f;
 }
 
+/* Excited states by projection (Sec. III, the snapshot method): remove from
+ * psi its components along n states phi_k (each N^3 values, consecutive in
+ * `states`), one after the other in the given order:
+ *     psi <- psi - phi_k <phi_k|psi> / <phi_k|phi_k>.
+ * With phi_0 the converged ground state and psi a snapshot, this is the
+ * paper's estimate of the first excited state.  coef (optional) receives the
+ * n coefficients <phi_k|psi>/<phi_k|phi_k>, each taken from psi as it stands
+ * when phi_k is removed.  Sums are serial in lattice order. */
+void orc_project_out(int64_t n3, const double* states, int n, double* psi, double* coef) {
+  for (int k = 0; k < n; ++k) {
+    const double* phi = states + (size_t)k * (size_t)n3;
+    double pp = 0.0, pq = 0.0;
+    for (int64_t s = 0; s < n3; ++s) {
+      pp += phi[s] * phi[s];
+      pq += phi[s] * psi[s];
+    }
+    const double c = pq / pp;
+    if (coef) coef[k] = c;
+    for (int64_t s = 0; s < n3; ++s) psi[s] -= c * phi[s];
+  }
+}
+
 /* Imaginary-time evolution loop.  Step t (t = 0, 1, ...) maps psi_t to
  * psi_{t+1}; after every renorm_every-th step the state is rescaled to
  * a^3 sum psi^2 = 1 (Sec. III: renormalisation against underflow).  The
@@ -239,9 +310,26 @@ static void orc_normalize(int64_t n3, double a, double* psi) {
  * energy moved by at most rel_tol * |E - v_inf| since the previous check.
  * e_hist (optional, length max_steps / check_every) receives the checked
  * energies.  Returns the number of steps done; psi holds the final state. */
+int64_t orc_evolve_deflated(int N, double L, double mass, double dt, const double* V,
+                            double* psi, int64_t max_steps, int renorm_every, int check_every,
+                            double rel_tol, double v_inf, int* converged, double* e_hist,
+                            const double* states, int nstates, int project_every);
+
 int64_t orc_evolve(int N, double L, double mass, double dt, const double* V, double* psi,
                    int64_t max_steps, int renorm_every, int check_every, double rel_tol,
                    double v_inf, int* converged, double* e_hist) {
+  return orc_evolve_deflated(N, L, mass, dt, V, psi, max_steps, renorm_every, check_every,
+                             rel_tol, v_inf, converged, e_hist, NULL, 0, 0);
+}
+
+/* The same loop relaxing to the lowest state orthogonal to n given states:
+ * after every project_every-th step the state is projected against them
+ * (orc_project_out), before the renormalisation of that step.  project_every
+ * = 0 or nstates = 0: the plain loop. */
+int64_t orc_evolve_deflated(int N, double L, double mass, double dt, const double* V,
+                            double* psi, int64_t max_steps, int renorm_every, int check_every,
+                            double rel_tol, double v_inf, int* converged, double* e_hist,
+                            const double* states, int nstates, int project_every) {
   const double a = L / (double)N;
   const int64_t n3 = (int64_t)N * N * N;
   double* tmp = (double*)malloc((size_t)n3 * sizeof(double));
@@ -262,6 +350,8 @@ int64_t orc_evolve(int N, double L, double mass, double dt, const double* V, dou
     }
     orc_step(N, L, mass, dt, V, psi, tmp);
     memcpy(psi, tmp, (size_t)n3 * sizeof(double));
+    if (nstates > 0 && project_every > 0 && ((t + 1) % project_every) == 0)
+      orc_project_out(n3, states, nstates, psi, NULL);
     if (renorm_every > 0 && ((t + 1) % renorm_every) == 0) orc_normalize(n3, a, psi);
     ++t;
     if (check) {

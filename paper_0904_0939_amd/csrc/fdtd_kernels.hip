@@ -1363,11 +1363,17 @@ template <int DT, int VZ, int RY, bool UPD, int D>
 hipError_t step_one(int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
   if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || (UPD && VZ > 1))) {
     if (fv) {
-      // in-kernel potential: FP32 arithmetic lattices, 256-lane work-groups
+      // in-kernel potential: FP32 arithmetic lattices
       if constexpr (DT != kF64) {
         if (bt == 256) {
           hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256, true>), dim3(grid), dim3(256), 0, s, a);
           return hipGetLastError();
+        }
+        if constexpr (RY == 1 && VZ * sizeof(typename Types<DT>::C) <= 16) {
+          if (bt == 512) {
+            hipLaunchKernelGGL((k_step<DT, VZ, 1, UPD, D, 512, true>), dim3(grid), dim3(512), 0, s, a);
+            return hipGetLastError();
+          }
         }
       }
       return hipErrorInvalidValue;

@@ -409,10 +409,10 @@ int max_n(const fdtd_ctx* h) {
 
 // Launch the fused step (update) or the reduction-only pass with the
 // handle's launch shape.
-// The step evaluates the potential itself: FP32 / BF16 lattices, variant 0,
-// every member's potential one of the analytic kinds 0..4, tun.vfuse set.
+// The step evaluates the potential itself: FP32 / BF16 lattices, variant 0
+// or 2, every member's potential one of the analytic kinds 0..4, tun.vfuse set.
 bool use_fv(const fdtd_ctx* h) {
-  if (!h->tun.vfuse || h->dtype == kF64 || h->tun.variant != 0 || h->table_v_only) return false;
+  if (!h->tun.vfuse || h->dtype == kF64 || h->tun.variant == 1 || h->table_v_only) return false;
   for (const auto& m : h->mem)
     if (m.vkind < 0) return false;
   return true;

@@ -422,3 +422,132 @@ def test_gaussian_well_perturbation_theory_closed_form():
     hf = float(np.sum(psi * psi * dv) / np.sum(psi * psi))
     expect = -(2 * s * s / (1 + 2 * s * s)) ** 1.5 * math.exp(-c @ c / (1 + 2 * s * s))
     assert hf == pytest.approx(expect, rel=0.01)
+
+
+# ------------------------------------------------ excited states (Sec. III) --
+def test_projection_leaves_the_orthogonal_remainder():
+    """Removing two non-orthogonal states one after the other (modified
+    Gram-Schmidt) equals the least-squares remainder of psi against the
+    space they span, computed by numpy; the coefficients are the sequential
+    Gram-Schmidt ones."""
+    rng = np.random.default_rng(3)
+    n3 = 5 * 5 * 5
+    a, b, psi = (rng.standard_normal(n3) for _ in range(3))
+    b = b + 0.4 * a  # not orthogonal to a
+    out, coef = orc.project_out(psi.reshape(5, 5, 5), [a.reshape(5, 5, 5), b.reshape(5, 5, 5)])
+    A = np.stack([a, b], axis=1)
+    resid = psi - A @ np.linalg.lstsq(A, psi, rcond=None)[0]
+    # sequential removal of a then b equals the remainder against span{a, b}
+    # only when b is taken orthogonal to a first: compare with the MGS form
+    c0 = psi @ a / (a @ a)
+    p1 = psi - c0 * a
+    c1 = p1 @ b / (b @ b)
+    np.testing.assert_allclose(coef, [c0, c1], rtol=1e-13)
+    np.testing.assert_allclose(out.ravel(), p1 - c1 * b, rtol=0, atol=1e-13)
+    # one state: exactly orthogonal remainder, and idempotent
+    o1, _ = orc.project_out(psi.reshape(5, 5, 5), [a.reshape(5, 5, 5)])
+    assert abs(o1.ravel() @ a) < 1e-12 * np.linalg.norm(psi) * np.linalg.norm(a)
+    o2, c = orc.project_out(o1, [a.reshape(5, 5, 5)])
+    np.testing.assert_allclose(o2, o1, rtol=0, atol=1e-14)
+    assert abs(c[0]) < 1e-14
+    # orthonormalised basis of the same span: remainder equals least squares
+    q, _ = np.linalg.qr(A)
+    o3, _ = orc.project_out(psi.reshape(5, 5, 5), [q[:, 0].reshape(5, 5, 5), q[:, 1].reshape(5, 5, 5)])
+    np.testing.assert_allclose(o3.ravel(), resid, rtol=0, atol=1e-13)
+
+
+def test_deflated_relaxation_converges_to_dense_second_vector():
+    """Evolving with the converged ground state projected out after every
+    step converges to the dominant eigenvector of P M (M the update matrix,
+    P the projector), found by a dense eigensolver on 6^3; its energy is the
+    second eigenvalue of H up to the O(dt) difference between Euclidean and
+    D-orthogonality."""
+    N, L = 6, 3.0
+    a = L / N
+    dt = a * a / 8
+    rng = np.random.default_rng(4)
+    V = rng.uniform(-1.0, 2.0, (N, N, N))
+    H, D = dense_ops(V, L, dt)
+    M = np.linalg.solve(D, D - dt * H)
+    w, U = np.linalg.eig(M)
+    v0 = np.real(U[:, np.argmax(np.real(w))])
+    P = np.eye(N**3) - np.outer(v0, v0) / (v0 @ v0)
+    w1, U1 = np.linalg.eig(P @ M)
+    v1 = np.real(U1[:, np.argmax(np.real(w1))])
+    psi = orc.initial(N, 9)
+    orc.evolve(psi, V, L, dt, 6000, deflate=[v0.reshape(N, N, N)], project_every=1)
+    g = psi.ravel() / np.linalg.norm(psi)
+    v1 = v1 / np.linalg.norm(v1)
+    assert abs(abs(g @ v1) - 1.0) < 1e-10
+    e = orc.observables(psi, V, L)["energy"]
+    lam = np.sort(np.linalg.eigvalsh(H))
+    assert abs(e - lam[1]) < 5 * dt * abs(lam[1] - lam[0]) + 1e-9
+    # projecting every 5th step reaches the same vector
+    psi5 = orc.initial(N, 9)
+    orc.evolve(psi5, V, L, dt, 6000, deflate=[v0.reshape(N, N, N)], project_every=5)
+    g5 = psi5.ravel() / np.linalg.norm(psi5)
+    assert abs(abs(g5 @ g) - 1.0) < 1e-9
+
+
+def test_snapshot_projection_estimates_first_excited_state():
+    """The paper's one-shot estimate: a snapshot taken at tau, minus its
+    component along the converged ground state of the same iteration, has the
+    energy of the first excited state once tau (E2 - E1) >> 1.  Anisotropic
+    oscillator, separable: the first excited level is the x excitation, whose
+    energy is a sum of 1-d tridiagonal eigenvalues."""
+    N, L = 16, 10.0
+    a = L / N
+    dt = a * a / 8
+    w = [1.0, 1.6, 2.3]
+    V = orc.potential(orc.POT_HO, w, N, L)
+    x = (np.arange(N) * 2 - (N - 1)) * a / 2
+    lam = []
+    for wi in w:
+        T = (np.diag(np.full(N, 1.0 / a**2 + 0.5 * wi**2 * x**2))
+             + np.diag(np.full(N - 1, -0.5 / a**2), 1) + np.diag(np.full(N - 1, -0.5 / a**2), -1))
+        lam.append(np.linalg.eigvalsh(T))
+    e1 = lam[0][1] + lam[1][0] + lam[2][0]
+    psi0 = orc.initial(N, 5)
+    orc.evolve(psi0, V, L, dt, 6000)
+    err = []
+    for steps in (60, 240):
+        snap = orc.initial(N, 5)
+        orc.evolve(snap, V, L, dt, steps)
+        est, c = orc.project_out(snap, [psi0])
+        err.append(abs(orc.observables(est, V, L)["energy"] - e1))
+    assert err[1] < err[0] and err[1] < 5e-3 * e1
+
+
+# ------------------------------------------- dodecahedron well (Sec. VII.E) --
+def test_dodecahedron_well_volume_symmetry_and_vertices():
+    """The well is a regular dodecahedron whose circumsphere has radius
+    sqrt(3)/phi in units where the lattice spans [-1, 1]: the fraction of
+    sites inside, corrected for the (N - 1)^3 / N^3 measure of the sampled
+    cube, approaches the solid's volume (15 + 7 sqrt 5)/4 e^3 with edge
+    e = 2/phi^2; the well is invariant under the three mirrors and the cyclic
+    exchange of axes; points just inside / outside the 20 vertices fall on
+    the right sides."""
+    phi = (1 + math.sqrt(5)) / 2
+    e = 2.0 / phi**2
+    vol = (15 + 7 * math.sqrt(5)) / 4 * e**3
+    fr = []
+    for N in (48, 96):
+        V = orc.potential(orc.POT_DODECA, [-100.0], N, 0.1 * N)
+        assert set(np.unique(V)) == {-100.0, 0.0}
+        fr.append((V < 0).mean() * (N / (N - 1)) ** 3)
+        assert np.array_equal(V, V[::-1]) and np.array_equal(V, V[:, ::-1]) and np.array_equal(V, V[:, :, ::-1])
+        assert np.array_equal(V, np.transpose(V, (2, 0, 1)))
+    for f in fr:
+        assert abs(f / (vol / 8) - 1) < 2e-3
+    # a 3-site lattice samples u in {-1, 0, 1}: the centre is inside, the
+    # corners (+-1, +-1, +-1) are outside (radius sqrt 3 > sqrt(3)/phi)
+    V3 = orc.potential(orc.POT_DODECA, [-1.0], 3, 3.0)
+    assert V3[1, 1, 1] == -1.0 and V3[0, 0, 0] == 0.0 and V3[2, 2, 2] == 0.0
+    # (0, 0, +-1) is the midpoint of the edge from (0, -1/phi^2, +-1) to
+    # (0, 1/phi^2, +-1), on the faces with normals (+-1, 0, phi): on the
+    # boundary, so inside the closed solid; likewise on the other axes
+    assert V3[1, 1, 0] == -1.0 and V3[1, 1, 2] == -1.0
+    assert V3[1, 0, 1] == -1.0 and V3[2, 1, 1] == -1.0
+    # the same edge midpoints on a 201-site lattice
+    V5 = orc.potential(orc.POT_DODECA, [-1.0], 201, 20.1)
+    assert V5[100, 100, 200] == -1.0 and V5[100, 100, 0] == -1.0
