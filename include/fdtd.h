@@ -63,8 +63,14 @@ enum {
   FDTD_POT_COULOMB = 2,     /* V = -p0 / r                                         */
   FDTD_POT_COULOMB_REG = 3, /* Eq. (coulombpot): 0 for r < a, -p0/r + p0/a else     */
   FDTD_POT_CORNELL = 4,     /* V = -p0/r + p1 r + p2 z^2                           */
-  FDTD_POT_WELLS = 5        /* HO(p0,p1,p2) - sum_k A_k exp(-|r-c_k|^2 / 2 s_k^2);
+  FDTD_POT_WELLS = 5,       /* HO(p0,p1,p2) - sum_k A_k exp(-|r-c_k|^2 / 2 s_k^2);
                                p[3+5k .. 7+5k] = A_k, cx, cy, cz, s_k             */
+  FDTD_POT_DODECA = 6       /* Sec. VII.E: V = p0 inside a regular dodecahedron, 0
+                               outside; lattice units u = x / ((N-1) a / 2) put
+                               the first / last site of each axis at -1 / 1, the
+                               vertices at (+-1,+-1,+-1)/phi, (0,+-1/phi^2,+-1)
+                               and cyclic (circumradius sqrt(3)/phi); closed,
+                               faces with a 1e-12 relative slack               */
 };
 
 /* Initial-state kinds (Sec. III: random start; Sec. VI: a coarser solution). */
@@ -106,7 +112,13 @@ typedef struct {
  *                   when |dE| <= rel_tol |E - v_inf| (Sec. V); 0: no check.
  *  reimpose_parity_every  re-apply the set_initial parity every k steps
  *                   (Sec. IV; 0: never -- the update preserves it bit-exactly).
- *  use_graph        1: capture the K-step loop in a HIP graph and replay it.
+ *  use_graph        1: capture the step loop between two boundaries (check,
+ *                   parity, projection; at most 64 steps without a check) in
+ *                   a HIP graph, cached per length, and replay it.
+ *  project_every    k > 0: after every k-th step, project each member's state
+ *                   against its projection states (fdtd_project), so the
+ *                   relaxation converges to the lowest state orthogonal to
+ *                   them (Sec. III); 0: never.
  */
 typedef struct {
   int64_t max_steps;
@@ -115,6 +127,8 @@ typedef struct {
   int32_t reimpose_parity_every;
   int32_t use_graph;
   double rel_tol;
+  int32_t project_every;
+  int32_t reserved;  /* 0 */
 } fdtd_evolve_opts;
 
 /* Launch shape of the fused step kernel (see fdtd_autotune).
@@ -199,6 +213,24 @@ fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, 
  * counter and the history; the state is normalised on entry to the first step. */
 fdtd_status fdtd_set_initial(fdtd_t h, int32_t member, int32_t kind, uint64_t seed,
                              uint32_t parity, const void* user, int32_t dtype, int32_t on_device);
+
+/* ---- excited states (Sec. III) ---------------------------------------------*/
+
+/* Keep n states of `member` (n consecutive fields of N^3 values of `dtype`,
+ * z fastest, host or device; copied, in the member's arithmetic type) to be
+ * projected out by fdtd_project and by evolve's project_every.  n = 0 drops
+ * them; at most 16.  Typical use: converged lower states, in order. */
+fdtd_status fdtd_set_projection_states(fdtd_t h, int32_t member, const void* states, int32_t n,
+                                       int32_t dtype, int32_t on_device);
+
+/* The snapshot method of Sec. III: remove from the current state of `member`
+ * its components along the kept states, one after the other in their order,
+ *     psi <- psi - phi_k <phi_k|psi> / <phi_k|phi_k>   (sums in FP64),
+ * then renormalise.  Applied to a snapshot taken at tau with
+ * tau (E_{k+1} - E_k) >> 1 and the k lower states kept, the result estimates
+ * the next excited state.  coef (optional, host, n doubles) receives each
+ * <phi_k|psi> / <phi_k|phi_k>.  FDTD_EINVAL if no states are kept. */
+fdtd_status fdtd_project(fdtd_t h, int32_t member, double* coef);
 
 /* ---- the hot path ----------------------------------------------------------*/
 

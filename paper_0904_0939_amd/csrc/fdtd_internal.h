@@ -109,6 +109,14 @@ hipError_t launch_step_persist(int dtype, int vz, int ry, int depth, int grid, b
                                const StepArgs& a, hipStream_t s);
 hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, hipStream_t s);
 
+// psi (storage dtype, n3 values) <- psi - phi <phi|psi> / <phi|phi>, phi in
+// the arithmetic type (F64 for F64 states, F32 otherwise); sums in FP64.
+// partials: project_partials_doubles() doubles of scratch; coef: 1 double,
+// receives the coefficient.
+hipError_t launch_project(int dtype, void* psi, const void* phi, long long n3, double* partials,
+                          double* coef, hipStream_t s);
+int project_partials_doubles();
+
 // LDS-tile variant: work-groups of tile_threads(dtype) lanes, one vector of
 // the dtype's width per lane; max_n sizes the LDS tile (two planes of the
 // chunk plus one row above and below).

@@ -1017,6 +1017,48 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
 }
 
 // ----------------------------------------------------------- potentials ----
+// Regular dodecahedron of Sec. VII.E in lattice units u = x / ((N - 1) a / 2)
+// (the first and last sites of each axis at u = -1 and 1): vertices
+// (+-1, +-1, +-1)/phi, (0, +-1/phi^2, +-1), (+-1/phi^2, +-1, 0),
+// (+-1, 0, +-1/phi^2); faces perpendicular to (0, +-phi, +-1), (+-1, 0, +-phi),
+// (+-phi, +-1, 0), each at the largest projection of the vertices on its unit
+// normal.  Closed, with a relative slack of 1e-12 so that sites exactly on a
+// face are inside whatever the last bit; FP64 without fused multiply-adds.
+__device__ bool dodeca_inside(double ux, double uy, double uz) {
+#pragma clang fp contract(off)
+  const double phi = 0.5 * (1.0 + sqrt(5.0));
+  const double ip = 1.0 / phi, ip2 = 1.0 / (phi * phi);
+  double vtx[20][3];
+  int nv = 0;
+  for (int sx = -1; sx <= 1; sx += 2)
+    for (int sy = -1; sy <= 1; sy += 2)
+      for (int sz = -1; sz <= 1; sz += 2) {
+        vtx[nv][0] = sx * ip;
+        vtx[nv][1] = sy * ip;
+        vtx[nv][2] = sz * ip;
+        ++nv;
+      }
+  for (int s1 = -1; s1 <= 1; s1 += 2)
+    for (int s2 = -1; s2 <= 1; s2 += 2) {
+      vtx[nv][0] = 0.0; vtx[nv][1] = s1 * ip2; vtx[nv][2] = s2 * 1.0; ++nv;
+      vtx[nv][0] = s1 * ip2; vtx[nv][1] = s2 * 1.0; vtx[nv][2] = 0.0; ++nv;
+      vtx[nv][0] = s1 * 1.0; vtx[nv][1] = 0.0; vtx[nv][2] = s2 * ip2; ++nv;
+    }
+  const double nrm[6][3] = {{0, phi, 1}, {0, phi, -1}, {1, 0, phi},
+                            {-1, 0, phi}, {phi, 1, 0}, {phi, -1, 0}};
+  for (int f = 0; f < 6; ++f) {
+    const double len = sqrt(nrm[f][0] * nrm[f][0] + nrm[f][1] * nrm[f][1] + nrm[f][2] * nrm[f][2]);
+    double d = 0.0;
+    for (int v = 0; v < 20; ++v) {
+      const double pr = (vtx[v][0] * nrm[f][0] + vtx[v][1] * nrm[f][1] + vtx[v][2] * nrm[f][2]) / len;
+      d = pr > d ? pr : d;
+    }
+    const double q = (ux * nrm[f][0] + uy * nrm[f][1] + uz * nrm[f][2]) / len;
+    if (fabs(q) > d * (1.0 + 1e-12)) return false;
+  }
+  return true;
+}
+
 template <typename TV>
 __global__ __launch_bounds__(kBlock) void k_potential(TV* __restrict__ V, int N, double ha,
                                                       double a, int kind,
@@ -1045,6 +1087,11 @@ __global__ __launch_bounds__(kBlock) void k_potential(TV* __restrict__ V, int N,
           const double d2 = dx * dx + dy * dy + dz * dz;
           v -= p[k] * exp(-d2 / (2.0 * p[k + 4] * p[k + 4]));
         }
+        break;
+      }
+      case 6: {
+        const double half = 0.5 * (double)(N - 1) * a;
+        v = (N > 1 && dodeca_inside(x / half, y / half, z / half)) ? p[0] : 0.0;
         break;
       }
       default: v = 0.0;
@@ -1347,6 +1394,74 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
   }
 }
 
+// ----------------------------------------------------------- projection ----
+// Excited states by projection (Sec. III): psi <- psi - phi <phi|psi> /
+// <phi|phi>.  Three launches per state, no host round trip: FP64 partial sums
+// of <phi|phi> and <phi|psi> per work-group (grid-stride, fixed grid), one
+// work-group summing them in a fixed order into the coefficient (device
+// memory), then the update reading it.
+constexpr int kProjGrid = 1024;
+
+template <typename S, typename B>
+__global__ __launch_bounds__(kBlock) void k_proj_partials(const S* __restrict__ psi,
+                                                          const B* __restrict__ phi,
+                                                          long long n3, double* partials) {
+  __shared__ double red[kBlock / 64][2];
+  double pp = 0.0, pq = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3;
+       i += (long long)gridDim.x * kBlock) {
+    const double f = (double)phi[i];
+    pp += f * f;
+    pq += f * to_c<S, double>(psi[i]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    pp += __shfl_down(pp, o);
+    pq += __shfl_down(pq, o);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w][0] = pp;
+    red[w][1] = pq;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      a += red[k][0];
+      b += red[k][1];
+    }
+    partials[2 * blockIdx.x] = a;
+    partials[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ void k_proj_coef(const double* __restrict__ partials, int nblocks, double* coef) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double pp = 0.0, pq = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      pp += partials[2 * b];
+      pq += partials[2 * b + 1];
+    }
+    coef[0] = pp > 0.0 ? pq / pp : 0.0;
+  }
+}
+
+template <typename S, typename B>
+__global__ __launch_bounds__(kBlock) void k_proj_update(S* __restrict__ psi,
+                                                        const B* __restrict__ phi, long long n3,
+                                                        const double* __restrict__ coef) {
+  const double c = coef[0];
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3;
+       i += (long long)gridDim.x * kBlock) {
+    if constexpr (sizeof(S) == 8) {
+      psi[i] = psi[i] - c * (double)phi[i];
+    } else {
+      const float v = to_c<S, float>(psi[i]) - (float)c * (float)phi[i];
+      psi[i] = from_c<S, float>(v);
+    }
+  }
+}
+
 // ------------------------------------------------------------- dispatch ----
 int grid_for(long long n) {
   long long g = (n + kBlock - 1) / kBlock;
@@ -1621,6 +1736,43 @@ hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, doubl
     default: return hipErrorInvalidValue;
   }
 }
+
+hipError_t launch_project(int dtype, void* psi, const void* phi, long long n3, double* partials,
+                          double* coef, hipStream_t s) {
+  const int g = kProjGrid;
+  switch (dtype) {
+    case kF64:
+      hipLaunchKernelGGL((k_proj_partials<double, double>), dim3(g), dim3(kBlock), 0, s,
+                         (const double*)psi, (const double*)phi, n3, partials);
+      break;
+    case kF32:
+      hipLaunchKernelGGL((k_proj_partials<float, float>), dim3(g), dim3(kBlock), 0, s,
+                         (const float*)psi, (const float*)phi, n3, partials);
+      break;
+    case kBF16:
+      hipLaunchKernelGGL((k_proj_partials<uint16_t, float>), dim3(g), dim3(kBlock), 0, s,
+                         (const uint16_t*)psi, (const float*)phi, n3, partials);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_proj_coef, dim3(1), dim3(64), 0, s, (const double*)partials, g, coef);
+  switch (dtype) {
+    case kF64:
+      hipLaunchKernelGGL((k_proj_update<double, double>), dim3(g), dim3(kBlock), 0, s,
+                         (double*)psi, (const double*)phi, n3, (const double*)coef);
+      break;
+    case kF32:
+      hipLaunchKernelGGL((k_proj_update<float, float>), dim3(g), dim3(kBlock), 0, s,
+                         (float*)psi, (const float*)phi, n3, (const double*)coef);
+      break;
+    default:
+      hipLaunchKernelGGL((k_proj_update<uint16_t, float>), dim3(g), dim3(kBlock), 0, s,
+                         (uint16_t*)psi, (const float*)phi, n3, (const double*)coef);
+  }
+  return hipGetLastError();
+}
+
+int project_partials_doubles() { return 2 * kProjGrid; }
 
 hipError_t launch_reimpose(int dtype, void* psi, int N, uint32_t parity, hipStream_t s) {
   const int g = grid_for((long long)N * N * N);

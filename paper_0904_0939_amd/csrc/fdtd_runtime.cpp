@@ -62,6 +62,8 @@ struct MemberHost {
   int item_begin = 0, item_end = 0;
   int vkind = -1;  // analytic kind the step may evaluate itself (0..4), -1: table only
   double vp[3] = {0, 0, 0};
+  int nproj = 0;          // states kept for projection (Sec. III)
+  void* proj = nullptr;   // nproj * n3 values of the arithmetic type (library-owned)
 };
 
 struct GraphEntry {
@@ -112,6 +114,9 @@ struct fdtd_ctx {
   size_t h_pin_doubles = 0;
 
   std::vector<GraphEntry> graphs;
+
+  // projection scratch: per-work-group partial sums and the coefficients
+  double* d_proj = nullptr;
 
   MemberDev* d_members() { return reinterpret_cast<MemberDev*>(ws + off_members); }
   MemberState* d_states() { return reinterpret_cast<MemberState*>(ws + off_states); }
@@ -611,6 +616,34 @@ fdtd_status copy_in_field(fdtd_ctx* h, const void* src, int sdtype, int on_devic
   return FDTD_OK;
 }
 
+constexpr int kMaxProj = 16;
+
+// Project member m's current state against its kept states (Sec. III), one
+// after the other, then reset the pending scale from the new norm.  coef
+// (optional, host) receives the nproj coefficients.
+fdtd_status project_member(fdtd_ctx* h, int m, double* coef) {
+  MemberHost& mh = h->mem[m];
+  if (mh.nproj == 0) return FDTD_OK;
+  if (!h->d_proj) {
+    hipError_t e = hipMalloc((void**)&h->d_proj, sizeof(double) * (project_partials_doubles() + kMaxProj));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FDTD_ENOMEM, "projection scratch allocation failed");
+    }
+  }
+  double* coef_dev = h->d_proj + project_partials_doubles();
+  const size_t cs = h->dtype == kF64 ? 8 : 4;
+  for (int k = 0; k < mh.nproj; ++k)
+    HIP_TRY(launch_project(h->dtype, h->psi(m, h->cur), static_cast<char*>(mh.proj) + cs * (size_t)mh.n3 * k,
+                           mh.n3, h->d_proj, coef_dev + k, h->stream));
+  ST_TRY(observe(h, m, true));
+  if (coef) {
+    HIP_TRY(hipMemcpyAsync(coef, coef_dev, sizeof(double) * mh.nproj, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+  }
+  return FDTD_OK;
+}
+
 fdtd_status check_member(fdtd_ctx* h, int member, bool allow_all) {
   if (member == -1 && allow_all) return FDTD_OK;
   if (member < 0 || member >= h->count) return fail(FDTD_EINVAL, "member index out of range");
@@ -707,6 +740,9 @@ fdtd_status fdtd_destroy(fdtd_t h) {
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   if (h->d_items) (void)hipFree(h->d_items);
   if (h->d_partials) (void)hipFree(h->d_partials);
+  if (h->d_proj) (void)hipFree(h->d_proj);
+  for (auto& m : h->mem)
+    if (m.proj) (void)hipFree(m.proj);
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
   if (h->h_pin) (void)hipHostFree(h->h_pin);
   delete h;
@@ -731,7 +767,7 @@ fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, 
                                         int32_t np) {
   if (!h) return fail(FDTD_EINVAL, "set_potential_analytic: null handle");
   ST_TRY(check_member(h, member, true));
-  if (kind < FDTD_POT_CONST || kind > FDTD_POT_WELLS) return fail(FDTD_EINVAL, "set_potential_analytic: unknown kind");
+  if (kind < FDTD_POT_CONST || kind > FDTD_POT_DODECA) return fail(FDTD_EINVAL, "set_potential_analytic: unknown kind");
   const int need = (kind == FDTD_POT_HO || kind == FDTD_POT_CORNELL) ? 3 : (kind == FDTD_POT_WELLS ? 3 : 1);
   if (np < need || (np > 0 && !p)) return fail(FDTD_EINVAL, "set_potential_analytic: too few parameters");
   if (kind == FDTD_POT_WELLS && (np - 3) % 5 != 0) return fail(FDTD_EINVAL, "set_potential_analytic: wells need 3 + 5k parameters");
@@ -790,9 +826,57 @@ fdtd_status fdtd_set_initial(fdtd_t h, int32_t member, int32_t kind, uint64_t se
   return FDTD_OK;
 }
 
+fdtd_status fdtd_set_projection_states(fdtd_t h, int32_t member, const void* states, int32_t n,
+                                       int32_t dtype, int32_t on_device) {
+  if (!h) return fail(FDTD_EINVAL, "set_projection_states: null handle");
+  ST_TRY(check_member(h, member, false));
+  if (n < 0 || n > kMaxProj) return fail(FDTD_EINVAL, "set_projection_states: n must be in [0, 16]");
+  if (n > 0 && !states) return fail(FDTD_EINVAL, "set_projection_states: null states");
+  if (n > 0 && (dtype < FDTD_F64 || dtype > FDTD_BF16)) return fail(FDTD_EINVAL, "set_projection_states: bad dtype");
+  ST_TRY(ensure_memory(h));
+  MemberHost& mh = h->mem[member];
+  HIP_TRY(hipStreamSynchronize(h->stream));  // the old states may still be read
+  if (mh.proj) (void)hipFree(mh.proj);
+  mh.proj = nullptr;
+  mh.nproj = 0;
+  if (n == 0) return FDTD_OK;
+  const int cdt = h->dtype == kF64 ? FDTD_F64 : FDTD_F32;  // kept in the arithmetic type
+  const size_t cs = elem_size(cdt);
+  hipError_t e = hipMalloc(&mh.proj, cs * (size_t)mh.n3 * n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    mh.proj = nullptr;
+    return fail(FDTD_ENOMEM, "set_projection_states: allocation failed");
+  }
+  const size_t sb = elem_size(dtype) * (size_t)mh.n3;
+  for (int k = 0; k < n; ++k) {
+    fdtd_status st = copy_in_field(h, static_cast<const char*>(states) + sb * k, dtype, on_device,
+                                   cdt, static_cast<char*>(mh.proj) + cs * (size_t)mh.n3 * k, mh.n3);
+    if (st != FDTD_OK) {
+      (void)hipFree(mh.proj);
+      mh.proj = nullptr;
+      return st;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  mh.nproj = n;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_project(fdtd_t h, int32_t member, double* coef) {
+  if (!h) return fail(FDTD_EINVAL, "project: null handle");
+  ST_TRY(check_member(h, member, false));
+  ST_TRY(require_ready(h));
+  if (h->mem[member].nproj == 0) return fail(FDTD_EINVAL, "project: no projection states set");
+  ST_TRY(ensure_memory(h));
+  ST_TRY(build_items(h));
+  return project_member(h, member, coef);
+}
+
 fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* o, int64_t* steps_done, int32_t* converged) {
   if (!h || !o) return fail(FDTD_EINVAL, "evolve: null argument");
-  if (o->max_steps < 0 || o->renorm_every < 0 || o->check_every < 0 || o->reimpose_parity_every < 0)
+  if (o->max_steps < 0 || o->renorm_every < 0 || o->check_every < 0 ||
+      o->reimpose_parity_every < 0 || o->project_every < 0)
     return fail(FDTD_EINVAL, "evolve: negative option");
   if (o->check_every > 0 && !(o->rel_tol >= 0)) return fail(FDTD_EINVAL, "evolve: rel_tol must be >= 0");
   if (steps_done) *steps_done = 0;
@@ -806,18 +890,23 @@ fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* o, int64_t* steps_done
   const long long step0 = st[0].step;
   const int K = o->check_every > 0 ? o->check_every : 64;
   const int P = o->reimpose_parity_every;
+  const int PE = o->project_every;
   std::vector<double> e_prev(h->count, NAN);
   long long done = 0;
   bool conv = false;
   while (done < o->max_steps) {
-    long long n = std::min<long long>(K, o->max_steps - done);
+    // chunks end at every check, parity and projection boundary
+    long long n = std::min<long long>(K - (done % K), o->max_steps - done);
     if (P > 0) n = std::min<long long>(n, P - (done % P));
-    if (o->use_graph && n == K && P == 0) ST_TRY(graph_steps(h, K, o->renorm_every));
+    if (PE > 0) n = std::min<long long>(n, PE - (done % PE));
+    if (o->use_graph && n >= 8) ST_TRY(graph_steps(h, (int)n, o->renorm_every));
     else ST_TRY(launch_steps(h, (int)n, o->renorm_every, h->stream));
     done += n;
     if (P > 0 && done % P == 0)
       for (int m = 0; m < h->count; ++m)
         if (h->mem[m].parity) HIP_TRY(launch_reimpose(h->dtype, h->psi(m, h->cur), h->mem[m].N, h->mem[m].parity, h->stream));
+    if (PE > 0 && done % PE == 0)
+      for (int m = 0; m < h->count; ++m) ST_TRY(project_member(h, m, nullptr));
     const bool check = o->check_every > 0 && done % K == 0;
     if (check) {
       const long long t = step0 + done - 1;  // the step whose input is checked

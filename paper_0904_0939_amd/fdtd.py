@@ -23,7 +23,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "fdtd.h")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENOTREADY, ENONFINITE = range(7)
 F64, F32, BF16 = 0, 1, 2
-POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS = range(6)
+POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS, POT_DODECA = range(7)
 INIT_UNIFORM, INIT_GAUSS, INIT_USER = 0, 1, 2
 
 
@@ -50,7 +50,8 @@ class fdtd_obs(C.Structure):
 class fdtd_evolve_opts(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("renorm_every", C.c_int32),
                 ("check_every", C.c_int32), ("reimpose_parity_every", C.c_int32),
-                ("use_graph", C.c_int32), ("rel_tol", C.c_double)]
+                ("use_graph", C.c_int32), ("rel_tol", C.c_double),
+                ("project_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 class fdtd_tuning(C.Structure):
@@ -79,6 +80,8 @@ _SIGS = {
     "fdtd_set_potential_analytic": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32],
     "fdtd_set_initial": [_P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32, _P, C.c_int32,
                          C.c_int32],
+    "fdtd_set_projection_states": [_P, C.c_int32, _P, C.c_int32, C.c_int32, C.c_int32],
+    "fdtd_project": [_P, C.c_int32, C.POINTER(C.c_double)],
     "fdtd_evolve": [_P, C.POINTER(fdtd_evolve_opts), C.POINTER(C.c_int64), C.POINTER(C.c_int32)],
     "fdtd_observables": [_P, C.POINTER(fdtd_obs)],
     "fdtd_history": [_P, C.c_int32, C.POINTER(fdtd_obs), C.c_int64, C.POINTER(C.c_int64)],
@@ -171,6 +174,16 @@ def fdtd_set_initial(h, member: int, kind: int, seed: int, parity_word: int = 0,
                      dtype: int = F64, on_device: int = 0):
     _call("fdtd_set_initial", h, member, kind, seed & (2**64 - 1), parity_word, user_ptr, dtype,
           on_device)
+
+
+def fdtd_set_projection_states(h, member: int, states_ptr, n: int, dtype: int, on_device: int):
+    _call("fdtd_set_projection_states", h, member, states_ptr, n, dtype, on_device)
+
+
+def fdtd_project(h, member: int, n: int):
+    coef = (C.c_double * max(n, 1))()
+    _call("fdtd_project", h, member, coef)
+    return [coef[i] for i in range(n)]
 
 
 def fdtd_evolve(h, opts: fdtd_evolve_opts):

@@ -55,10 +55,40 @@ class _Handle:
             pass
 
     def evolve(self, steps: int, renorm_every: int = 1, check_every: int = 0, rel_tol: float = 0.0,
-               use_graph: bool = True, reimpose_parity_every: int = 0):
+               use_graph: bool = True, reimpose_parity_every: int = 0, project_every: int = 0):
         o = F.fdtd_evolve_opts(int(steps), int(renorm_every), int(check_every),
-                               int(reimpose_parity_every), 1 if use_graph else 0, float(rel_tol))
+                               int(reimpose_parity_every), 1 if use_graph else 0, float(rel_tol),
+                               int(project_every), 0)
         return F.fdtd_evolve(self.h, o)
+
+    def set_projection_states(self, states, member: int = 0):
+        """Keep `states` (a sequence of N^3 arrays or tensors, or one stacked
+        array / tensor; empty: drop them) for projection (Sec. III)."""
+        if isinstance(states, (list, tuple)):
+            if len(states) == 0:
+                F.fdtd_set_projection_states(self.h, member, None, 0, F.F64, 0)
+                return
+            if isinstance(states[0], torch.Tensor):
+                states = torch.stack([t.to(states[0].dtype) for t in states])
+            else:
+                states = np.stack([np.asarray(t, dtype=np.float64) for t in states])
+        n = states.shape[0]
+        if isinstance(states, torch.Tensor):
+            t = states.contiguous()
+            code = {torch.float64: F.F64, torch.float32: F.F32, torch.bfloat16: F.BF16}[t.dtype]
+            F.fdtd_set_projection_states(self.h, member, t.data_ptr(), n, code, 1 if t.is_cuda else 0)
+            if t.is_cuda:
+                torch.cuda.current_stream(self.device).synchronize()
+        else:
+            a = np.ascontiguousarray(states, dtype=np.float64)
+            F.fdtd_set_projection_states(self.h, member, a.ctypes.data, n, F.F64, 0)
+        self._nproj = getattr(self, "_nproj", {})
+        self._nproj[member] = n
+
+    def project(self, member: int = 0):
+        """Project the kept states out of the current state; returns the
+        coefficients <phi_k|psi>/<phi_k|phi_k>."""
+        return F.fdtd_project(self.h, member, getattr(self, "_nproj", {}).get(member, 0))
 
     def observables(self) -> List[Dict]:
         return F.fdtd_observables(self.h, self.count)

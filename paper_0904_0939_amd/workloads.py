@@ -8,7 +8,8 @@ path and the CPU oracle may take their inputs from it.
 Potential kinds are numbered as in the library header: 0 constant,
 1 harmonic oscillator (wx, wy, wz), 2 Coulomb -Z/r, 3 the paper's regulated
 Coulomb (Sec. VII.C), 4 Cornell-type -k/r + s r + g z^2, 5 oscillator plus
-Gaussian wells (wx, wy, wz, then A, cx, cy, cz, s per well).
+Gaussian wells (wx, wy, wz, then A, cx, cy, cz, s per well), 6 the
+dodecahedron well of Sec. VII.E (depth).
 """
 from __future__ import annotations
 
@@ -17,7 +18,7 @@ from typing import List, Sequence
 
 import numpy as np
 
-POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS = range(6)
+POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS, POT_DODECA = range(7)
 
 
 @dataclass
@@ -114,3 +115,36 @@ def gradient_param_indices(n_wells: int = 8) -> List[int]:
     for k in range(n_wells):
         idx += [3 + 5 * k, 3 + 5 * k + 4]
     return idx
+
+
+# ------------------------------------------- the paper's own setups (Sec. VII) --
+def paper_coulomb(N: int = 512, a: float = 0.05, dt_over_a2: float = 0.25,
+                  parity: int = 0) -> Lattice:
+    """Regulated Coulomb potential of Sec. VII.C (0 for r < a, -1/r + 1/a
+    beyond), m = 1, dt = a^2/4: 512^3 at a = 0.05 (L = 25.6 Bohr radii;
+    printed binding energies -0.499 and -0.122) and, by the multi-resolution
+    chain of Sec. VII.G, 1024^3 at a = 0.025 (-0.499632).  V at infinity is
+    1/a, so the binding energy is E - 1/a."""
+    return Lattice(N, N * a, POT_COULOMB_REG, [1.0], dt_over_a2=dt_over_a2, v_inf=1.0 / a,
+                   seed=11, parity=parity)
+
+
+def paper_coulomb_az() -> Lattice:
+    """The A_z start of Sec. VII.F: regulated Coulomb on 256^3, a = 0.2,
+    dt = 0.01 (= a^2/4); printed E_1 = -0.12507 and, for the next state odd
+    in z, E_2 = -0.055360."""
+    return Lattice(256, 256 * 0.2, POT_COULOMB_REG, [1.0], dt_over_a2=0.25, v_inf=5.0, seed=12,
+                   parity=parity_word(z=2))
+
+
+def paper_ho_512() -> Lattice:
+    """Isotropic oscillator of Sec. VII.D: 512^3, a = 0.02 (L = 10.24),
+    dt = 1e-4 (= a^2/4); printed E_0 = 1.49996."""
+    return Lattice(512, 10.24, POT_HO, [1.0, 1.0, 1.0], dt_over_a2=0.25, seed=13)
+
+
+def paper_dodeca(N: int = 128) -> Lattice:
+    """Dodecahedron well of Sec. VII.E, V = -100 inside: a = 0.1,
+    dt = 0.001 (= a^2/10); printed E_0 = -99.78 and E_1 = -99.55 on 128^3,
+    E_0 = -99.97 on 512^3."""
+    return Lattice(N, N * 0.1, POT_DODECA, [-100.0], dt_over_a2=0.1, seed=14)

@@ -36,10 +36,11 @@ def test_potential_kind_numbering_matches_the_oracle():
     from paper_0904_0939_amd import workloads as W
 
     for name in ("POT_CONST", "POT_HO", "POT_COULOMB", "POT_COULOMB_REG", "POT_CORNELL",
-                 "POT_WELLS"):
+                 "POT_WELLS", "POT_DODECA"):
         assert getattr(F, name) == getattr(oracle, name) == getattr(W, name)
     hdr = open(F.HEADER).read()
-    for i, name in enumerate(["CONST", "HO", "COULOMB", "COULOMB_REG", "CORNELL", "WELLS"]):
+    for i, name in enumerate(["CONST", "HO", "COULOMB", "COULOMB_REG", "CORNELL", "WELLS",
+                              "DODECA"]):
         assert f"FDTD_POT_{name} = {i}" in hdr
 
 
@@ -91,6 +92,12 @@ def test_call_order_and_workspace_checks_without_device():
         p = (C.c_double * 4)(1, 1, 1, 1)
         assert status_of("fdtd_set_potential_analytic", h, 0, F.POT_WELLS, p, 4) == F.EINVAL
         assert status_of("fdtd_energy_grad", h, 0, 1, None, 0, None, 0, None, None, None) == F.EINVAL
+        assert status_of("fdtd_set_projection_states", h, 0, None, 2, F.F64, 0) == F.EINVAL
+        assert status_of("fdtd_set_projection_states", h, 0, C.c_void_p(64), 17, F.F64, 0) == F.EINVAL
+        assert status_of("fdtd_set_projection_states", h, 1, C.c_void_p(64), 1, F.F64, 0) == F.EINVAL
+        assert status_of("fdtd_project", h, 0, None) == F.ENOTREADY
+        bad = F.fdtd_evolve_opts(10, 1, 0, 0, 0, 0.0, -1, 0)
+        assert status_of("fdtd_evolve", h, C.byref(bad), None, None) == F.EINVAL
     finally:
         F.fdtd_destroy(h)
 
