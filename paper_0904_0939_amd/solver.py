@@ -212,26 +212,38 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
              dtypes: Sequence[str], seed: int = 0, rel_tol: Sequence[float] = (1e-7,),
              max_steps: Sequence[int] = (200000,), check_every: int = 100,
              dt_over_a2: float = 0.125, mass: float = 1.0, parity: int = 0,
-             use_graph: bool = True):
+             use_graph: bool = True, v_inf: float = 0.0, project: Optional[Dict] = None,
+             project_every: int = 10, keep: bool = False):
     """Multi-resolution chain (Sec. VI): relax from noise on levels[0], then
     reseed each finer level by trilinear interpolation of the previous one.
-    Returns (final Solver, per-level [(N, steps, converged)])."""
+    project: optional {N: [states]} projected out every project_every steps
+    on level N (excited states, Sec. III).  keep: also return each level's
+    final state (FP32 device tensor) in a dict.  Returns (final Solver,
+    per-level [(N, steps, converged)][, kept states])."""
     prev = None
     log = []
+    kept = {}
     for i, N in enumerate(levels):
-        s = Solver(N, L, mass=mass, dtype=dtypes[i], dt_over_a2=dt_over_a2)
+        s = Solver(N, L, mass=mass, dtype=dtypes[i], dt_over_a2=dt_over_a2, v_inf=v_inf)
         s.set_potential(kind, params)
         if prev is None:
             s.set_initial(seed, parity=parity)
         else:
             F.fdtd_upsample(prev.h, 0, s.h, 0)
             prev.close()
+        pe = 0
+        if project and N in project:
+            s.set_projection_states(project[N])
+            pe = project_every
         tol = rel_tol[min(i, len(rel_tol) - 1)]
         mx = max_steps[min(i, len(max_steps) - 1)]
-        done, conv = s.evolve(mx, check_every=check_every, rel_tol=tol, use_graph=use_graph)
+        done, conv = s.evolve(mx, check_every=check_every, rel_tol=tol, use_graph=use_graph,
+                              project_every=pe)
         log.append((N, done, conv))
+        if keep:
+            kept[N] = s.psi_tensor(0, dtype=torch.float32)
         prev = s
-    return prev, log
+    return (prev, log, kept) if keep else (prev, log)
 
 
 class EnergyOfPotential(torch.autograd.Function):
