@@ -164,9 +164,21 @@ typedef struct {
  *         instead of streaming the V table from HBM (12 -> 8 bytes per site for
  *         F32, 8 -> 4 for BF16); variant 0 (per-step or persistent) only, and
  *         not inside fdtd_energy_grad.  V then differs from the table (V computed
- *         in FP64, rounded once) by a few FP32 ulps.  0: always read the table. */
+ *         in FP64, rounded once) by a few FP32 ulps.  0: always read the table;
+ *  tblock  0 (default): one pass over HBM per step; 2: temporal blocking, two
+ *         steps per pass (psi and V read once, psi written once per two steps).
+ *         A work item first advances its chunk plus the N sites (one row) on
+ *         each side and one plane on each side in x by one step, in
+ *         registers and LDS, then its own chunk by the second.  F32 / F64
+ *         lattices with 2N <= 256 vz, ry = 1, vz = the vector width, depth <= 2
+ *         (F32) or 1 (F64), variant 0, persist 0; not inside fdtd_energy_grad.
+ *         The rescale can only follow a pass: one due after a pass's first
+ *         step (renorm_every) is applied after its second, so results are
+ *         bit-identical to one launch per step of the same shape whenever no
+ *         rescale falls inside a pass (renorm_every even, passes from an even
+ *         step count).  An odd remainder of steps runs one launch per step. */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse, tblock;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/
@@ -291,6 +303,8 @@ fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
  * for later handles of this process.  The state, step counters and history
  * are saved first and restored after (the trials step the lattice).  A shape
  * found in the cache is set without timing; best_ms then receives -1.
+ * The shapes include two-step passes (tblock = 2), which move a rescale due
+ * after a pass's first step to its second (see fdtd_tuning).
  * chosen (optional) receives the shape; best_ms (optional) its time per step. */
 fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen,
                           double* best_ms);

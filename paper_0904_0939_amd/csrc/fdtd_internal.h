@@ -86,6 +86,7 @@ struct StepArgs {
   double* ring;         // history: n_members * ring_cap * kRec
   int ring_cap;
   double* obs_out;      // observe mode: n_members * kRec
+  int slot_stride;      // two-step passes: step t + 1's partials at slot_stride + slot
   // persistent launches only
   int steps;            // steps this launch advances every member
   unsigned int spin_limit;  // polls of a dependency wait before it gives up
@@ -101,6 +102,12 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // bt = 256; every member's vkind must be >= 0) instead of reading V.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        bool fv, const StepArgs& a, hipStream_t s);
+// Two steps per pass (temporal blocking, update only): vz = the dtype's
+// vector width, ry in {1, 2}, depth in {1, 2}; needs 2 N <= 256 vz for every
+// member, partials for 2 * slot_stride slots, and max_n = the largest N.
+hipError_t launch_step2(int dtype, int ry, int depth, bool fv, int grid, int max_n,
+                        const StepArgs& a, hipStream_t s);
+
 // Persistent form of launch_step (update only): `grid` work-groups take
 // (step, item) tickets in order and advance every member a.steps steps; an
 // item of step t waits until its member has finalised step t - 1.

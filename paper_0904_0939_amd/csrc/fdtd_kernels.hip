@@ -31,6 +31,12 @@
 
 #include "fdtd_internal.h"
 
+// No implicit fused multiply-adds anywhere in this file: every fma is written
+// out (fma_c), so a site's arithmetic is the same whichever kernel it is
+// inlined into.  The one-step, persistent and two-step kernels then give the
+// same bits for the same step.
+#pragma clang fp contract(off)
+
 namespace fdtd {
 namespace {
 
@@ -112,6 +118,8 @@ __device__ __forceinline__ void zero_vec(C (&o)[VZ]) {
 
 __device__ __forceinline__ float rcp_c(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_c(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -295,8 +303,12 @@ __device__ __forceinline__ T ld_agent(const T& x) {
 // Last work-group of member m: record the step's sums, set the scale of the
 // next update, advance the step counter, flag non-finite sums, re-arm the
 // completion counter and, last, publish the step as finalised (release).
+// rn: -1 the renorm_every rule (rescale when the new step count is a
+// multiple of renorm_every); 0 no rescale; 1 the rule applied to this step or
+// the one before (the second step of a temporally blocked pass: a rescale due
+// after the first is deferred to it).
 __device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, int m,
-                                      const double (&tot)[5], bool upd) {
+                                      const double (&tot)[5], bool upd, int rn = -1) {
   MemberState& st = A.states[m];
   const double kin = -M.kin_scale * tot[1];
   const long long t = ld_agent(st.step);
@@ -306,7 +318,8 @@ __device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, 
 #pragma unroll
     for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
     const long long nt = t + 1;
-    const bool renorm = A.renorm_every > 0 && (nt % A.renorm_every) == 0;
+    const bool renorm = A.renorm_every > 0 && rn != 0 &&
+                        ((nt % A.renorm_every) == 0 || (rn == 1 && ((nt - 1) % A.renorm_every) == 0));
     st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
     st.step = nt;
     if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) &&
@@ -468,7 +481,6 @@ struct StepBody {
     if constexpr (FV) {
       const double xd = (2.0 * x - k.cN) * k.ha;
       const C x2 = (C)(xd * xd);
-      const C vx = k.hx * x2;
 #pragma unroll
       for (int r = 0; r < RY; ++r)
 #pragma unroll
@@ -476,7 +488,7 @@ struct StepBody {
           const C r2 = x2 + ln.w2[r][j];
           const C inv = __builtin_amdgcn_rsqf(r2 + k.ve);  // 1/r, hardware (~1 ulp)
           const C rr = r2 * inv;
-          const C vv = __builtin_fmaf(k.q1, inv, __builtin_fmaf(k.q2, rr, vx + ln.vl[r][j]));
+          const C vv = fma_c(k.q1, inv, fma_c(k.q2, rr, fma_c(k.hx, x2, ln.vl[r][j])));
           v[r][j] = rr < k.va ? C(0) : vv;
         }
     } else {
@@ -498,12 +510,31 @@ struct StepBody {
   // reductions of plane x into acc.  SHZ: the z neighbours across a vector
   // boundary come from the adjacent lanes, d.zm / d.zp hold them for the
   // wave's edge lanes only; otherwise d.zm / d.zp hold them for every lane.
-  template <bool SHZ = kSHZ>
-  static __device__ __forceinline__ void update(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
+  template <bool SHZ = kSHZ, int RYL = RY>
+  static __device__ __forceinline__ void update(const Ctx& k, const Lane<RYL, VZ, C>& ln, int x,
                                                 const C (&pm)[RY][VZ], const C (&pc)[RY][VZ],
                                                 const C (&pn)[RY][VZ], const C (&vv)[RY][VZ],
                                                 const PlaneIn<RY, VZ, C>& d, double (&acc)[5],
                                                 bool live = true) {
+    C unused[1][VZ];
+    update_core<SHZ, false, RY>(k, ln, x, pm, pc, pn, vv, d, acc, live, unused);
+  }
+
+  // The update of plane x.  TOREG: instead of storing the new values to
+  // HBM, return them (as stored: rounded to the storage type) in outv, and
+  // reduce only the first NRED vectors (the temporally blocked step keeps a
+  // halo vector whose sites another work item owns).
+  // The lane may carry more vectors than RY (RYL >= RY): the first RY are
+  // updated.
+  template <bool SHZ, bool TOREG, int NRED, int NO, int RYL>
+  static __device__ __forceinline__ void update_core(const Ctx& k, const Lane<RYL, VZ, C>& ln,
+                                                     int x, const C (&pm)[RY][VZ],
+                                                     const C (&pc)[RY][VZ],
+                                                     const C (&pn)[RY][VZ],
+                                                     const C (&vv)[RY][VZ],
+                                                     const PlaneIn<RY, VZ, C>& d,
+                                                     double (&acc)[5], bool live,
+                                                     C (&outv)[NO][VZ]) {
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
     const __amdgpu_buffer_rsrc_t ro = plane_rsrc(k.out, x, k.N, k.pbytes);
@@ -555,23 +586,28 @@ struct StepBody {
                 ((lft - p) + (rgt - p));
         }
         const C p2 = p * p;
-        s0 += p2;
-        kin += p * lap;
-        pot += vv[r][j] * p2;
-        r2 += ln.w2[r][j] * p2;
+        const C v = vv[r][j];
+        if (r < NRED) {
+          s0 += p2;
+          kin = fma_c(p, lap, kin);
+          pot = fma_c(v, p2, pot);
+          r2 = fma_c(ln.w2[r][j], p2, r2);
+        }
         if constexpr (UPD) {
-          const C B = rcp_c(C(1) + k.eps * vv[r][j]);
-          const C nv = k.sc * (p + B * (k.c * lap - k.dt * vv[r][j] * p));
+          const C B = rcp_c(fma_c(k.eps, v, C(1)));
+          const C g = fma_c(k.c, lap, -((k.dt * v) * p));  // c lap - dt V psi
+          const C nv = k.sc * fma_c(B, g, p);
           if constexpr (sizeof(S) == 2) {
             o.v[j] = f32_to_bf16_sr((float)nv, rb[j]);
           } else {
             o.v[j] = (S)nv;
           }
           const C od = to_c<S, C>(o.v[j]);
-          s1 += live ? od * od : C(0);
+          if (r < NRED) s1 = live ? fma_c(od, od, s1) : s1;
+          if constexpr (TOREG) outv[r][j] = od;
         }
       }
-      if constexpr (UPD) bstore<S, VZ, FDTD_AUX_OUT>(ro, ln.off[r], o);
+      if constexpr (UPD && !TOREG) bstore<S, VZ, FDTD_AUX_OUT>(ro, ln.off[r], o);
     }
     acc[0] += (double)s0;
     acc[1] += (double)kin;
@@ -796,6 +832,304 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepAr
   }
 }
 
+// -------------------------------------- temporal blocking: two steps ----
+// k_step2 advances every member two steps per pass over HBM (psi and V read
+// once, psi'' written once).  A work item owns a chunk of F = 256 VZ RY sites
+// of the flattened (y, z) plane and streams x.  Step t runs on its own
+// vectors plus one halo vector per lane covering the N sites before and the
+// N after the chunk (the y and z neighbours of the chunk's edge sites), with
+// the loads and arithmetic of the one-step kernel; its results stay in
+// registers (own vectors, planes x - 1, x, x + 1) and go to an LDS copy of
+// the plane for the neighbours.  Step t + 1 follows one plane behind, from
+// registers and LDS.  Per-site arithmetic, reduction grouping and rounding
+// bits are those of one-step launches with renorm_every = 2, so the results
+// are the same bits: step t never rescales, step t + 1 rescales at the end
+// of the pass when the renorm_every rule asks for it.  Needs 2 N <= 256 VZ
+// (one halo vector per lane).
+// Work-group barrier fenced on LDS only: outstanding global loads (the
+// prefetched planes) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int DT, int VZ, int RY, int D, bool FV>
+struct Step2 {
+  static constexpr int BT = 256;
+  using B1 = StepBody<DT, VZ, RY + 1, true, FV>;  // step t: own vectors + the halo vector
+  using B2 = StepBody<DT, VZ, RY, true, FV>;      // step t + 1: own vectors
+  using S = typename B1::S;
+  using TV = typename B1::TV;
+  using C = typename B1::C;
+  static constexpr unsigned kES = sizeof(S);
+
+  struct Rings {
+    C qs[6][RY + 1][VZ];               // psi_t of planes, own + halo
+    C vs[6][RY + 1][VZ];               // V of planes, own + halo
+    PlaneIn<RY + 1, VZ, C> nb[6];      // y / z neighbours of psi_t planes
+    C us[3][RY][VZ];                   // step-t results, own vectors
+  };
+
+  // Stage X (slot SL = (X - base) % 6 with base = xb - 1): prefetch, step t
+  // at plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1
+  // at plane X - 1, then the work-group barrier.
+  template <int SL, bool STEP2>
+  static __device__ __forceinline__ void stage(const typename B1::Ctx& k1,
+                                               const typename B2::Ctx& k2,
+                                               const Lane<RY + 1, VZ, C>& ln1, const bool (&own)[RY],
+                                               int X, int xb, int xe, C* tile, unsigned TS,
+                                               unsigned N, Rings& g, double (&acc1)[5],
+                                               double (&acc2)[5]) {
+    const int tid = threadIdx.x;
+    B1::fetch_own(k1, ln1, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
+    B1::fetch_v(k1, ln1, X + D, g.vs[(SL + D) % 6]);
+    B1::fetch(k1, ln1, X + D, g.nb[(SL + D) % 6]);
+    // step t at plane X: the work item's own planes [xb, xe) count in the
+    // reductions, the halo planes xb - 1 and xe do not
+    double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    C un[RY + 1][VZ];
+    B1::template update_core<false, true, RY>(k1, ln1, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                              g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
+                                              tmp, true, un);
+    if (X >= xb && X < xe) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc1[q] += tmp[q];
+    }
+    // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
+    // one-step kernel drops their stores; here they feed step t + 1)
+    const bool inx = (unsigned)X < N;
+#pragma unroll
+    for (int r = 0; r <= RY; ++r)
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) un[r][j] = inx ? un[r][j] : C(0);
+    C* t = tile + (unsigned)(X & 1) * TS;
+#pragma unroll
+    for (int r = 0; r <= RY; ++r) {
+      // own vector r at N + (r * BT + tid) * VZ, the halo vector at its
+      // flattened offset from the chunk start - N
+      const unsigned idx = r < RY ? N + (unsigned)(r * BT + tid) * VZ
+                                  : ((unsigned)tid < N / VZ ? (unsigned)tid * VZ
+                                                            : TS - 2u * N + (unsigned)tid * VZ);
+      const bool put = r < RY || (unsigned)tid < 2u * N / VZ;
+      if (put) {
+        Pack<C, VZ> pk;
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) pk.v[j] = un[r][j];
+        *reinterpret_cast<Pack<C, VZ>*>(t + idx) = pk;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r)
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) g.us[SL % 3][r][j] = un[r][j];
+    if constexpr (STEP2) {
+      // step t + 1 at plane X - 1: psi_{t+1} planes X - 2, X - 1, X in
+      // registers, the y / z neighbours of plane X - 1 from LDS.  A vector
+      // past the end of the plane (not lattice sites) gets zero neighbours,
+      // as its loads in the one-step kernel: its result is not stored, but
+      // it enters the output norm.
+      const C* tp = tile + (unsigned)((X - 1) & 1) * TS;
+      PlaneIn<RY, VZ, C> d;
+#pragma unroll
+      for (int r = 0; r < RY; ++r) {
+        const unsigned idx = N + (unsigned)(r * BT + tid) * VZ;
+        const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + idx - N);
+        const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + idx + N);
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          d.ym[r][j] = own[r] ? pm.v[j] : C(0);
+          d.yp[r][j] = own[r] ? pp.v[j] : C(0);
+        }
+        d.zm[r] = own[r] ? tp[idx - 1] : C(0);
+        d.zp[r] = own[r] ? tp[idx + VZ] : C(0);
+      }
+      const C(&vown)[RY][VZ] = reinterpret_cast<const C(&)[RY][VZ]>(g.vs[(SL + 5) % 6]);
+      // the lane's first RY vectors are the own ones
+      B2::template update<false>(k2, ln1, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
+                                 g.us[SL % 3], vown, d, acc2);
+    }
+    lds_barrier();
+  }
+};
+
+// Lane vector r of a temporally blocked work item: site f of the flattened
+// plane (ok: a lattice site), with every offset the one-step loads use.
+template <typename Body, int RYL, int VZ, typename C>
+__device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f, bool ok,
+                                        const MemberDev& M, int N, double cN, double ha) {
+  constexpr unsigned kES = sizeof(typename Body::S);
+  using TV = typename Body::TV;
+  const unsigned fe = ok ? f : kDeadLane;
+  const int y = ok ? (int)(f / (unsigned)N) : 0;
+  const int z0 = ok ? (int)(f - (unsigned)y * N) : 0;
+  ln.off[r] = fe * kES;
+  ln.voff[r] = fe * (unsigned)sizeof(TV);
+  ln.offm[r] = (fe - (unsigned)N) * kES;
+  ln.offp[r] = (fe + (unsigned)N) * kES;
+  ln.offzm[r] = fe * kES - kES;
+  ln.offzp[r] = fe * kES + VZ * kES;
+  ln.zmask_lo[r] = (ok && z0 > 0) ? 1.f : 0.f;
+  ln.zmask_hi[r] = (ok && z0 + VZ < N) ? 1.f : 0.f;
+  const double yc = (2.0 * y - cN) * ha;
+  const int cy = min(y, N - 1 - y);
+  uint32_t key[VZ];
+#pragma unroll
+  for (int j = 0; j < VZ; ++j) {
+    const double zc = (2.0 * (z0 + j) - cN) * ha;
+    ln.w2[r][j] = (C)(yc * yc + zc * zc);
+    Body::vlane(ln, r, j, M.vkind, M.vp, M.a, yc, zc);
+    const int z = z0 + j;
+    key[j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
+  }
+  Body::hash_lane(ln, r, N, key);
+}
+
+template <int DT, int VZ, int RY, int D, bool FV>
+__global__ __launch_bounds__(256, FDTD_STEP_MIN_WAVES) void k_step2(StepArgs A) {
+  using T = Step2<DT, VZ, RY, D, FV>;
+  using B1 = typename T::B1;
+  using B2 = typename T::B2;
+  using S = typename T::S;
+  using TV = typename T::TV;
+  using C = typename T::C;
+  constexpr int BT = 256;
+  constexpr unsigned kES = sizeof(S);
+  extern __shared__ __align__(16) unsigned char smem[];
+  C* tile = reinterpret_cast<C*>(smem);
+  __shared__ double s_red[BT / 64][5];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+
+  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
+    const Item item = A.items[A.item_offset + li];
+    const int m = item.member;
+    const MemberDev& M = A.members[m];
+    const int N = M.N;
+    const unsigned P = (unsigned)M.plane;
+    const unsigned F = (unsigned)(BT * VZ * RY);
+    const unsigned TS = F + 2u * (unsigned)N;  // LDS plane: chunk plus N sites each side
+    const double cN = (double)(N - 1), ha = M.ha;
+    const long long step = ld_agent(A.states[m].step);
+
+    typename B1::Ctx k1;
+    k1.in = M.psi[A.src];
+    k1.out = M.psi[A.src ^ 1];  // unused: step t goes to registers
+    k1.Vf = static_cast<const TV*>(M.V);
+    k1.pbytes = P * kES;
+    k1.vbytes = P * (unsigned)sizeof(TV);
+    k1.N = N;
+    k1.xe = item.xe + 1;  // step t also runs on plane xe (the halo plane)
+    k1.c = (C)M.c;
+    k1.dt = (C)M.dt;
+    k1.eps = (C)(0.5 * M.dt);
+    k1.sc = (C)ld_agent(A.states[m].scale);
+    k1.ha = ha;
+    k1.cN = cN;
+    k1.smix = hash32((uint32_t)step);
+    if constexpr (FV) B1::vcoef(k1, M.vkind, M.vp, M.a);
+    typename B2::Ctx k2;
+    k2.in = M.psi[A.src];
+    k2.out = M.psi[A.src ^ 1];
+    k2.Vf = k1.Vf;
+    k2.pbytes = k1.pbytes;
+    k2.vbytes = k1.vbytes;
+    k2.N = N;
+    k2.xe = item.xe;
+    k2.c = k1.c;
+    k2.dt = k1.dt;
+    k2.eps = k1.eps;
+    k2.sc = C(1);  // no rescale between the two steps of a pass
+    k2.ha = ha;
+    k2.cN = cN;
+    k2.smix = hash32((uint32_t)(step + 1));
+    if constexpr (FV) B2::vcoef(k2, M.vkind, M.vp, M.a);
+
+    Lane<RY + 1, VZ, C> ln1;
+    bool own[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const unsigned f = (unsigned)item.f0 + (unsigned)(r * BT + tid) * VZ;
+      own[r] = f < P;
+      tb_lane<B1>(ln1, r, f, own[r], M, N, cN, ha);
+    }
+    {
+      // halo vector: lanes below N / VZ take the N sites before the chunk,
+      // the next N / VZ lanes the N sites after it; the rest idle
+      const unsigned nh = (unsigned)N / VZ;
+      const unsigned u = (unsigned)tid;
+      const unsigned f = u < nh ? (unsigned)item.f0 - (unsigned)N + u * VZ
+                                : (unsigned)item.f0 + F + (u - nh) * VZ;  // may wrap: not a site
+      tb_lane<B1>(ln1, RY, f, u < 2u * nh && f < P, M, N, cN, ha);
+    }
+
+    double acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    typename T::Rings g;
+    const int xb = item.xb, xe = item.xe, base = xb - 1;
+#pragma unroll
+    for (int i = 0; i < D + 2; ++i) B1::fetch_own(k1, ln1, base - 1 + i, g.qs[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      B1::fetch_v(k1, ln1, base + i, g.vs[i]);
+      B1::fetch(k1, ln1, base + i, g.nb[i]);
+    }
+    // planes xb - 1 and xb: step t only; then both steps, six stages a trip
+    T::template stage<0, false>(k1, k2, ln1, own, base, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    T::template stage<1, false>(k1, k2, ln1, own, base + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    int X = xb + 1;
+    for (; X + 6 <= xe + 1; X += 6) {
+      T::template stage<2, true>(k1, k2, ln1, own, X, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      T::template stage<3, true>(k1, k2, ln1, own, X + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      T::template stage<4, true>(k1, k2, ln1, own, X + 2, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      T::template stage<5, true>(k1, k2, ln1, own, X + 3, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      T::template stage<0, true>(k1, k2, ln1, own, X + 4, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      T::template stage<1, true>(k1, k2, ln1, own, X + 5, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    }
+    if (X <= xe) T::template stage<2, true>(k1, k2, ln1, own, X, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    if (X + 1 <= xe) T::template stage<3, true>(k1, k2, ln1, own, X + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    if (X + 2 <= xe) T::template stage<4, true>(k1, k2, ln1, own, X + 2, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    if (X + 3 <= xe) T::template stage<5, true>(k1, k2, ln1, own, X + 3, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    if (X + 4 <= xe) T::template stage<0, true>(k1, k2, ln1, own, X + 4, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+
+    // ---- partials of both steps; the member's last work-group finalises them
+    block_sum<5, BT / 64>(acc1, s_red);
+    block_sum<5, BT / 64>(acc2, s_red);
+    if (tid == 0) {
+      double* p1 = A.partials + (long long)item.slot * kRec;
+      double* p2 = A.partials + (long long)(A.slot_stride + item.slot) * kRec;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        p1[q] = acc1[q];
+        p2[q] = acc2[q];
+      }
+      __threadfence();
+      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+      s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
+    }
+    __syncthreads();
+    if (s_last) {
+      __threadfence();
+      double t1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, t2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = M.item_begin + tid; i < M.item_end; i += BT) {
+        const double* p1 = A.partials + (long long)i * kRec;
+        const double* p2 = A.partials + (long long)(A.slot_stride + i) * kRec;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          t1[q] += p1[q];
+          t2[q] += p2[q];
+        }
+      }
+      block_sum<5, BT / 64>(t1, s_red);
+      block_sum<5, BT / 64>(t2, s_red);
+      if (tid == 0) {
+        finalize(A, M, m, t1, true, 0);  // never rescales: step t + 1 already ran
+        finalize(A, M, m, t2, true, 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------- fused step, LDS plane tiles ----
 // Variant of k_step for large work-groups: each lane owns one vector of VZ
 // sites, the work-group a chunk of kTB * VZ consecutive sites of the
@@ -812,11 +1146,6 @@ struct TileShape {
   static constexpr int kTB = DT == kBF16 ? 512 : 1024;  // threads per work-group
 };
 
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 template <int DT, int VZ, bool UPD, int D>
 struct TileBody {
@@ -1625,14 +1954,59 @@ int tile_threads(int dtype) { return dtype == kBF16 ? 512 : 1024; }
 
 hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max_n,
                             const StepArgs& a, hipStream_t s) {
-  if (grid < 1) return hipErrorInvalidValue;
   const unsigned vz = dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8);
+  // one halo vector per lane covers the N sites on each side of the chunk
+  if (grid < 1 || max_n < 1 || 2u * (unsigned)max_n > 256u * vz) return hipErrorInvalidValue;
   const unsigned cs = dtype == kF64 ? 8 : 4;
   const unsigned lds = 2u * ((unsigned)tile_threads(dtype) * vz + 2u * (unsigned)max_n) * cs;
   switch (dtype) {
     case kF64: return tile_dt<kF64>(depth, update, grid, lds, a, s);
     case kF32: return tile_dt<kF32>(depth, update, grid, lds, a, s);
     case kBF16: return tile_dt<kBF16>(depth, update, grid, lds, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int DT, int VZ, int RY, int D, bool FV>
+hipError_t step2_one(int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_step2<DT, VZ, RY, D, FV>), dim3(grid), dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+// Shapes whose registers fit one wave per SIMD without spilling much: one
+// own vector per lane (the halo vector doubles the first step's state), FP64
+// without deep prefetch; BF16 lanes (8 sites) do not fit.
+template <int DT, int VZ, bool FV>
+hipError_t step2_ry(int ry, int depth, int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
+  if (ry != 1) return hipErrorInvalidValue;
+  if (depth == 1) return step2_one<DT, VZ, 1, 1, FV>(grid, lds, a, s);
+  if constexpr (DT == kF32) {
+    if (depth == 2) return step2_one<DT, VZ, 1, 2, FV>(grid, lds, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int DT>
+hipError_t step2_dt(int ry, int depth, bool fv, int grid, unsigned lds, const StepArgs& a,
+                    hipStream_t s) {
+  constexpr int VZ = Types<DT>::kVec;
+  if constexpr (DT == kF32) {
+    if (fv) return step2_ry<DT, VZ, true>(ry, depth, grid, lds, a, s);
+  }
+  if (fv) return hipErrorInvalidValue;
+  return step2_ry<DT, VZ, false>(ry, depth, grid, lds, a, s);
+}
+
+hipError_t launch_step2(int dtype, int ry, int depth, bool fv, int grid, int max_n,
+                        const StepArgs& a, hipStream_t s) {
+  const unsigned vz = dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8);
+  // one halo vector per lane covers the N sites on each side of the chunk
+  if (grid < 1 || max_n < 1 || 2u * (unsigned)max_n > 256u * vz) return hipErrorInvalidValue;
+  const unsigned cs = dtype == kF64 ? 8 : 4;
+  const unsigned lds = 2u * (256u * vz * (unsigned)ry + 2u * (unsigned)max_n) * cs;
+  switch (dtype) {
+    case kF64: return step2_dt<kF64>(ry, depth, fv, grid, lds, a, s);
+    case kF32: return step2_dt<kF32>(ry, depth, fv, grid, lds, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -384,7 +384,8 @@ fdtd_status build_items(fdtd_ctx* h) {
     h->d_partials = nullptr;
     h->items_cap = 0;
     hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * 2 * (size_t)n);
-    hipError_t e2 = hipMalloc((void**)&h->d_partials, sizeof(double) * kRec * n);
+    // two slots per work item: a two-step pass keeps both steps' partials
+    hipError_t e2 = hipMalloc((void**)&h->d_partials, sizeof(double) * kRec * 2 * (size_t)n);
     if (e1 != hipSuccess || e2 != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "device allocation of work items failed");
@@ -482,7 +483,20 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
     }
     return FDTD_OK;
   }
-  for (int k = 0; k < n; ++k) {
+  int k = 0;
+  if (h->tun.tblock == 2 && !h->table_v_only) {
+    // two steps per pass; a rescale due after a pass's first step is
+    // deferred to its second
+    for (; k + 2 <= n; k += 2) {
+      StepArgs a = base_args(h);
+      a.renorm_every = renorm_every;
+      a.slot_stride = h->n_items;
+      HIP_TRY(launch_step2(h->dtype, h->tun.ry, h->tun.depth, use_fv(h), launch_grid(h, a.n_items),
+                           max_n(h), a, s));
+      h->cur ^= 1;  // psi_{t+2} is in the other buffer
+    }
+  }
+  for (; k < n; ++k) {
     StepArgs a = base_args(h);
     a.renorm_every = renorm_every;
     HIP_TRY(launch_kernel(h, true, launch_grid(h, a.n_items), a, s));
@@ -494,7 +508,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
          a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant &&
-         a.persist == b.persist && a.vfuse == b.vfuse;
+         a.persist == b.persist && a.vfuse == b.vfuse && a.tblock == b.tblock;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -682,6 +696,15 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   if (t.persist < 0 || t.persist > 65536) return fail(FDTD_EINVAL, "tuning: persist must be in [0, 65536]");
   if (t.persist > 0 && t.variant != 0) return fail(FDTD_EINVAL, "tuning: persistent launches need variant 0");
   if (t.vfuse != 0 && t.vfuse != 1) return fail(FDTD_EINVAL, "tuning: vfuse must be 0 or 1");
+  if (t.tblock != 0 && t.tblock != 2) return fail(FDTD_EINVAL, "tuning: tblock must be 0 or 2");
+  if (t.tblock == 2) {
+    if (h->dtype == kBF16) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs an F32 or F64 lattice");
+    if (t.variant != 0 || t.persist != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0 and persist 0");
+    if (t.ry != 1 || t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs ry = 1 and vz = the dtype's vector width");
+    if (t.depth > (h->dtype == kF32 ? 2 : 1)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs depth <= 2 (F32) or 1 (F64)");
+    for (auto& m : h->mem)
+      if (2LL * m.N > 256LL * t.vz) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs 2N <= 256 vz");
+  }
   if (t.variant == 2) {
     if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");
     if (h->dtype == kBF16 && t.vz > 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs vz = 1 for BF16");
@@ -1198,6 +1221,12 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
       for (int depth : {1, 2, 3}) {
         if (!go || xc > maxN || !all_div) continue;
         go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 1});
+      }
+    // two steps per pass (validation drops the shapes it does not cover)
+    for (int xc : {0, 32, 64, 128, 256})
+      for (int depth : {1, 2}) {
+        if (!go || xc > maxN || !all_div) continue;
+        go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, 0, 0, 2});
       }
   }
   // restore

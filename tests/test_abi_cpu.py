@@ -115,7 +115,7 @@ def test_tuning_validation_is_host_side():
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0, 1))
         assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
                                                   "xcd_remap": 0, "depth": 1, "variant": 0,
-                                                  "persist": 0, "vfuse": 0}
+                                                  "persist": 0, "vfuse": 0, "tblock": 0}
         # persistent launches: variant 0 only, bounded step count
         for bad in [F.fdtd_tuning(1, 1, 8, 0, 1, 1, 2, 8), F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, -1),
                     F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, 65537)]:
@@ -127,6 +127,34 @@ def test_tuning_validation_is_host_side():
         assert status_of("fdtd_set_tuning", h, C.byref(F.fdtd_tuning(1, 1, 8, 0, 1, 1, 1))) == F.EINVAL
     finally:
         F.fdtd_destroy(h)
+
+
+def test_two_step_passes_validation():
+    """tblock = 2: F32 / F64 only, full vectors, ry = 1, shallow prefetch,
+    variant 0 without persistence, and 2N <= 256 vz (one halo vector per lane)."""
+    h32 = F.fdtd_create(cfg(N=64, dtype=F.F32))
+    h64 = F.fdtd_create(cfg(N=64, dtype=F.F64))
+    hb = F.fdtd_create(cfg(N=64, dtype=F.BF16))
+    big = F.fdtd_create(cfg(N=516, L=40.0, dtype=F.F32))
+    try:
+        ok32 = F.fdtd_tuning(4, 1, 0, 0, 1, 2, 0, 0, 1, 2)
+        F.fdtd_set_tuning(h32, ok32)
+        assert F.fdtd_get_tuning(h32).tblock == 2
+        for bad in [F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 0, 1, 1),   # tblock 1
+                    F.fdtd_tuning(4, 2, 0, 0, 1, 1, 0, 0, 1, 2),   # ry 2
+                    F.fdtd_tuning(1, 1, 0, 0, 1, 1, 0, 0, 1, 2),   # scalar lanes
+                    F.fdtd_tuning(4, 1, 0, 0, 1, 3, 0, 0, 1, 2),   # depth 3
+                    F.fdtd_tuning(4, 1, 0, 0, 1, 1, 2, 0, 1, 2),   # variant 2
+                    F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 8, 1, 2)]:  # persistent
+            assert status_of("fdtd_set_tuning", h32, C.byref(bad)) == F.EINVAL
+        F.fdtd_set_tuning(h64, F.fdtd_tuning(2, 1, 0, 0, 1, 1, 0, 0, 1, 2))
+        assert status_of("fdtd_set_tuning", h64, C.byref(F.fdtd_tuning(2, 1, 0, 0, 1, 2, 0, 0, 1, 2))) == F.EINVAL
+        assert status_of("fdtd_set_tuning", hb, C.byref(F.fdtd_tuning(8, 1, 0, 0, 1, 1, 0, 0, 1, 2))) == F.EINVAL
+        # 2 * 516 > 256 * 4
+        assert status_of("fdtd_set_tuning", big, C.byref(F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 0, 1, 2))) == F.EINVAL
+    finally:
+        for h in (h32, h64, hb, big):
+            F.fdtd_destroy(h)
 
 
 def test_status_strings_and_null_handles():

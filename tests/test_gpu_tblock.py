@@ -1,0 +1,102 @@
+"""Temporal blocking (tuning field `tblock` = 2): one pass over HBM advances a
+lattice two steps.  Whenever no rescale falls inside a pass (renorm_every = 2
+from step 0) it must give the same bits as one launch per step of the same
+launch shape; with a rescale every step, or passes that start at an odd step,
+it must still follow the FP64 oracle to the parity tolerances (FP64 1e-10,
+FP32 1e-5)."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle as orc  # noqa: E402
+from paper_0904_0939_amd import fdtd as F  # noqa: E402
+from paper_0904_0939_amd import workloads as W  # noqa: E402
+from paper_0904_0939_amd.solver import Solver  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+VW = {"f32": 4, "f64": 2}
+POT = {"ho": (F.POT_HO, [1.0, 1.2, 0.8]), "cornell": (F.POT_CORNELL, W.CORNELL_PARAMS)}
+
+
+def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.0, seed=5):
+    s = Solver(N, L, dtype=dtype)
+    s.set_potential(*POT[pot])
+    s.set_initial(seed)
+    s.set_tuning(VW[dtype], 1, xchunk, 0, 1, depth, 0, 0, vfuse, tblock)
+    s.evolve(steps, renorm_every=renorm, use_graph=graph)
+    out = (s.state(), s.observables()[0], s.history(0, steps))
+    s.close()
+    return out
+
+
+# (dtype, N, potential, xchunk, depth, vfuse): chunks of 256 vz sites with a
+# ragged last chunk, several x-ranges per lattice, the in-kernel potential,
+# and the largest side one halo vector per lane covers (2N = 256 vz)
+CASES = [
+    ("f32", 40, "cornell", 0, 1, 0),
+    ("f32", 64, "ho", 8, 2, 0),
+    ("f32", 96, "cornell", 24, 1, 1),
+    ("f32", 512, "cornell", 0, 1, 1),
+    ("f64", 48, "ho", 0, 1, 0),
+    ("f64", 256, "cornell", 32, 1, 0),
+]
+
+
+@pytest.mark.parametrize("dtype,N,pot,xchunk,depth,vfuse", CASES)
+def test_two_step_passes_equal_one_step_launches(dtype, N, pot, xchunk, depth, vfuse):
+    steps = 40 if N >= 256 else 120
+    for graph in (True, False):
+        say(f"case: tblock {dtype} N={N} {pot} xchunk={xchunk} depth={depth} vfuse={vfuse} graph={graph}")
+        ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 2, graph)
+        got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 2, graph)
+        assert np.array_equal(got[0], ref[0])
+        assert got[1] == ref[1]
+        assert got[2] == ref[2]
+        assert ref[1]["step"] == steps
+
+
+def test_odd_step_count_runs_a_single_step_at_the_end():
+    say("case: tblock odd count f32 40^3")
+    ref = run("f32", 40, "ho", 0, 1, 0, 0, 61, 2, True)
+    got = run("f32", 40, "ho", 0, 1, 0, 2, 61, 2, True)
+    assert np.array_equal(got[0], ref[0]) and got[2] == ref[2]
+
+
+@pytest.mark.parametrize("dtype,N,pot,tol", [("f64", 32, "ho", 1e-10), ("f32", 40, "cornell", 1e-5)])
+def test_rescale_every_step_and_odd_starts_follow_the_oracle(dtype, N, pot, tol):
+    """renorm_every = 1 defers each pass's first rescale to its second step;
+    after 3 steps the passes start at odd steps.  The oracle rescales every
+    step: the normalised states and energies agree to the dtype's tolerance."""
+    say(f"case: tblock vs oracle {dtype} N={N}")
+    L, seed = 10.0, 7
+    s = Solver(N, L, dtype=dtype)
+    s.set_potential(*POT[pot])
+    s.set_initial(seed)
+    s.set_tuning(VW[dtype], 1, 0, 0, 1, 1, 0, 0, 0, 2)
+    s.evolve(3)
+    s.evolve(300)
+    kind, params = POT[pot]
+    V = orc.potential(kind, params, N, L)
+    psi = orc.initial(N, seed)
+    orc.evolve(psi, V, L, (L / N) ** 2 / 8, 303)
+    e_gpu = s.observables()[0]["energy"]
+    e_orc = orc.observables(psi, V, L)["energy"]
+    say(f"energy {e_gpu:.12f} oracle {e_orc:.12f}")
+    assert e_gpu == pytest.approx(e_orc, rel=tol)
+    assert rel_l2(s.psi(), orc.normalized(psi, L)) < tol
+    hist = s.history(0, 303)
+    assert [r["step"] for r in hist] == list(range(303))
