@@ -167,16 +167,18 @@ typedef struct {
  *         in FP64, rounded once) by a few FP32 ulps.  0: always read the table;
  *  tblock  0 (default): one pass over HBM per step; 2: temporal blocking, two
  *         steps per pass (psi and V read once, psi written once per two steps).
- *         A work item first advances its chunk plus the N sites (one row) on
- *         each side and one plane on each side in x by one step, in
- *         registers and LDS, then its own chunk by the second.  F32 / F64
- *         lattices with 2N <= 256 vz, ry = 1, vz = the vector width, depth <= 2
- *         (F32) or 1 (F64), variant 0, persist 0; not inside fdtd_energy_grad.
- *         The rescale can only follow a pass: one due after a pass's first
- *         step (renorm_every) is applied after its second, so results are
- *         bit-identical to one launch per step of the same shape whenever no
- *         rescale falls inside a pass (renorm_every even, passes from an even
- *         step count).  An odd remainder of steps runs one launch per step. */
+ *         Work items are then tiles of the (y, z) plane (F32: 16 x 64 sites,
+ *         F64: 16 x 32) streaming x: a work item first advances its tile plus
+ *         a one-site frame around it (and one plane on each side in x) by one
+ *         step, in registers and LDS, then its own tile by the second.  F32 /
+ *         F64 lattices of any side, ry = 1, vz = the vector width, variant 0,
+ *         persist 0; not inside fdtd_energy_grad.  The rescale can only
+ *         follow a pass: one due after a pass's first step (renorm_every) is
+ *         applied after its second.  With the rescale off the states are the
+ *         same bits as one launch per step (shared per-site arithmetic); the
+ *         reductions then differ only in FP64 summation order (per tile
+ *         instead of per flattened chunk).  An odd remainder of steps runs one
+ *         launch per step. */
 typedef struct {
   int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse, tblock;
 } fdtd_tuning;

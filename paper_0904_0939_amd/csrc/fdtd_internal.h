@@ -29,7 +29,7 @@ struct MemberDev {
   int N;
   int item_begin;     // this member's work items are [item_begin, item_end)
   int item_end;
-  int pad0;
+  int tb_begin;       // its tiles of two-step passes are [tb_begin, tb_end)
   long long plane;    // N * N
   double ha;          // a / 2 (site coordinate = (2 i - (N - 1)) * ha)
   double c;           // dt / (2 m a^2)
@@ -39,7 +39,7 @@ struct MemberDev {
   double a;           // lattice spacing
   double vp[3];       // parameters of an analytic potential (kind vkind)
   int vkind;          // analytic kind 0..4 the step may evaluate itself; -1: table only
-  int pad1;
+  int tb_end;
 };
 
 // Mutable per-member state, resident on the device.
@@ -102,11 +102,15 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // bt = 256; every member's vkind must be >= 0) instead of reading V.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        bool fv, const StepArgs& a, hipStream_t s);
-// Two steps per pass (temporal blocking, update only): vz = the dtype's
-// vector width, ry in {1, 2}, depth in {1, 2}; needs 2 N <= 256 vz for every
-// member, partials for 2 * slot_stride slots, and max_n = the largest N.
-hipError_t launch_step2(int dtype, int ry, int depth, bool fv, int grid, int max_n,
-                        const StepArgs& a, hipStream_t s);
+// Two steps per pass (temporal blocking, update only; F32 / F64): work items
+// are tiles of kTbRows(dtype) x kTbCols(dtype) sites of the (y, z) plane,
+// whose f0 is the tile origin y0 N + z0; one vector of the dtype's width per
+// lane (256 lanes); depth 1 (F64) or 1..2 (F32); partials for 2 *
+// slot_stride slots.
+constexpr int kTbCols(int dtype) { return dtype == kF64 ? 32 : 64; }
+constexpr int kTbRows(int dtype) { return 256 * (dtype == kF64 ? 2 : 4) / kTbCols(dtype); }
+hipError_t launch_step2(int dtype, int depth, bool fv, int grid, const StepArgs& a,
+                        hipStream_t s);
 
 // Persistent form of launch_step (update only): `grid` work-groups take
 // (step, item) tickets in order and advance every member a.steps steps; an

@@ -834,18 +834,19 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepAr
 
 // -------------------------------------- temporal blocking: two steps ----
 // k_step2 advances every member two steps per pass over HBM (psi and V read
-// once, psi'' written once).  A work item owns a chunk of F = 256 VZ RY sites
-// of the flattened (y, z) plane and streams x.  Step t runs on its own
-// vectors plus one halo vector per lane covering the N sites before and the
-// N after the chunk (the y and z neighbours of the chunk's edge sites), with
-// the loads and arithmetic of the one-step kernel; its results stay in
-// registers (own vectors, planes x - 1, x, x + 1) and go to an LDS copy of
-// the plane for the neighbours.  Step t + 1 follows one plane behind, from
-// registers and LDS.  Per-site arithmetic, reduction grouping and rounding
-// bits are those of one-step launches with renorm_every = 2, so the results
-// are the same bits: step t never rescales, step t + 1 rescales at the end
-// of the pass when the renorm_every rule asks for it.  Needs 2 N <= 256 VZ
-// (one halo vector per lane).
+// once, psi'' written once).  A work item owns a tile of kTbRows(DT) x
+// kTbCols(DT) sites of the (y, z) plane and streams x; each lane holds one
+// vector of VZ consecutive z sites (a tile row is 256 bytes).
+// Step t runs on the tile's own vectors and on a frame of single halo sites
+// (the rows y0 - 1 and y0 + rows, the columns z0 - 1 and z0 + cols), with the
+// loads and arithmetic of the one-step kernel; its results stay in registers
+// (planes x - 1, x, x + 1 of the own vectors) and go to an LDS copy of the
+// framed tile for the y / z neighbours.  Step t + 1 follows one plane behind,
+// from registers and LDS.  Per-site arithmetic is that of the one-step
+// kernel, so with the rescale off the states are the same bits; the
+// reductions group their sums by tile instead of by flattened chunk (FP64
+// summation order only).  Step t never rescales; step t + 1 takes a rescale
+// due after either step.
 // Work-group barrier fenced on LDS only: outstanding global loads (the
 // prefetched planes) stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {
@@ -854,100 +855,102 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-template <int DT, int VZ, int RY, int D, bool FV>
+template <int DT, int VZ, int D, bool FV>
 struct Step2 {
   static constexpr int BT = 256;
-  using B1 = StepBody<DT, VZ, RY + 1, true, FV>;  // step t: own vectors + the halo vector
-  using B2 = StepBody<DT, VZ, RY, true, FV>;      // step t + 1: own vectors
-  using S = typename B1::S;
-  using TV = typename B1::TV;
-  using C = typename B1::C;
-  static constexpr unsigned kES = sizeof(S);
+  static constexpr int TZ = kTbCols(DT);            // tile columns (z sites)
+  static constexpr int LPR = TZ / VZ;               // lanes per tile row
+  static constexpr int TY = BT / LPR;               // tile rows
+  static constexpr int NH = 2 * TZ + 2 * TY;        // halo sites, one per lane
+  static constexpr int NHW = (NH + 63) / 64;        // waves that carry halo sites
+  static constexpr int RP = TZ + 8;                 // LDS row pitch: own z at 4 .. 4 + TZ - 1
+  static constexpr int TS = (TY + 2) * RP;          // LDS plane: rows y0 - 1 .. y0 + TY
+  static_assert(TY == kTbRows(DT) && TZ % VZ == 0, "tile shape");
+  static_assert(NH <= BT, "one halo site per lane");
+  using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
+  using H = StepBody<DT, 1, 1, true, FV>;   // halo sites
+  using C = typename B::C;
 
   struct Rings {
-    C qs[6][RY + 1][VZ];               // psi_t of planes, own + halo
-    C vs[6][RY + 1][VZ];               // V of planes, own + halo
-    PlaneIn<RY + 1, VZ, C> nb[6];      // y / z neighbours of psi_t planes
-    C us[3][RY][VZ];                   // step-t results, own vectors
+    C qs[6][1][VZ];          // psi_t of planes, own vectors
+    C vs[6][1][VZ];          // V of planes
+    PlaneIn<1, VZ, C> nb[6]; // y / z neighbours of psi_t planes
+    C qh[6][1][1];           // the same for the lane's halo site
+    C vh[6][1][1];
+    PlaneIn<1, 1, C> nh[6];
+    C us[3][1][VZ];          // step-t results, own vectors
   };
 
-  // Stage X (slot SL = (X - base) % 6 with base = xb - 1): prefetch, step t
-  // at plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1
-  // at plane X - 1, then the work-group barrier.
+  // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
+  // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
+  // plane X - 1, then the work-group barrier.
   template <int SL, bool STEP2>
-  static __device__ __forceinline__ void stage(const typename B1::Ctx& k1,
-                                               const typename B2::Ctx& k2,
-                                               const Lane<RY + 1, VZ, C>& ln1, const bool (&own)[RY],
-                                               int X, int xb, int xe, C* tile, unsigned TS,
-                                               unsigned N, Rings& g, double (&acc1)[5],
-                                               double (&acc2)[5]) {
-    const int tid = threadIdx.x;
-    B1::fetch_own(k1, ln1, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
-    B1::fetch_v(k1, ln1, X + D, g.vs[(SL + D) % 6]);
-    B1::fetch(k1, ln1, X + D, g.nb[(SL + D) % 6]);
-    // step t at plane X: the work item's own planes [xb, xe) count in the
-    // reductions, the halo planes xb - 1 and xe do not
-    double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    C un[RY + 1][VZ];
-    B1::template update_core<false, true, RY>(k1, ln1, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
-                                              g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
-                                              tmp, true, un);
-    if (X >= xb && X < xe) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) acc1[q] += tmp[q];
+  static __device__ __forceinline__ void stage(const typename B::Ctx& kb,
+                                               const typename H::Ctx& kh,
+                                               const typename B::Ctx& k2,
+                                               const Lane<1, VZ, C>& lb, const Lane<1, 1, C>& lh,
+                                               bool own, bool halo_wave, int obase, int hidx,
+                                               int X, int xb, int xe, unsigned N, C* tile,
+                                               Rings& g, double (&acc1)[5], double (&acc2)[5]) {
+    B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
+    B::fetch_v(kb, lb, X + D, g.vs[(SL + D) % 6]);
+    B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
+    if (halo_wave) {
+      H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % 6]);
+      H::fetch_v(kh, lh, X + D, g.vh[(SL + D) % 6]);
+      H::fetch(kh, lh, X + D, g.nh[(SL + D) % 6]);
     }
     // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
     // one-step kernel drops their stores; here they feed step t + 1)
     const bool inx = (unsigned)X < N;
+    C* t = tile + (X & 1) * TS;
+    {
+      // step t, own vectors: the work item's planes [xb, xe) count in the
+      // reductions, the halo planes xb - 1 and xe do not
+      double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      C un[1][VZ];
+      B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                              g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
+                                              tmp, true, un);
+      if (X >= xb && X < xe) {
 #pragma unroll
-    for (int r = 0; r <= RY; ++r)
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) un[r][j] = inx ? un[r][j] : C(0);
-    C* t = tile + (unsigned)(X & 1) * TS;
-#pragma unroll
-    for (int r = 0; r <= RY; ++r) {
-      // own vector r at N + (r * BT + tid) * VZ, the halo vector at its
-      // flattened offset from the chunk start - N
-      const unsigned idx = r < RY ? N + (unsigned)(r * BT + tid) * VZ
-                                  : ((unsigned)tid < N / VZ ? (unsigned)tid * VZ
-                                                            : TS - 2u * N + (unsigned)tid * VZ);
-      const bool put = r < RY || (unsigned)tid < 2u * N / VZ;
-      if (put) {
-        Pack<C, VZ> pk;
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) pk.v[j] = un[r][j];
-        *reinterpret_cast<Pack<C, VZ>*>(t + idx) = pk;
+        for (int q = 0; q < 5; ++q) acc1[q] += tmp[q];
       }
+      Pack<C, VZ> pk;
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        pk.v[j] = inx ? un[0][j] : C(0);
+        g.us[SL % 3][0][j] = pk.v[j];
+      }
+      *reinterpret_cast<Pack<C, VZ>*>(t + obase) = pk;
     }
-#pragma unroll
-    for (int r = 0; r < RY; ++r)
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) g.us[SL % 3][r][j] = un[r][j];
+    if (halo_wave) {
+      // step t, halo site (no reductions: another work item owns it)
+      double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      C uh[1][1];
+      H::template update_core<false, true, 0>(kh, lh, X, g.qh[SL % 6], g.qh[(SL + 1) % 6],
+                                              g.qh[(SL + 2) % 6], g.vh[SL % 6], g.nh[SL % 6],
+                                              tmp, true, uh);
+      if ((int)threadIdx.x < NH) t[hidx] = inx ? uh[0][0] : C(0);
+    }
     if constexpr (STEP2) {
       // step t + 1 at plane X - 1: psi_{t+1} planes X - 2, X - 1, X in
       // registers, the y / z neighbours of plane X - 1 from LDS.  A vector
-      // past the end of the plane (not lattice sites) gets zero neighbours,
-      // as its loads in the one-step kernel: its result is not stored, but
-      // it enters the output norm.
-      const C* tp = tile + (unsigned)((X - 1) & 1) * TS;
-      PlaneIn<RY, VZ, C> d;
+      // outside the lattice gets zero neighbours, as its loads in the
+      // one-step kernel: its result is not stored, but it enters the norm.
+      const C* tp = tile + ((X - 1) & 1) * TS;
+      PlaneIn<1, VZ, C> d;
+      const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase - RP);
+      const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase + RP);
 #pragma unroll
-      for (int r = 0; r < RY; ++r) {
-        const unsigned idx = N + (unsigned)(r * BT + tid) * VZ;
-        const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + idx - N);
-        const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + idx + N);
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-          d.ym[r][j] = own[r] ? pm.v[j] : C(0);
-          d.yp[r][j] = own[r] ? pp.v[j] : C(0);
-        }
-        d.zm[r] = own[r] ? tp[idx - 1] : C(0);
-        d.zp[r] = own[r] ? tp[idx + VZ] : C(0);
+      for (int j = 0; j < VZ; ++j) {
+        d.ym[0][j] = own ? pm.v[j] : C(0);
+        d.yp[0][j] = own ? pp.v[j] : C(0);
       }
-      const C(&vown)[RY][VZ] = reinterpret_cast<const C(&)[RY][VZ]>(g.vs[(SL + 5) % 6]);
-      // the lane's first RY vectors are the own ones
-      B2::template update<false>(k2, ln1, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
-                                 g.us[SL % 3], vown, d, acc2);
+      d.zm[0] = own ? tp[obase - 1] : C(0);
+      d.zp[0] = own ? tp[obase + VZ] : C(0);
+      B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
+                                g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
     }
     lds_barrier();
   }
@@ -985,21 +988,25 @@ __device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f,
   Body::hash_lane(ln, r, N, key);
 }
 
-template <int DT, int VZ, int RY, int D, bool FV>
-__global__ __launch_bounds__(256, FDTD_STEP_MIN_WAVES) void k_step2(StepArgs A) {
-  using T = Step2<DT, VZ, RY, D, FV>;
-  using B1 = typename T::B1;
-  using B2 = typename T::B2;
-  using S = typename T::S;
-  using TV = typename T::TV;
+#ifndef FDTD_TB_MIN_WAVES
+#define FDTD_TB_MIN_WAVES 1  // waves per SIMD the register budget must allow
+#endif
+
+template <int DT, int VZ, int D, bool FV>
+__global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
+  using T = Step2<DT, VZ, D, FV>;
+  using B = typename T::B;
+  using H = typename T::H;
   using C = typename T::C;
+  using TV = typename B::TV;
   constexpr int BT = 256;
-  constexpr unsigned kES = sizeof(S);
-  extern __shared__ __align__(16) unsigned char smem[];
-  C* tile = reinterpret_cast<C*>(smem);
+  constexpr unsigned kES = sizeof(typename B::S);
+  __shared__ __align__(16) C tile[2 * T::TS];
   __shared__ double s_red[BT / 64][5];
   __shared__ int s_last;
   const int tid = threadIdx.x;
+  // the waves that carry halo sites (uniform per wave)
+  const bool halo_wave = __builtin_amdgcn_readfirstlane(tid >> 6) < T::NHW;
 
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x) {
     const Item item = A.items[A.item_offset + li];
@@ -1007,89 +1014,111 @@ __global__ __launch_bounds__(256, FDTD_STEP_MIN_WAVES) void k_step2(StepArgs A) 
     const MemberDev& M = A.members[m];
     const int N = M.N;
     const unsigned P = (unsigned)M.plane;
-    const unsigned F = (unsigned)(BT * VZ * RY);
-    const unsigned TS = F + 2u * (unsigned)N;  // LDS plane: chunk plus N sites each side
     const double cN = (double)(N - 1), ha = M.ha;
     const long long step = ld_agent(A.states[m].step);
+    const int y0 = item.f0 / N, z0 = item.f0 - y0 * N;  // tile origin
 
-    typename B1::Ctx k1;
-    k1.in = M.psi[A.src];
-    k1.out = M.psi[A.src ^ 1];  // unused: step t goes to registers
-    k1.Vf = static_cast<const TV*>(M.V);
-    k1.pbytes = P * kES;
-    k1.vbytes = P * (unsigned)sizeof(TV);
-    k1.N = N;
-    k1.xe = item.xe + 1;  // step t also runs on plane xe (the halo plane)
-    k1.c = (C)M.c;
-    k1.dt = (C)M.dt;
-    k1.eps = (C)(0.5 * M.dt);
-    k1.sc = (C)ld_agent(A.states[m].scale);
-    k1.ha = ha;
-    k1.cN = cN;
-    k1.smix = hash32((uint32_t)step);
-    if constexpr (FV) B1::vcoef(k1, M.vkind, M.vp, M.a);
-    typename B2::Ctx k2;
-    k2.in = M.psi[A.src];
-    k2.out = M.psi[A.src ^ 1];
-    k2.Vf = k1.Vf;
-    k2.pbytes = k1.pbytes;
-    k2.vbytes = k1.vbytes;
-    k2.N = N;
+    typename B::Ctx kb;
+    kb.in = M.psi[A.src];
+    kb.out = M.psi[A.src ^ 1];  // unused: step t goes to registers
+    kb.Vf = static_cast<const TV*>(M.V);
+    kb.pbytes = P * kES;
+    kb.vbytes = P * (unsigned)sizeof(TV);
+    kb.N = N;
+    kb.xe = item.xe + 1;  // step t also runs on plane xe (the halo plane)
+    kb.c = (C)M.c;
+    kb.dt = (C)M.dt;
+    kb.eps = (C)(0.5 * M.dt);
+    kb.sc = (C)ld_agent(A.states[m].scale);
+    kb.ha = ha;
+    kb.cN = cN;
+    kb.smix = hash32((uint32_t)step);
+    if constexpr (FV) B::vcoef(kb, M.vkind, M.vp, M.a);
+    typename H::Ctx kh;
+    kh.in = kb.in;
+    kh.out = kb.out;
+    kh.Vf = kb.Vf;
+    kh.pbytes = kb.pbytes;
+    kh.vbytes = kb.vbytes;
+    kh.N = N;
+    kh.xe = kb.xe;
+    kh.c = kb.c;
+    kh.dt = kb.dt;
+    kh.eps = kb.eps;
+    kh.sc = kb.sc;
+    kh.ha = ha;
+    kh.cN = cN;
+    kh.smix = kb.smix;
+    if constexpr (FV) H::vcoef(kh, M.vkind, M.vp, M.a);
+    typename B::Ctx k2 = kb;
     k2.xe = item.xe;
-    k2.c = k1.c;
-    k2.dt = k1.dt;
-    k2.eps = k1.eps;
     k2.sc = C(1);  // no rescale between the two steps of a pass
-    k2.ha = ha;
-    k2.cN = cN;
     k2.smix = hash32((uint32_t)(step + 1));
-    if constexpr (FV) B2::vcoef(k2, M.vkind, M.vp, M.a);
 
-    Lane<RY + 1, VZ, C> ln1;
-    bool own[RY];
-#pragma unroll
-    for (int r = 0; r < RY; ++r) {
-      const unsigned f = (unsigned)item.f0 + (unsigned)(r * BT + tid) * VZ;
-      own[r] = f < P;
-      tb_lane<B1>(ln1, r, f, own[r], M, N, cN, ha);
+    // own vector: row tid / LPR, columns (tid % LPR) * VZ of the tile
+    const int ly = tid / T::LPR, lz = (tid % T::LPR) * VZ;
+    const int yo = y0 + ly, zo = z0 + lz;
+    const bool own = yo < N && zo < N;
+    const int obase = (ly + 1) * T::RP + 4 + lz;
+    Lane<1, VZ, C> lb;
+    tb_lane<B>(lb, 0, (unsigned)(yo * N + zo), own, M, N, cN, ha);
+    // halo site of lanes below NH: row y0 - 1, row y0 + TY, column z0 - 1,
+    // column z0 + TZ
+    int hy, hz, hidx;
+    if (tid < T::TZ) {
+      hy = y0 - 1, hz = z0 + tid, hidx = 4 + tid;
+    } else if (tid < 2 * T::TZ) {
+      hy = y0 + T::TY, hz = z0 + tid - T::TZ, hidx = (T::TY + 1) * T::RP + 4 + tid - T::TZ;
+    } else if (tid < 2 * T::TZ + T::TY) {
+      hy = y0 + tid - 2 * T::TZ, hz = z0 - 1, hidx = (tid - 2 * T::TZ + 1) * T::RP + 3;
+    } else {
+      hy = y0 + tid - 2 * T::TZ - T::TY, hz = z0 + T::TZ;
+      hidx = (tid - 2 * T::TZ - T::TY + 1) * T::RP + 4 + T::TZ;
     }
-    {
-      // halo vector: lanes below N / VZ take the N sites before the chunk,
-      // the next N / VZ lanes the N sites after it; the rest idle
-      const unsigned nh = (unsigned)N / VZ;
-      const unsigned u = (unsigned)tid;
-      const unsigned f = u < nh ? (unsigned)item.f0 - (unsigned)N + u * VZ
-                                : (unsigned)item.f0 + F + (u - nh) * VZ;  // may wrap: not a site
-      tb_lane<B1>(ln1, RY, f, u < 2u * nh && f < P, M, N, cN, ha);
-    }
+    const bool hok = tid < T::NH && hy >= 0 && hy < N && hz >= 0 && hz < N;
+    Lane<1, 1, C> lh;
+    tb_lane<H>(lh, 0, hok ? (unsigned)(hy * N + hz) : 0u, hok, M, N, cN, ha);
 
     double acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     typename T::Rings g;
     const int xb = item.xb, xe = item.xe, base = xb - 1;
 #pragma unroll
-    for (int i = 0; i < D + 2; ++i) B1::fetch_own(k1, ln1, base - 1 + i, g.qs[i]);
+    for (int i = 0; i < D + 2; ++i) B::fetch_own(kb, lb, base - 1 + i, g.qs[i]);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      B1::fetch_v(k1, ln1, base + i, g.vs[i]);
-      B1::fetch(k1, ln1, base + i, g.nb[i]);
+      B::fetch_v(kb, lb, base + i, g.vs[i]);
+      B::fetch(kb, lb, base + i, g.nb[i]);
     }
+    if (halo_wave) {
+#pragma unroll
+      for (int i = 0; i < D + 2; ++i) H::fetch_own(kh, lh, base - 1 + i, g.qh[i]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        H::fetch_v(kh, lh, base + i, g.vh[i]);
+        H::fetch(kh, lh, base + i, g.nh[i]);
+      }
+    }
+#define FDTD_STAGE2(SL, S2, XX)                                                                  \
+  T::template stage<SL, S2>(kb, kh, k2, lb, lh, own, halo_wave, obase, hidx, XX, xb, xe,         \
+                            (unsigned)N, tile, g, acc1, acc2)
     // planes xb - 1 and xb: step t only; then both steps, six stages a trip
-    T::template stage<0, false>(k1, k2, ln1, own, base, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-    T::template stage<1, false>(k1, k2, ln1, own, base + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    FDTD_STAGE2(0, false, base);
+    FDTD_STAGE2(1, false, base + 1);
     int X = xb + 1;
     for (; X + 6 <= xe + 1; X += 6) {
-      T::template stage<2, true>(k1, k2, ln1, own, X, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-      T::template stage<3, true>(k1, k2, ln1, own, X + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-      T::template stage<4, true>(k1, k2, ln1, own, X + 2, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-      T::template stage<5, true>(k1, k2, ln1, own, X + 3, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-      T::template stage<0, true>(k1, k2, ln1, own, X + 4, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-      T::template stage<1, true>(k1, k2, ln1, own, X + 5, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+      FDTD_STAGE2(2, true, X);
+      FDTD_STAGE2(3, true, X + 1);
+      FDTD_STAGE2(4, true, X + 2);
+      FDTD_STAGE2(5, true, X + 3);
+      FDTD_STAGE2(0, true, X + 4);
+      FDTD_STAGE2(1, true, X + 5);
     }
-    if (X <= xe) T::template stage<2, true>(k1, k2, ln1, own, X, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-    if (X + 1 <= xe) T::template stage<3, true>(k1, k2, ln1, own, X + 1, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-    if (X + 2 <= xe) T::template stage<4, true>(k1, k2, ln1, own, X + 2, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-    if (X + 3 <= xe) T::template stage<5, true>(k1, k2, ln1, own, X + 3, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
-    if (X + 4 <= xe) T::template stage<0, true>(k1, k2, ln1, own, X + 4, xb, xe, tile, TS, (unsigned)N, g, acc1, acc2);
+    if (X <= xe) FDTD_STAGE2(2, true, X);
+    if (X + 1 <= xe) FDTD_STAGE2(3, true, X + 1);
+    if (X + 2 <= xe) FDTD_STAGE2(4, true, X + 2);
+    if (X + 3 <= xe) FDTD_STAGE2(5, true, X + 3);
+    if (X + 4 <= xe) FDTD_STAGE2(0, true, X + 4);
+#undef FDTD_STAGE2
 
     // ---- partials of both steps; the member's last work-group finalises them
     block_sum<5, BT / 64>(acc1, s_red);
@@ -1104,13 +1133,13 @@ __global__ __launch_bounds__(256, FDTD_STEP_MIN_WAVES) void k_step2(StepArgs A) 
       }
       __threadfence();
       const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
-      s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
+      s_last = (done + 1u == (unsigned int)(M.tb_end - M.tb_begin));
     }
     __syncthreads();
     if (s_last) {
       __threadfence();
       double t1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, t2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-      for (int i = M.item_begin + tid; i < M.item_end; i += BT) {
+      for (int i = M.tb_begin + tid; i < M.tb_end; i += BT) {
         const double* p1 = A.partials + (long long)i * kRec;
         const double* p2 = A.partials + (long long)(A.slot_stride + i) * kRec;
 #pragma unroll
@@ -1955,8 +1984,9 @@ int tile_threads(int dtype) { return dtype == kBF16 ? 512 : 1024; }
 hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max_n,
                             const StepArgs& a, hipStream_t s) {
   const unsigned vz = dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8);
-  // one halo vector per lane covers the N sites on each side of the chunk
-  if (grid < 1 || max_n < 1 || 2u * (unsigned)max_n > 256u * vz) return hipErrorInvalidValue;
+  // the first 2N / vz lanes load the halo rows: 2N <= (lanes) vz
+  if (grid < 1 || max_n < 1 || 2u * (unsigned)max_n > (unsigned)tile_threads(dtype) * vz)
+    return hipErrorInvalidValue;
   const unsigned cs = dtype == kF64 ? 8 : 4;
   const unsigned lds = 2u * ((unsigned)tile_threads(dtype) * vz + 2u * (unsigned)max_n) * cs;
   switch (dtype) {
@@ -1967,46 +1997,33 @@ hipError_t launch_step_tile(int dtype, int depth, bool update, int grid, int max
   }
 }
 
-template <int DT, int VZ, int RY, int D, bool FV>
-hipError_t step2_one(int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_step2<DT, VZ, RY, D, FV>), dim3(grid), dim3(256), lds, s, a);
+namespace {
+
+template <int DT, int D, bool FV>
+hipError_t step2_one(int grid, const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_step2<DT, Types<DT>::kVec, D, FV>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-// Shapes whose registers fit one wave per SIMD without spilling much: one
-// own vector per lane (the halo vector doubles the first step's state), FP64
-// without deep prefetch; BF16 lanes (8 sites) do not fit.
-template <int DT, int VZ, bool FV>
-hipError_t step2_ry(int ry, int depth, int grid, unsigned lds, const StepArgs& a, hipStream_t s) {
-  if (ry != 1) return hipErrorInvalidValue;
-  if (depth == 1) return step2_one<DT, VZ, 1, 1, FV>(grid, lds, a, s);
-  if constexpr (DT == kF32) {
-    if (depth == 2) return step2_one<DT, VZ, 1, 2, FV>(grid, lds, a, s);
+template <int DT, bool FV>
+hipError_t step2_depth(int depth, int grid, const StepArgs& a, hipStream_t s) {
+  switch (depth) {
+    case 1: return step2_one<DT, 1, FV>(grid, a, s);
+    case 2: return step2_one<DT, 2, FV>(grid, a, s);
+    case 3: return step2_one<DT, 3, FV>(grid, a, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipErrorInvalidValue;
 }
 
-template <int DT>
-hipError_t step2_dt(int ry, int depth, bool fv, int grid, unsigned lds, const StepArgs& a,
-                    hipStream_t s) {
-  constexpr int VZ = Types<DT>::kVec;
-  if constexpr (DT == kF32) {
-    if (fv) return step2_ry<DT, VZ, true>(ry, depth, grid, lds, a, s);
-  }
-  if (fv) return hipErrorInvalidValue;
-  return step2_ry<DT, VZ, false>(ry, depth, grid, lds, a, s);
-}
+}  // namespace
 
-hipError_t launch_step2(int dtype, int ry, int depth, bool fv, int grid, int max_n,
-                        const StepArgs& a, hipStream_t s) {
-  const unsigned vz = dtype == kF64 ? 2 : (dtype == kF32 ? 4 : 8);
-  // one halo vector per lane covers the N sites on each side of the chunk
-  if (grid < 1 || max_n < 1 || 2u * (unsigned)max_n > 256u * vz) return hipErrorInvalidValue;
-  const unsigned cs = dtype == kF64 ? 8 : 4;
-  const unsigned lds = 2u * (256u * vz * (unsigned)ry + 2u * (unsigned)max_n) * cs;
+hipError_t launch_step2(int dtype, int depth, bool fv, int grid, const StepArgs& a,
+                        hipStream_t s) {
+  if (grid < 1) return hipErrorInvalidValue;
   switch (dtype) {
-    case kF64: return step2_dt<kF64>(ry, depth, fv, grid, lds, a, s);
-    case kF32: return step2_dt<kF32>(ry, depth, fv, grid, lds, a, s);
+    case kF64: return fv ? hipErrorInvalidValue : step2_depth<kF64, false>(depth, grid, a, s);
+    case kF32: return fv ? step2_depth<kF32, true>(depth, grid, a, s)
+                         : step2_depth<kF32, false>(depth, grid, a, s);
     default: return hipErrorInvalidValue;
   }
 }

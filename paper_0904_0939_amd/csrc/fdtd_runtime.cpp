@@ -60,6 +60,7 @@ struct MemberHost {
   bool pot_set = false, init_set = false;
   uint32_t parity = 0;
   int item_begin = 0, item_end = 0;
+  int tb_begin = 0, tb_end = 0;  // tiles of two-step passes (member order)
   int vkind = -1;  // analytic kind the step may evaluate itself (0..4), -1: table only
   double vp[3] = {0, 0, 0};
   int nproj = 0;          // states kept for projection (Sec. III)
@@ -94,12 +95,16 @@ struct fdtd_ctx {
   // work items (library-allocated, depend on the tuning): d_items in member
   // order (a member's items at [item_begin, item_end), for per-member
   // launches), d_order the same items in the order whole-batch launches
-  // process them; both live in one allocation of 2 * items_cap
+  // process them, d_titems the tiles of two-step passes in processing order
+  // (tblock = 2 only); one allocation of 2 * items_cap + titems_cap
   Item* d_items = nullptr;
   Item* d_order = nullptr;
+  Item* d_titems = nullptr;
   double* d_partials = nullptr;
   int n_items = 0;
   int items_cap = 0;
+  int n_titems = 0;
+  int titems_cap = 0;
   bool items_valid = false;
 
   int cur = 0;  // buffer holding the current state (all members)
@@ -254,6 +259,8 @@ MemberDev member_dev(fdtd_ctx* h, int i) {
   d.N = m.N;
   d.item_begin = m.item_begin;
   d.item_end = m.item_end;
+  d.tb_begin = m.tb_begin;
+  d.tb_end = m.tb_end;
   d.plane = (long long)m.N * m.N;
   d.ha = m.ha;
   d.c = m.c;
@@ -321,82 +328,122 @@ int x_bound(int N, int nx, int b) { return (int)(((long long)b * N) / nx); }
 // long-streaming work-group per CU beats more, shorter ones; on the batch of
 // 64 lattices of side 48..160, whole-N items handed out longest first beat
 // every shorter split (item start-up outweighs the better balance).
-int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
+// Work items per plane of a lattice of side N: chunks of the flattened plane,
+// or (two steps per pass) tiles of the (y, z) plane.
+long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
+  if (t.tblock == 2) {
+    const long long ty = kTbRows(h->dtype), tz = kTbCols(h->dtype);
+    return ((N + ty - 1) / ty) * ((N + tz - 1) / tz);
+  }
   const long long F = chunk_sites(h, t);
+  return ((long long)N * N + F - 1) / F;
+}
+
+int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
   for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;
-    for (const auto& m : h->mem) items += (((long long)m.N * m.N + F - 1) / F) * x_parts(m.N, xc);
+    for (const auto& m : h->mem) items += plane_items(h, t, m.N) * x_parts(m.N, xc);
     if (items >= 256) return xc;
   }
   return 8;
 }
 
-fdtd_status build_items(fdtd_ctx* h) {
-  if (h->items_valid) return FDTD_OK;
-  fdtd_tuning t = h->tun;
+// Work items of every member for the tuning t: chunks of the flattened plane
+// (tiles = false) or tiles of the (y, z) plane (two steps per pass), times
+// the x-ranges; phys in member order (slot = index), order in processing
+// order: each member's items optionally permuted so that the work-groups one
+// XCD runs take neighbouring tiles; on a batch, longest items first (stable,
+// so the permutation survives among equal lengths), which keeps the slots
+// busy to the end of the launch.
+void make_items(fdtd_ctx* h, fdtd_tuning t, bool tiles, std::vector<Item>& phys,
+                std::vector<Item>& order, std::vector<int>& begin, std::vector<int>& end) {
+  t.tblock = tiles ? 2 : 0;
   if (t.xchunk == 0) t.xchunk = auto_xchunk(h, t);
-  std::vector<Item> phys;
+  const long long F = chunk_sites(h, t);
+  const int ty = kTbRows(h->dtype);
+  phys.clear();
+  order.clear();
+  begin.assign(h->count, 0);
+  end.assign(h->count, 0);
   for (int i = 0; i < h->count; ++i) {
-    MemberHost& m = h->mem[i];
-    const long long P = (long long)m.N * m.N;
-    const long long F = chunk_sites(h, t);
-    const int nchunk = (int)((P + F - 1) / F);
-    const int nx = x_parts(m.N, t.xchunk);
-    m.item_begin = (int)phys.size();
+    const int N = h->mem[i].N;
+    const int nchunk = (int)plane_items(h, t, N);
+    const int tz_n = (N + kTbCols(h->dtype) - 1) / kTbCols(h->dtype);  // tiles row-major over the plane
+    const int nx = x_parts(N, t.xchunk);
+    begin[i] = (int)phys.size();
     for (int bx = 0; bx < nx; ++bx)
       for (int ch = 0; ch < nchunk; ++ch) {
         Item it;
         it.member = i;
-        it.f0 = (int)(ch * F);
-        it.xb = x_bound(m.N, nx, bx);
-        it.xe = x_bound(m.N, nx, bx + 1);
+        it.f0 = tiles ? (ch / tz_n) * ty * N + (ch % tz_n) * kTbCols(h->dtype) : (int)(ch * F);
+        it.xb = x_bound(N, nx, bx);
+        it.xe = x_bound(N, nx, bx + 1);
         it.slot = (int)phys.size();
         phys.push_back(it);
       }
-    m.item_end = (int)phys.size();
+    end[i] = (int)phys.size();
   }
-  const int n = (int)phys.size();
-  // Processing order: each member's items optionally permuted so that the
-  // work-groups one XCD runs take neighbouring tiles; on a batch, longest
-  // items first (stable, so the permutation survives among equal lengths),
-  // which keeps the slots busy to the end of the launch.
-  std::vector<Item> order;
-  order.reserve(n);
+  order.reserve(phys.size());
   for (int i = 0; i < h->count; ++i) {
-    const MemberHost& m = h->mem[i];
-    const int cnt = m.item_end - m.item_begin;
+    const int cnt = end[i] - begin[i];
     std::vector<int> p;
     if (t.xcd_remap) xcd_permute(p, cnt);
     else {
       p.resize(cnt);
       for (int b = 0; b < cnt; ++b) p[b] = b;
     }
-    for (int b = 0; b < cnt; ++b) order.push_back(phys[m.item_begin + p[b]]);
+    for (int b = 0; b < cnt; ++b) order.push_back(phys[begin[i] + p[b]]);
   }
   if (h->count > 1)
     std::stable_sort(order.begin(), order.end(),
                      [](const Item& a, const Item& b) { return a.xe - a.xb > b.xe - b.xb; });
-  if (n > h->items_cap) {
+}
+
+fdtd_status build_items(fdtd_ctx* h) {
+  if (h->items_valid) return FDTD_OK;
+  std::vector<Item> phys, order, tphys, torder;
+  std::vector<int> b, e, tb, te;
+  make_items(h, h->tun, false, phys, order, b, e);
+  if (h->tun.tblock == 2) make_items(h, h->tun, true, tphys, torder, tb, te);
+  for (int i = 0; i < h->count; ++i) {
+    h->mem[i].item_begin = b[i];
+    h->mem[i].item_end = e[i];
+    h->mem[i].tb_begin = tb.empty() ? 0 : tb[i];
+    h->mem[i].tb_end = te.empty() ? 0 : te[i];
+  }
+  const int n = (int)phys.size(), nt = (int)tphys.size();
+  if (n > h->items_cap || nt > h->titems_cap) {
     if (h->d_items) (void)hipFree(h->d_items);
     if (h->d_partials) (void)hipFree(h->d_partials);
     h->d_items = nullptr;
     h->d_order = nullptr;
+    h->d_titems = nullptr;
     h->d_partials = nullptr;
     h->items_cap = 0;
-    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * 2 * (size_t)n);
-    // two slots per work item: a two-step pass keeps both steps' partials
-    hipError_t e2 = hipMalloc((void**)&h->d_partials, sizeof(double) * kRec * 2 * (size_t)n);
+    h->titems_cap = 0;
+    const int cap = n, tcap = nt;
+    // chunk items in member and processing order, then the tiles in
+    // processing order; partials: one slot per chunk item, two per tile (a
+    // two-step pass keeps both steps' sums)
+    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * (2 * (size_t)cap + (size_t)tcap));
+    hipError_t e2 = hipMalloc((void**)&h->d_partials,
+                              sizeof(double) * kRec * std::max((size_t)cap, 2 * (size_t)tcap));
     if (e1 != hipSuccess || e2 != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "device allocation of work items failed");
     }
-    h->items_cap = n;
+    h->items_cap = cap;
+    h->titems_cap = tcap;
   }
   h->d_order = h->d_items + h->items_cap;
+  h->d_titems = h->d_order + h->items_cap;
   HIP_TRY(hipMemcpyAsync(h->d_items, phys.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->d_order, order.data(), sizeof(Item) * n, hipMemcpyHostToDevice, h->stream));
+  if (nt)
+    HIP_TRY(hipMemcpyAsync(h->d_titems, torder.data(), sizeof(Item) * nt, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->n_items = n;
+  h->n_titems = nt;
   ST_TRY(upload_members(h));
   h->items_valid = true;
   return FDTD_OK;
@@ -490,9 +537,10 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
     for (; k + 2 <= n; k += 2) {
       StepArgs a = base_args(h);
       a.renorm_every = renorm_every;
-      a.slot_stride = h->n_items;
-      HIP_TRY(launch_step2(h->dtype, h->tun.ry, h->tun.depth, use_fv(h), launch_grid(h, a.n_items),
-                           max_n(h), a, s));
+      a.items = h->d_titems;
+      a.n_items = h->n_titems;
+      a.slot_stride = h->n_titems;
+      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), launch_grid(h, a.n_items), a, s));
       h->cur ^= 1;  // psi_{t+2} is in the other buffer
     }
   }
@@ -701,9 +749,6 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
     if (h->dtype == kBF16) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs an F32 or F64 lattice");
     if (t.variant != 0 || t.persist != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0 and persist 0");
     if (t.ry != 1 || t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs ry = 1 and vz = the dtype's vector width");
-    if (t.depth > (h->dtype == kF32 ? 2 : 1)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs depth <= 2 (F32) or 1 (F64)");
-    for (auto& m : h->mem)
-      if (2LL * m.N > 256LL * t.vz) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs 2N <= 256 vz");
   }
   if (t.variant == 2) {
     if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");

@@ -1,9 +1,11 @@
 """Temporal blocking (tuning field `tblock` = 2): one pass over HBM advances a
-lattice two steps.  Whenever no rescale falls inside a pass (renorm_every = 2
-from step 0) it must give the same bits as one launch per step of the same
-launch shape; with a rescale every step, or passes that start at an odd step,
-it must still follow the FP64 oracle to the parity tolerances (FP64 1e-10,
-FP32 1e-5)."""
+lattice two steps, on tiles of the (y, z) plane.  With the rescale off it
+must give the same bits as one launch per step of the same vector width (the
+per-site arithmetic is shared; only the FP64 summation order of the
+reductions differs, tiles instead of flattened chunks); with a rescale every
+second step the states agree to the rounding of that order; with a rescale
+every step, or passes that start at an odd step, it must follow the FP64
+oracle to the parity tolerances (FP64 1e-10, FP32 1e-5)."""
 import sys
 
 import numpy as np
@@ -14,7 +16,7 @@ pytestmark = pytest.mark.gpu
 import oracle as orc  # noqa: E402
 from paper_0904_0939_amd import fdtd as F  # noqa: E402
 from paper_0904_0939_amd import workloads as W  # noqa: E402
-from paper_0904_0939_amd.solver import Solver  # noqa: E402
+from paper_0904_0939_amd.solver import Batch, Solver  # noqa: E402
 
 
 def say(*a):
@@ -43,17 +45,24 @@ def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.
     return out
 
 
-# (dtype, N, potential, xchunk, depth, vfuse): chunks of 256 vz sites with a
-# ragged last chunk, several x-ranges per lattice, the in-kernel potential,
-# and the largest side one halo vector per lane covers (2N = 256 vz)
+# (dtype, N, potential, xchunk, depth, vfuse): tiles ragged in y and z,
+# several x-ranges per lattice, the in-kernel potential, and sides beyond
+# 256 vz (F32 tiles are 32 x 32 sites, F64 16 x 32)
 CASES = [
     ("f32", 40, "cornell", 0, 1, 0),
     ("f32", 64, "ho", 8, 2, 0),
     ("f32", 96, "cornell", 24, 1, 1),
-    ("f32", 512, "cornell", 0, 1, 1),
+    ("f32", 516, "cornell", 0, 2, 1),
     ("f64", 48, "ho", 0, 1, 0),
-    ("f64", 256, "cornell", 32, 1, 0),
+    ("f64", 300, "cornell", 32, 1, 0),
 ]
+
+
+def same_records(h1, h2, rel):
+    assert [r["step"] for r in h1] == [r["step"] for r in h2]
+    for a, b in zip(h1, h2):
+        for k in ("norm2", "energy", "kinetic", "potential", "r_rms"):
+            assert a[k] == pytest.approx(b[k], rel=rel, abs=1e-300), (a["step"], k)
 
 
 @pytest.mark.parametrize("dtype,N,pot,xchunk,depth,vfuse", CASES)
@@ -61,19 +70,26 @@ def test_two_step_passes_equal_one_step_launches(dtype, N, pot, xchunk, depth, v
     steps = 40 if N >= 256 else 120
     for graph in (True, False):
         say(f"case: tblock {dtype} N={N} {pot} xchunk={xchunk} depth={depth} vfuse={vfuse} graph={graph}")
-        ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 2, graph)
-        got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 2, graph)
+        # rescale off: the states are the same bits
+        ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 0, graph)
+        got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 0, graph)
         assert np.array_equal(got[0], ref[0])
-        assert got[1] == ref[1]
-        assert got[2] == ref[2]
-        assert ref[1]["step"] == steps
+        assert ref[1]["step"] == got[1]["step"] == steps
+        same_records(got[2], ref[2], 1e-12)
+    # a rescale every second step: the scale comes from sums taken in another
+    # order, so the states agree to that rounding
+    ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 2, True)
+    got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 2, True)
+    assert rel_l2(got[0], ref[0]) < (1e-6 if dtype == "f32" else 1e-13)
+    same_records(got[2], ref[2], 1e-6 if dtype == "f32" else 1e-12)
 
 
 def test_odd_step_count_runs_a_single_step_at_the_end():
     say("case: tblock odd count f32 40^3")
-    ref = run("f32", 40, "ho", 0, 1, 0, 0, 61, 2, True)
-    got = run("f32", 40, "ho", 0, 1, 0, 2, 61, 2, True)
-    assert np.array_equal(got[0], ref[0]) and got[2] == ref[2]
+    ref = run("f32", 40, "ho", 0, 1, 0, 0, 61, 0, True)
+    got = run("f32", 40, "ho", 0, 1, 0, 2, 61, 0, True)
+    assert np.array_equal(got[0], ref[0])
+    same_records(got[2], ref[2], 1e-12)
 
 
 @pytest.mark.parametrize("dtype,N,pot,tol", [("f64", 32, "ho", 1e-10), ("f32", 40, "cornell", 1e-5)])
@@ -100,3 +116,24 @@ def test_rescale_every_step_and_odd_starts_follow_the_oracle(dtype, N, pot, tol)
     assert rel_l2(s.psi(), orc.normalized(psi, L)) < tol
     hist = s.history(0, 303)
     assert [r["step"] for r in hist] == list(range(303))
+
+
+def test_batch_two_step_passes_equal_one_step_launches():
+    """Lattices of several sides in one handle: tiles of every member in one
+    launch, each member's sums finalised by its own last work-group."""
+    say("case: tblock batch f32")
+    rng = np.random.default_rng(4)
+    lats = [W.Lattice(N, 12.0, W.POT_WELLS, W.random_wells(rng), seed=2) for N in (40, 64, 96, 48, 72)]
+    out = []
+    for tblock in (0, 2):
+        b = Batch(lats, dtype="f32")
+        for m, l in enumerate(lats):
+            b.set_potential(l.pot_kind, l.pot_params, member=m)
+        b.set_initial(2)
+        b.set_tuning(4, 1, 0, 0, 1, 2, 0, 0, 0, tblock)
+        b.evolve(60, renorm_every=0)
+        out.append(([b.state(m) for m in range(len(lats))], [b.history(m, 60) for m in range(len(lats))]))
+        b.close()
+    for m in range(len(lats)):
+        assert np.array_equal(out[0][0][m], out[1][0][m]), m
+        same_records(out[1][1][m], out[0][1][m], 1e-12)
