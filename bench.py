@@ -66,10 +66,14 @@ def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
     es = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
     copy_bytes = es * sites
 
+    def is_step(name):
+        if key.endswith("_tb2"):
+            return "k_step2<" in name
+        return "k_step<" in name and ", true," in name
+
     def per_launch(path):
         R = rows(path)
-        step = [float(r["Counter_Value"]) for r in R
-                if "k_step<" in r["Kernel_Name"] and ", true," in r["Kernel_Name"]]
+        step = [float(r["Counter_Value"]) for r in R if is_step(r["Kernel_Name"])]
         copy = [float(r["Counter_Value"]) for r in R if "copyBuffer" in r["Kernel_Name"]]
         return statistics.median(step), max(copy)
 
@@ -83,7 +87,7 @@ def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
     avg_ns = None
     if stats_csv:
         for r in rows(stats_csv):
-            if "k_step<" in r["Name"] and ", true," in r["Name"]:
+            if is_step(r["Name"]):
                 avg_ns = float(r["AverageNs"])
     rec = {"kernel_sha": kernel_hash(), "workloads": {}}
     try:
@@ -317,7 +321,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         f, w, st = args.summarize_rocprof
-        summarize_rocprof(f, w, st if st != "-" else None, f"cornell{args.n}_{args.dtype}",
+        tb = args.tuning.count(",") == 9 and args.tuning.split(",")[9].strip() == "2"
+        summarize_rocprof(f, w, st if st != "-" else None,
+                          f"cornell{args.n}_{args.dtype}" + ("_tb2" if tb else ""),
                           args.n ** 3, args.dtype)
         return
     if args.gpus != 1:
@@ -372,8 +378,12 @@ def main():
     note(f"one step per pass: {ms_per_step:.4f} ms/step")
     sites = N ** 3
     rate = sites * args.steps / (gpu_ms * 1e-3)
+    # one launch reads psi and V once and writes psi once: one step, or two
+    # with temporal blocking
+    tb = tun.get("tblock", 0) == 2
+    steps_per_launch = 2 if tb else 1
     alg_bytes = BYTES_PER_SITE[args.dtype] * sites
-    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = alg_bytes / (steps_per_launch * ms_per_step * 1e-3) / 1e9
     ob = s.observables()[0]
     # a plain device-to-device copy of the state (runtime copy kernel, bytes
     # known): the calibration point of the HBM byte counters
@@ -381,7 +391,7 @@ def main():
     cal = torch.empty((N, N, N), dtype=es, device="cuda")
     F.fdtd_get_state(s.h, 0, cal.data_ptr(), 1)
     del cal
-    key = f"cornell{N}_{args.dtype}"
+    key = f"cornell{N}_{args.dtype}" + ("_tb2" if tb else "")
     traffic = measured_traffic(key, sites)
     in_kernel_v = None
     if not args.no_extras and args.dtype != "f64":
@@ -426,7 +436,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"cornell_{N}^3_{args.dtype}_fused_step",
+        "config": {"workload": f"cornell_{N}^3_{args.dtype}_" + ("two_step_pass" if tb else "fused_step"),
                    "potential": "-0.4/r + 0.2 r + 0.05 z^2", "N": N, "L": L, "dt": lat.dt,
                    "reductions": "FP64 norm, <H>, r^2 of the input + norm of the output, every step",
                    "renormalise_every": 1, "hip_graph": graph, "tuning": tun,
