@@ -476,6 +476,8 @@ struct StepBody {
   // V of the lane's sites of plane x (needed for x < xe): loaded from the
   // table, or (FV) evaluated from the coordinates.  r^2 = x^2 + (y^2 + z^2)
   // and the other terms are mirror-symmetric bit for bit, as in the table.
+  // VAUX: cache policy of the V table loads.
+  template <int VAUX = FDTD_AUX_V>
   static __device__ __forceinline__ void fetch_v(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                  C (&v)[RY][VZ]) {
     if constexpr (FV) {
@@ -494,7 +496,7 @@ struct StepBody {
     } else {
       const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
 #pragma unroll
-      for (int r = 0; r < RY; ++r) bload<TV, VZ, C, FDTD_AUX_V>(rv, ln.voff[r], v[r]);
+      for (int r = 0; r < RY; ++r) bload<TV, VZ, C, VAUX>(rv, ln.voff[r], v[r]);
     }
   }
 
@@ -855,6 +857,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// V of a tile's sites is read again as the halo frame of its neighbours, so
+// the two-step kernel keeps V loads in the caches.
+#ifndef FDTD_TB_AUX_V
+#define FDTD_TB_AUX_V 0
+#endif
+constexpr int kTbVAux = FDTD_TB_AUX_V;
+
 template <int DT, int VZ, int D, bool FV>
 struct Step2 {
   static constexpr int BT = 256;
@@ -893,11 +902,11 @@ struct Step2 {
                                                int X, int xb, int xe, unsigned N, C* tile,
                                                Rings& g, double (&acc1)[5], double (&acc2)[5]) {
     B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
-    B::fetch_v(kb, lb, X + D, g.vs[(SL + D) % 6]);
+    B::template fetch_v<kTbVAux>(kb, lb, X + D, g.vs[(SL + D) % 6]);
     B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
     if (halo_wave) {
       H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % 6]);
-      H::fetch_v(kh, lh, X + D, g.vh[(SL + D) % 6]);
+      H::template fetch_v<kTbVAux>(kh, lh, X + D, g.vh[(SL + D) % 6]);
       H::fetch(kh, lh, X + D, g.nh[(SL + D) % 6]);
     }
     // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
@@ -1086,7 +1095,7 @@ __global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
     for (int i = 0; i < D + 2; ++i) B::fetch_own(kb, lb, base - 1 + i, g.qs[i]);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      B::fetch_v(kb, lb, base + i, g.vs[i]);
+      B::template fetch_v<kTbVAux>(kb, lb, base + i, g.vs[i]);
       B::fetch(kb, lb, base + i, g.nb[i]);
     }
     if (halo_wave) {
@@ -1094,7 +1103,7 @@ __global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
       for (int i = 0; i < D + 2; ++i) H::fetch_own(kh, lh, base - 1 + i, g.qh[i]);
 #pragma unroll
       for (int i = 0; i < D; ++i) {
-        H::fetch_v(kh, lh, base + i, g.vh[i]);
+        H::template fetch_v<kTbVAux>(kh, lh, base + i, g.vh[i]);
         H::fetch(kh, lh, base + i, g.nh[i]);
       }
     }

@@ -323,11 +323,6 @@ long long chunk_sites(const fdtd_ctx* h, const fdtd_tuning& t) {
 int x_parts(int N, int xc) { return (N + std::max(1, std::min(xc, N)) - 1) / std::max(1, std::min(xc, N)); }
 int x_bound(int N, int nx, int b) { return (int)(((long long)b * N) / nx); }
 
-// Longest x-stream (fewest re-read halo planes, least per-item start-up)
-// that still gives each of the 256 CUs a work item.  Measured: at 512^3 one
-// long-streaming work-group per CU beats more, shorter ones; on the batch of
-// 64 lattices of side 48..160, whole-N items handed out longest first beat
-// every shorter split (item start-up outweighs the better balance).
 // Work items per plane of a lattice of side N: chunks of the flattened plane,
 // or (two steps per pass) tiles of the (y, z) plane.
 long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
@@ -339,6 +334,11 @@ long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
   return ((long long)N * N + F - 1) / F;
 }
 
+// Longest x-stream (fewest re-read halo planes, least per-item start-up)
+// that still gives each of the 256 CUs a work item.  Measured: at 512^3 one
+// long-streaming work-group per CU beats more, shorter ones; on the batch of
+// 64 lattices of side 48..160, whole-N items handed out longest first beat
+// every shorter split (item start-up outweighs the better balance).
 int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
   for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;
