@@ -167,12 +167,12 @@ typedef struct {
  *         in FP64, rounded once) by a few FP32 ulps.  0: always read the table;
  *  tblock  0 (default): one pass over HBM per step; 2: temporal blocking, two
  *         steps per pass (psi and V read once, psi written once per two steps).
- *         Work items are then tiles of the (y, z) plane (F32: 16 x 64 sites,
- *         F64: 16 x 32) streaming x: a work item first advances its tile plus
- *         a one-site frame around it (and one plane on each side in x) by one
- *         step, in registers and LDS, then its own tile by the second.  F32 /
- *         F64 lattices of any side, ry = 1, vz = the vector width, variant 0,
- *         persist 0; not inside fdtd_energy_grad.  The rescale can only
+ *         Work items are then tiles of the (y, z) plane (F32 and BF16: 16 x
+ *         64 sites, F64: 16 x 32) streaming x: a work item first advances its
+ *         tile plus a one-site frame around it (and one plane on each side in
+ *         x) by one step, in registers and LDS, then its own tile by the
+ *         second.  Any lattice side (a multiple of vz), ry = 1, vz = the
+ *         vector width, variant 0, persist 0; not inside fdtd_energy_grad.  The rescale can only
  *         follow a pass: one due after a pass's first step (renorm_every) is
  *         applied after its second.  With the rescale off the states are the
  *         same bits as one launch per step (shared per-site arithmetic); the

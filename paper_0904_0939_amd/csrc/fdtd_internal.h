@@ -102,13 +102,13 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // bt = 256; every member's vkind must be >= 0) instead of reading V.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        bool fv, const StepArgs& a, hipStream_t s);
-// Two steps per pass (temporal blocking, update only; F32 / F64): work items
+// Two steps per pass (temporal blocking, update only): work items
 // are tiles of kTbRows(dtype) x kTbCols(dtype) sites of the (y, z) plane,
-// whose f0 is the tile origin y0 N + z0; one vector of the dtype's width per
-// lane (256 lanes); depth 1 (F64) or 1..2 (F32); partials for 2 *
-// slot_stride slots.
+// whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype) sites
+// per lane (256 lanes); depth 1..3; partials for 2 * slot_stride slots.
+constexpr int kTbVec(int dtype) { return dtype == kF64 ? 2 : 4; }  // sites per lane
 constexpr int kTbCols(int dtype) { return dtype == kF64 ? 32 : 64; }
-constexpr int kTbRows(int dtype) { return 256 * (dtype == kF64 ? 2 : 4) / kTbCols(dtype); }
+constexpr int kTbRows(int dtype) { return 256 * kTbVec(dtype) / kTbCols(dtype); }
 hipError_t launch_step2(int dtype, int depth, bool fv, int grid, const StepArgs& a,
                         hipStream_t s);
 

@@ -838,7 +838,8 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepAr
 // k_step2 advances every member two steps per pass over HBM (psi and V read
 // once, psi'' written once).  A work item owns a tile of kTbRows(DT) x
 // kTbCols(DT) sites of the (y, z) plane and streams x; each lane holds one
-// vector of VZ consecutive z sites (a tile row is 256 bytes).
+// vector of VZ consecutive z sites (a tile row is 256 bytes of F32 / F64; BF16
+// lattices use the F32 tile, 4 sites per lane).
 // Step t runs on the tile's own vectors and on a frame of single halo sites
 // (the rows y0 - 1 and y0 + rows, the columns z0 - 1 and z0 + cols), with the
 // loads and arithmetic of the one-step kernel; its results stay in registers
@@ -2010,7 +2011,7 @@ namespace {
 
 template <int DT, int D, bool FV>
 hipError_t step2_one(int grid, const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_step2<DT, Types<DT>::kVec, D, FV>), dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -2033,6 +2034,8 @@ hipError_t launch_step2(int dtype, int depth, bool fv, int grid, const StepArgs&
     case kF64: return fv ? hipErrorInvalidValue : step2_depth<kF64, false>(depth, grid, a, s);
     case kF32: return fv ? step2_depth<kF32, true>(depth, grid, a, s)
                          : step2_depth<kF32, false>(depth, grid, a, s);
+    case kBF16: return fv ? step2_depth<kBF16, true>(depth, grid, a, s)
+                          : step2_depth<kBF16, false>(depth, grid, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -746,9 +746,10 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
   if (t.vfuse != 0 && t.vfuse != 1) return fail(FDTD_EINVAL, "tuning: vfuse must be 0 or 1");
   if (t.tblock != 0 && t.tblock != 2) return fail(FDTD_EINVAL, "tuning: tblock must be 0 or 2");
   if (t.tblock == 2) {
-    if (h->dtype == kBF16) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs an F32 or F64 lattice");
     if (t.variant != 0 || t.persist != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0 and persist 0");
     if (t.ry != 1 || t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs ry = 1 and vz = the dtype's vector width");
+    for (auto& m : h->mem)
+      if (m.N % kTbVec(h->dtype) != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs every N to be a multiple of its lane vector");
   }
   if (t.variant == 2) {
     if (t.ry != 1) return fail(FDTD_EINVAL, "tuning: variant 2 needs ry = 1");
