@@ -523,11 +523,10 @@ struct StepBody {
   }
 
   // The update of plane x.  TOREG: instead of storing the new values to
-  // HBM, return them (as stored: rounded to the storage type) in outv, and
-  // reduce only the first NRED vectors (the temporally blocked step keeps a
-  // halo vector whose sites another work item owns).
-  // The lane may carry more vectors than RY (RYL >= RY): the first RY are
-  // updated.
+  // HBM, return them (as stored: rounded to the storage type) in outv.  Only
+  // the first NRED vectors enter the reductions (the two-step kernel's halo
+  // sites, NRED = 0, belong to another work item).  The lane may carry more
+  // vectors than RY (RYL >= RY): the first RY are updated.
   template <bool SHZ, bool TOREG, int NRED, int NO, int RYL>
   static __device__ __forceinline__ void update_core(const Ctx& k, const Lane<RYL, VZ, C>& ln,
                                                      int x, const C (&pm)[RY][VZ],
