@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 METRIC = "site-updates/s & HBM roofline %; time-to-E(1e-6 rel) plain vs FP32/batched"
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_SITE = {"f64": 24, "f32": 12, "bf16": 8}  # read psi + V, write psi'
+# FP32 adjoint step: read lambda, V, psi_t, psi_t+1 and G (FP64), write lambda and G
+ADJ_BYTES_PER_SITE = 4 * 4 + 8 + 4 + 8
 KERNEL_SRC = os.path.join(ROOT, "paper_0904_0939_amd", "csrc", "fdtd_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 
@@ -256,6 +258,49 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
     }
 
 
+def gradient_256(steps=4000, k=100):
+    """dE/d(A_k, s_k) of the 8-well potential at 256^3 (L = 12, FP32): the
+    adjoint driver's forward (checkpoints every k steps), the segment
+    recompute and the adjoint steps, timed as one call after an untimed
+    warm-up call; the forward alone is timed too, as the same number of
+    plain steps, so the recompute + adjoint share can be stated."""
+    import torch
+
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    lat = W.gradient_wells(256)
+    p = list(lat.pot_params)
+    wrt = W.gradient_param_indices()
+    s = Solver(256, lat.L, dtype="f32")
+    s.set_potential(F.POT_WELLS, p)
+    s.set_initial(lat.seed)
+    s.energy_grad(2 * k, k, theta=p, wrt=wrt)  # warm-up (allocations, first launches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E, g, _ = s.energy_grad(steps, k, theta=p, wrt=wrt)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    s.evolve(64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.evolve(steps, check_every=0, use_graph=True)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    s.close()
+    sites = 256 ** 3
+    adj = max(total - 2 * fwd, 0.0) / steps  # total minus forward and recompute
+    return {"workload": "wells8_256^3_f32_gradient", "steps": steps, "checkpoint_every": k,
+            "params": len(wrt), "seconds": total, "forward_ms_per_step": fwd / steps * 1e3,
+            "adjoint_ms_per_step_est": adj * 1e3,
+            "adjoint_bytes_per_site": ADJ_BYTES_PER_SITE,
+            "adjoint_GBs_est": ADJ_BYTES_PER_SITE * sites / adj / 1e9 if adj > 0 else None,
+            "energy": E, "grad_norm": float(sum(x * x for x in g)) ** 0.5,
+            "note": "adjoint time per step = (call - 2 x forward) / steps: the call runs the "
+                    "forward once and recomputes it segment by segment"}
+
+
 def batch64(loop=4000, autotune=True):
     """64 random oscillator-plus-wells potentials on lattices of side 48..160,
     FP32, the autotuned shape; with a persistent shape the `loop` steps of
@@ -315,7 +360,7 @@ def main():
                     help="vz,ry,xchunk,grid,xcd_remap,depth,variant,persist[,vfuse,tblock]")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-E and batch measurements")
-    ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64"])
+    ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64", "gradient_256"])
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV"),
                     help="turn rocprofv3 counter runs of this bench into profiles/step_traffic.json")
     args = ap.parse_args()
@@ -342,6 +387,9 @@ def main():
         return
     if args.only == "batch64":
         print(json.dumps(batch64()), flush=True)
+        return
+    if args.only == "gradient_256":
+        print(json.dumps(gradient_256()), flush=True)
         return
     lat = W.cornell(args.n)
     N, L = lat.N, lat.L
@@ -458,6 +506,8 @@ def main():
         note("time to E done")
         out["batch64"] = batch64()
         note("batch of 64 done")
+        out["gradient_256"] = gradient_256()
+        note("gradient done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, L, lat.pot_params, args.cpu_steps)
         note("cpu baseline done")

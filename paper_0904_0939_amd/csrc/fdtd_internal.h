@@ -157,7 +157,7 @@ struct AdjArgs {
   const void* psi_t1;   // psi_{t+1}
   double* G;            // dE/dV accumulator, FP64
   int N;
-  int pad0;
+  int nx;               // x-ranges per chunk column (set by launch_adjoint_step)
   double c, dt;
   double s_t;           // scale applied in forward step t
 };

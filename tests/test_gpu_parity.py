@@ -395,6 +395,27 @@ def test_gradient_fp32_matches_oracle_adjoint():
         assert gj == pytest.approx(float(np.sum(Go * orc.wells_dv(p, N, L, j))), rel=1e-4)
 
 
+@pytest.mark.parametrize("dtype,N", [("f64", 9), ("f32", 18), ("f32", 40), ("f64", 24)])
+def test_gradient_field_matches_oracle_across_launch_shapes(dtype, N):
+    """dE/dV site by site: scalar lanes (N not a multiple of the vector
+    width), several chunks of the flattened plane with a ragged last one, and
+    one x-range per plane (N = 40: 2 chunks x 40 ranges)."""
+    say(f"case: gradient field {dtype} {N}^3")
+    L, T, k = 8.0, 40, 9
+    p = [1.0, 1.2, 0.9, 1.5, 0.3, 0.0, -0.2, 0.8, 0.7, -1.0, 0.5, 0.2, 1.1]
+    s = Solver(N, L, dtype=dtype)
+    s.set_potential(F.POT_WELLS, p)
+    s.set_initial(15)
+    E, g, G = s.energy_grad(T, k, theta=p, wrt=[3, 7], want_field=True)
+    V = orc.potential(orc.POT_WELLS, p, N, L)
+    Eo, Go = orc.energy_grad_v(orc.initial(N, 15), V, L, (L / N) ** 2 / 8, T)
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    assert E == pytest.approx(Eo, rel=1e-12 if dtype == "f64" else 1e-5)
+    np.testing.assert_allclose(G.cpu().numpy(), Go, rtol=0, atol=tol * np.abs(Go).max())
+    for j, gj in zip([3, 7], g):
+        assert gj == pytest.approx(float(np.sum(Go * orc.wells_dv(p, N, L, j))), rel=tol)
+
+
 # ----------------------------------------------------------- error paths ----
 def test_nonfinite_initial_state_is_reported():
     s = Solver(16, 8.0, dtype="f32")
