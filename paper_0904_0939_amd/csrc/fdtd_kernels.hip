@@ -194,6 +194,7 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // used once: V, and the written state); kKeep leaves the default policy
 // (psi, whose lines are re-read as neighbours by adjacent lanes).
 constexpr int kKeep = 0;
+constexpr int kNT = 2;
 // Build-time choice of the policies of the four streams of the step kernel.
 #ifndef FDTD_AUX_PSI
 #define FDTD_AUX_PSI 0  // own-site psi loads (first touch of each plane)
@@ -247,7 +248,16 @@ __device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, C 
 template <typename S, int VZ, int AUX = kKeep>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, const Pack<S, VZ>& t) {
   constexpr int kBytes = (int)sizeof(S) * VZ;
-  if constexpr (kBytes == 16) {
+  if constexpr (kBytes == 32) {
+    Pack<S, VZ / 2> lo, hi;
+#pragma unroll
+    for (int j = 0; j < VZ / 2; ++j) {
+      lo.v[j] = t.v[j];
+      hi.v[j] = t.v[j + VZ / 2];
+    }
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, lo), r, (int)off, 0, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, hi), r, (int)off + 16, 0, AUX);
+  } else if constexpr (kBytes == 16) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, (int)off, 0, AUX);
   } else if constexpr (kBytes == 8) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, t), r, (int)off, 0, AUX);
@@ -1654,13 +1664,13 @@ __global__ void k_set_state(MemberState* st, int member, double scale, long long
 // loads the adjacent rows and lanes also make (served by L1 / L2).  Out-of-
 // range loads read 0 (zero ghosts).  Per site: lambda, V, psi_t, psi_{t+1}
 // and G read, lambda_t and G written.
-template <typename S, int VZ>
-__global__ __launch_bounds__(kBlock) void k_adjoint_step(AdjArgs a) {
+template <typename S, int VZ, int BT>
+__global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
   using C = typename std::conditional<sizeof(S) == 8, double, float>::type;
   constexpr unsigned kES = sizeof(S);
   const int N = a.N;
   const unsigned P = (unsigned)N * (unsigned)N, pb = P * kES;
-  const unsigned F = (unsigned)kBlock * VZ;
+  const unsigned F = (unsigned)BT * VZ;
   const int nchunk = (int)((P + F - 1) / F), nx = a.nx;
   const C c = (C)a.c, dt = (C)a.dt, eps = (C)(0.5 * a.dt), st = (C)a.s_t;
   const double hdt = -0.5 * a.dt, std_ = (double)st;
@@ -1708,12 +1718,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(AdjArgs a) {
       bload<S, 1, C>(rv, offzm, vzm);
       bload<S, 1, C>(rl, offzp, lzp);
       bload<S, 1, C>(rv, offzp, vzp);
-      bload<S, VZ, C>(plane_rsrc(a.psi_t, x, N, pb), off, pt);
-      bload<S, VZ, C>(plane_rsrc(a.psi_t1, x, N, pb), off, pt1);
-      double* g = a.G + (long long)x * P + f;
+      // read once and written once: past the caches, which keep lambda and V
+      // for the neighbour re-reads
+      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t, x, N, pb), off, pt);
+      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t1, x, N, pb), off, pt1);
+      const __amdgpu_buffer_rsrc_t rg = plane_rsrc(a.G, x, N, P * 8u);
       double gv[VZ];
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) gv[j] = ok ? g[j] : 0.0;
+      bload<double, VZ, double, kNT>(rg, fe * 8u, gv);
       C wp[VZ];
       Pack<S, VZ> o;
 #pragma unroll
@@ -1729,11 +1740,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(AdjArgs a) {
         const C B = rcp_c(C(1) + eps * vc[j]);
         gv[j] += (double)lc[j] * (hdt * (double)B) * (std_ * (double)pt[j] + (double)pt1[j]);
       }
-      bstore<S, VZ>(plane_rsrc(a.lam_out, x, N, pb), off, o);
-      if (ok) {
+      bstore<S, VZ, kNT>(plane_rsrc(a.lam_out, x, N, pb), off, o);
+      Pack<double, VZ> go;
 #pragma unroll
-        for (int j = 0; j < VZ; ++j) g[j] = gv[j];
-      }
+      for (int j = 0; j < VZ; ++j) go.v[j] = gv[j];
+      bstore<double, VZ, kNT>(rg, fe * 8u, go);
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         wm[j] = wc[j];
@@ -2262,22 +2273,22 @@ hipError_t launch_set_state(MemberState* st, int member, double scale, long long
 hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s) {
   if (a.N < 1 || (dtype != kF64 && dtype != kF32)) return hipErrorInvalidValue;
   // VZ sites per lane when N allows (a lane's vector stays within a z-row),
-  // else one; x split into ranges so that there are about 2048 work items
+  // else one
   const int vz = dtype == kF64 ? 2 : 4;
   const bool vec = a.N % vz == 0;
   const long long P = (long long)a.N * a.N, F = (long long)kBlock * (vec ? vz : 1);
   const long long nchunk = (P + F - 1) / F;
   AdjArgs b = a;
-  // 2048 work items (measured at 256^3 FP32: 256 -> 4096 items change the step by
-  // 3%, shorter x-ranges re-reading more planes but filling the CUs better)
+  // x split into ranges for about 2048 work items (measured at 256^3 FP32:
+  // 256 to 4096 items and 256 to 1024 lanes per work-group within 3%)
   b.nx = (int)std::min<long long>(a.N, std::max<long long>(1, (2048 + nchunk - 1) / nchunk));
   const int g = (int)std::min<long long>(nchunk * b.nx, 1 << 20);
   if (dtype == kF64) {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, 2>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<double, 1>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, 2, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<double, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
   } else {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, 4>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<float, 1>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, 4, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<float, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
   }
   return hipGetLastError();
 }
