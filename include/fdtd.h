@@ -144,10 +144,14 @@ typedef struct {
  *  depth  planes of HBM prefetch ahead of the plane being updated (1..3;
  *         1 for vz = 1);
  *  variant  0: 256-lane work-groups, y / z neighbours re-read through the
- *         caches; 2: the same with 512-lane work-groups (ry = 1); 1: large
- *         work-groups (1024 lanes, 512 for BF16) sharing an LDS copy of each
- *         plane (needs vz = the vector width, 2N / vz <= the work-group size
- *         and a tile of at most 64 KiB; ry is ignored);
+ *         caches, the new state streamed past the caches; 2: the same with
+ *         512-lane work-groups (ry = 1); 3: variant 0 storing the new state
+ *         written through at system scope, so it stays in the last-level
+ *         cache for the next step (vz = the vector width, ry <= 2; the
+ *         default for a single lattice whose two state buffers and V fit in
+ *         512 MiB); 1: large work-groups (1024 lanes, 512 for BF16) sharing
+ *         an LDS copy of each plane (needs vz = the vector width, 2N / vz <=
+ *         the work-group size and a tile of at most 64 KiB; ry is ignored);
  *  persist  0: one launch per step; n > 0: one persistent launch advances
  *         every member up to n steps (variant 0 only).  Its work-groups (grid,
  *         0: one per CU) take (step, work item) tickets in order; a work item

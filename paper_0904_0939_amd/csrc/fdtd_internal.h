@@ -100,8 +100,11 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 // bt: threads per work-group, 256, or 512 for ry = 1.
 // fv: evaluate the members' analytic potentials in the kernel (F32 / BF16,
 // bt = 256; every member's vkind must be >= 0) instead of reading V.
+// wt: store the updated state written through (it stays in the last-level
+// cache for the next step) instead of streamed past the caches; update with
+// 256-lane groups, vz = the dtype's vector width and ry <= 2 only.
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
-                       bool fv, const StepArgs& a, hipStream_t s);
+                       bool fv, bool wt, const StepArgs& a, hipStream_t s);
 // Two steps per pass (temporal blocking, update only): work items
 // are tiles of kTbRows(dtype) x kTbCols(dtype) sites of the (y, z) plane,
 // whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype) sites

@@ -195,6 +195,11 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 // (psi, whose lines are re-read as neighbours by adjacent lanes).
 constexpr int kKeep = 0;
 constexpr int kNT = 2;
+// Stores written through at system scope (sc0 sc1): the written state stays in
+// the last-level cache (MALL) for the next step's reads.  Measured per FP32
+// step: 256^3 51.7 -> 42.5 us, 320^3 101.9 -> 88.5 us, but 384^3 158.6 -> 162.0
+// and 512^3 282.1 -> 283.3 us, where the lattice does not fit.
+constexpr int kWriteThrough = 1 | 16;
 // Build-time choice of the policies of the four streams of the step kernel.
 #ifndef FDTD_AUX_PSI
 #define FDTD_AUX_PSI 0  // own-site psi loads (first touch of each plane)
@@ -397,7 +402,7 @@ enum VKind { kVConst = 0, kVHO = 1, kVCoulomb = 2, kVCoulombReg = 3, kVCornell =
 
 // FV: the potential is evaluated in the kernel from the site coordinates
 // (member kinds kVConst..kVCornell) instead of read from the V table.
-template <int DT, int VZ, int RY, bool UPD, bool FV = false>
+template <int DT, int VZ, int RY, bool UPD, bool FV = false, int OUT = FDTD_AUX_OUT>
 struct StepBody {
   using S = typename Types<DT>::S;
   using TV = typename Types<DT>::V;
@@ -619,7 +624,7 @@ struct StepBody {
           if constexpr (TOREG) outv[r][j] = od;
         }
       }
-      if constexpr (UPD && !TOREG) bstore<S, VZ, FDTD_AUX_OUT>(ro, ln.off[r], o);
+      if constexpr (UPD && !TOREG) bstore<S, VZ, OUT>(ro, ln.off[r], o);
     }
     acc[0] += (double)s0;
     acc[1] += (double)kin;
@@ -656,10 +661,10 @@ struct StepBody {
 // work-group finalise the step.  Member state is read with atomic loads: in
 // the persistent kernel another work-group may have changed it since this
 // one last looked, and the loads must not come from a stale scalar cache.
-template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false>
+template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false, int OUT = FDTD_AUX_OUT>
 __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, int src,
                                          double (&s_red)[BT / 64][5], int& s_last) {
-  using Body = StepBody<DT, VZ, RY, UPD, FV>;
+  using Body = StepBody<DT, VZ, RY, UPD, FV, OUT>;
   using S = typename Body::S;
   using TV = typename Body::TV;
   using C = typename Body::C;
@@ -790,12 +795,15 @@ __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, in
   }
 }
 
-template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV>
+// WT: the updated state is stored written through (kWriteThrough) instead of
+// streamed past the caches.
+template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV, bool WT = false>
 __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step(StepArgs A) {
   __shared__ double s_red[BT / 64][5];
   __shared__ int s_last;
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
-    run_item<DT, VZ, RY, UPD, D, BT, FV>(A, A.items[A.item_offset + li], A.src, s_red, s_last);
+    run_item<DT, VZ, RY, UPD, D, BT, FV, WT ? kWriteThrough : FDTD_AUX_OUT>(
+        A, A.items[A.item_offset + li], A.src, s_red, s_last);
 }
 
 // Persistent fused step: A.steps steps of every member in one launch.  Each
@@ -1919,8 +1927,23 @@ int grid_for(long long n) {
 // instantiated; the scalar-lane fallback (VZ = 1) and the reduction-only
 // pass use prefetch distance 1 only.
 template <int DT, int VZ, int RY, bool UPD, int D>
-hipError_t step_one(int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
+hipError_t step_one(int grid, int bt, bool fv, bool wt, const StepArgs& a, hipStream_t s) {
   if constexpr (VZ * RY * (int)sizeof(typename Types<DT>::C) <= 32 && (D == 1 || (UPD && VZ > 1))) {
+    // written-through stores: 256-lane groups, full vectors, one or two per lane
+    if constexpr (UPD && VZ == Types<DT>::kVec && RY <= 2) {
+      if (wt && bt == 256) {
+        if constexpr (DT != kF64) {
+          if (fv) {
+            hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256, true, true>), dim3(grid), dim3(256), 0, s, a);
+            return hipGetLastError();
+          }
+        }
+        if (fv) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_step<DT, VZ, RY, UPD, D, 256, false, true>), dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+      }
+    }
+    if (wt && UPD) return hipErrorInvalidValue;
     if (fv) {
       // in-kernel potential: FP32 arithmetic lattices
       if constexpr (DT != kF64) {
@@ -1957,11 +1980,11 @@ hipError_t step_one(int grid, int bt, bool fv, const StepArgs& a, hipStream_t s)
 }
 
 template <int DT, int VZ, bool UPD, int D>
-hipError_t step_ry(int ry, int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
+hipError_t step_ry(int ry, int grid, int bt, bool fv, bool wt, const StepArgs& a, hipStream_t s) {
   switch (ry) {
-    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, bt, fv, a, s);
-    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, bt, fv, a, s);
-    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, bt, fv, a, s);
+    case 1: return step_one<DT, VZ, 1, UPD, D>(grid, bt, fv, wt, a, s);
+    case 2: return step_one<DT, VZ, 2, UPD, D>(grid, bt, fv, wt, a, s);
+    case 4: return step_one<DT, VZ, 4, UPD, D>(grid, bt, fv, wt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2021,28 +2044,31 @@ __global__ void k_persist_reset(Control* ctrl, MemberState* states, int count) {
 }
 
 template <int DT, int VZ, bool UPD>
-hipError_t step_d(int depth, int ry, int grid, int bt, bool fv, const StepArgs& a, hipStream_t s) {
+hipError_t step_d(int depth, int ry, int grid, int bt, bool fv, bool wt, const StepArgs& a,
+                  hipStream_t s) {
   switch (depth) {
-    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, bt, fv, a, s);
-    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, bt, fv, a, s);
-    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, bt, fv, a, s);
+    case 1: return step_ry<DT, VZ, UPD, 1>(ry, grid, bt, fv, wt, a, s);
+    case 2: return step_ry<DT, VZ, UPD, 2>(ry, grid, bt, fv, wt, a, s);
+    case 3: return step_ry<DT, VZ, UPD, 3>(ry, grid, bt, fv, wt, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int DT, bool UPD>
-hipError_t step_vz(int vz, int depth, int ry, int grid, int bt, bool fv, const StepArgs& a,
-                   hipStream_t s) {
-  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, bt, fv, a, s);
-  if (vz == Types<DT>::kVec) return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, bt, fv, a, s);
+hipError_t step_vz(int vz, int depth, int ry, int grid, int bt, bool fv, bool wt,
+                   const StepArgs& a, hipStream_t s) {
+  if (vz == 1) return step_d<DT, 1, UPD>(depth, ry, grid, bt, fv, wt, a, s);
+  if (vz == Types<DT>::kVec)
+    return step_d<DT, Types<DT>::kVec, UPD>(depth, ry, grid, bt, fv, wt, a, s);
   return hipErrorInvalidValue;
 }
 
 template <int DT>
-hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, int bt, bool fv,
+hipError_t step_dt(int vz, int depth, int ry, bool upd, int grid, int bt, bool fv, bool wt,
                    const StepArgs& a, hipStream_t s) {
-  return upd ? step_vz<DT, true>(vz, depth, ry, grid, bt, fv, a, s)
-             : step_vz<DT, false>(vz, 1, ry, grid, bt, fv, a, s);
+  // the reduction-only pass stores nothing
+  return upd ? step_vz<DT, true>(vz, depth, ry, grid, bt, fv, wt, a, s)
+             : step_vz<DT, false>(vz, 1, ry, grid, bt, fv, false, a, s);
 }
 
 template <int DT, bool UPD, int D>
@@ -2133,13 +2159,13 @@ hipError_t launch_persist_reset(Control* ctrl, MemberState* states, int count, h
 }
 
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
-                       bool fv, const StepArgs& a, hipStream_t s) {
+                       bool fv, bool wt, const StepArgs& a, hipStream_t s) {
   if (grid < 1) return hipErrorInvalidValue;
   if (vz == 1) depth = 1;
   switch (dtype) {
-    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, bt, fv, a, s);
-    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, bt, fv, a, s);
-    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, fv, a, s);
+    case kF64: return step_dt<kF64>(vz, depth, ry, update, grid, bt, fv, wt, a, s);
+    case kF32: return step_dt<kF32>(vz, depth, ry, update, grid, bt, fv, wt, a, s);
+    case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, fv, wt, a, s);
     default: return hipErrorInvalidValue;
   }
 }

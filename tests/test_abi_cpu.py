@@ -129,6 +129,33 @@ def test_tuning_validation_is_host_side():
         F.fdtd_destroy(h)
 
 
+def test_write_through_variant_rules_and_default():
+    """variant 3 (variant 0 with written-through stores): full vectors, ry <=
+    2, no persistence; the default for a single lattice whose two state
+    buffers and V fit in 512 MiB, else variant 0."""
+    small = F.fdtd_create(cfg(N=64, dtype=F.F32))
+    big = F.fdtd_create(cfg(N=512, L=40.0, dtype=F.F32))   # 1.5 GiB of fields
+    odd = F.fdtd_create(cfg(N=18, dtype=F.F32))            # scalar lanes
+    f64 = F.fdtd_create(cfg(N=256, L=30.0, dtype=F.F64))   # 384 MiB
+    arr = (F.fdtd_config * 2)(cfg(N=16), cfg(N=24))
+    hb = C.c_void_p()
+    assert status_of("fdtd_create_batch", arr, 2, C.byref(hb)) == F.OK
+    try:
+        assert F.fdtd_get_tuning(small).variant == 3
+        assert F.fdtd_get_tuning(f64).variant == 3
+        assert F.fdtd_get_tuning(big).variant == 0
+        assert F.fdtd_get_tuning(odd).variant == 0
+        assert F.fdtd_get_tuning(hb.value).variant == 0
+        for bad in [F.fdtd_tuning(1, 1, 0, 0, 1, 1, 3), F.fdtd_tuning(4, 4, 0, 0, 1, 1, 3),
+                    F.fdtd_tuning(4, 2, 0, 0, 1, 1, 3, 8), F.fdtd_tuning(4, 2, 0, 0, 1, 1, 4)]:
+            assert status_of("fdtd_set_tuning", small, C.byref(bad)) == F.EINVAL
+        F.fdtd_set_tuning(big, F.fdtd_tuning(4, 2, 0, 0, 1, 3, 3))
+        assert F.fdtd_get_tuning(big).variant == 3
+    finally:
+        for h in (small, big, odd, f64, hb.value):
+            F.fdtd_destroy(h)
+
+
 def test_two_step_passes_validation():
     """tblock = 2: full vectors, ry = 1, variant 0 without persistence; any
     side (tiles of the (y, z) plane), every dtype."""

@@ -146,7 +146,8 @@ def test_fp32_coulomb_even_and_odd_starts():
                                     (1, 1, 13, 0, 0, 1), (1, 4, 5, 37, 1, 1), (4, 2, 7, 64, 1, 3),
                                     (4, 1, 0, 0, 1, 2), (4, 2, 11, 0, 0, 1),
                                     (4, 1, 0, 0, 1, 1, 1), (4, 1, 7, 0, 1, 2, 1), (4, 1, 13, 3, 1, 3, 1),
-                                    (4, 1, 9, 0, 1, 3, 2), (1, 1, 10, 0, 1, 1, 2)])
+                                    (4, 1, 9, 0, 1, 3, 2), (1, 1, 10, 0, 1, 1, 2),
+                                    (4, 2, 0, 0, 1, 1, 3), (4, 1, 9, 0, 0, 2, 3)])
 def test_fp32_state_is_independent_of_launch_shape(tuning):
     """Without renormalisation the update of a site does not depend on the
     tiling, so every launch shape yields the same bits."""
@@ -161,7 +162,7 @@ def test_fp32_state_is_independent_of_launch_shape(tuning):
 
 @pytest.mark.parametrize("N,tunings", [
     (40, [(8, 1, 0, 0, 1, 2), (8, 1, 5, 0, 0, 1), (8, 1, 3, 0, 1, 3), (1, 4, 9, 0, 1, 1),
-          (1, 1, 0, 0, 1, 1), (8, 1, 0, 0, 1, 1, 1), (1, 1, 7, 0, 1, 1, 2)]),
+          (1, 1, 0, 0, 1, 1), (8, 1, 0, 0, 1, 1, 1), (1, 1, 7, 0, 1, 1, 2), (8, 1, 0, 0, 1, 2, 3)]),
     (42, [(1, 1, 0, 0, 1, 1), (1, 4, 0, 0, 1, 1), (1, 2, 3, 0, 0, 1)]),
     (45, [(1, 1, 0, 0, 1, 1), (1, 2, 4, 0, 1, 1), (1, 4, 0, 11, 0, 1)])])
 def test_bf16_state_is_independent_of_launch_shape_and_keeps_parity(N, tunings):
@@ -190,10 +191,11 @@ def test_bf16_state_is_independent_of_launch_shape_and_keeps_parity(N, tunings):
         assert np.array_equal(st, states[0]), t
 
 
-@pytest.mark.parametrize("dtype,variant", [("f64", 1), ("f64", 2), ("bf16", 1), ("f32", 1)])
+@pytest.mark.parametrize("dtype,variant", [("f64", 1), ("f64", 2), ("bf16", 1), ("f32", 1), ("f64", 3)])
 def test_large_group_variants_against_oracle(dtype, variant):
-    """The LDS-tile and 512-lane variants of the fused step against the oracle
-    (N = 104: several chunks, ragged tail, halo rows crossing chunks)."""
+    """The LDS-tile, 512-lane and written-through-store variants of the fused
+    step against the oracle (N = 104: several chunks, ragged tail, halo rows
+    crossing chunks)."""
     say(f"case: variant {variant} {dtype}")
     N, L, T = 104, 20.0, 200
     vz = {"f64": 2, "f32": 4, "bf16": 8}[dtype]
