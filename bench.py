@@ -71,7 +71,11 @@ def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
     def is_step(name):
         if key.endswith("_tb2"):
             return "k_step2<" in name
-        return "k_step<" in name and ", true," in name
+        if "k_step<" not in name:
+            return False
+        # k_step<dtype, vz, ry, update, ...>: the update launches only
+        args = name.split("k_step<", 1)[1].split(">", 1)[0].split(",")
+        return len(args) > 3 and args[3].strip() == "true"
 
     def per_launch(path):
         R = rows(path)
