@@ -70,6 +70,7 @@ struct MemberHost {
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   int K = 0, renorm = 0, src = 0;
+  int dst = 0;  // buffer holding the state after the K steps (a two-step pass flips once)
   fdtd_tuning tun{};
 };
 
@@ -584,6 +585,7 @@ fdtd_status graph_steps(fdtd_ctx* h, int K, int renorm_every) {
     HIP_TRY(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     fdtd_status st = launch_steps(h, K, renorm_every, h->capture_stream);
     hipError_t e = hipStreamEndCapture(h->capture_stream, &graph);
+    const int cur1 = h->cur;
     h->cur = cur0;
     if (st != FDTD_OK) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -600,12 +602,13 @@ fdtd_status graph_steps(fdtd_ctx* h, int K, int renorm_every) {
     g.K = K;
     g.renorm = renorm_every;
     g.src = cur0;
+    g.dst = cur1;
     g.tun = h->tun;
     h->graphs.push_back(g);
     ge = &h->graphs.back();
   }
   HIP_TRY(hipGraphLaunch(ge->exec, h->stream));
-  if (K & 1) h->cur ^= 1;
+  h->cur = ge->dst;
   return FDTD_OK;
 }
 
