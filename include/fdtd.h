@@ -176,13 +176,14 @@ typedef struct {
  *         tile plus a one-site frame around it (and one plane on each side in
  *         x) by one step, in registers and LDS, then its own tile by the
  *         second.  Any lattice side (a multiple of vz), ry = 1, vz = the
- *         vector width, variant 0, persist 0; not inside fdtd_energy_grad.  The rescale can only
- *         follow a pass: one due after a pass's first step (renorm_every) is
- *         applied after its second.  With the rescale off the states are the
- *         same bits as one launch per step (shared per-site arithmetic); the
- *         reductions then differ only in FP64 summation order (per tile
- *         instead of per flattened chunk).  An odd remainder of steps runs one
- *         launch per step. */
+ *         vector width, variant 0, persist 0; not inside fdtd_energy_grad.
+ *         The rescale can only follow a pass: one due after a pass's first
+ *         step (renorm_every) is applied after its second.  With the rescale
+ *         off the states are the same bits as one launch per step (shared
+ *         per-site arithmetic; BF16: the same rounding bits); the reductions
+ *         then differ only in their summation order (per tile instead of per
+ *         flattened chunk; BF16 lanes also hold 4 sites instead of 8).  An odd
+ *         remainder of steps runs one launch per step. */
 typedef struct {
   int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse, tblock;
 } fdtd_tuning;
