@@ -316,6 +316,26 @@ __device__ __forceinline__ T ld_agent(const T& x) {
   return __hip_atomic_load(const_cast<T*>(&x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// A work item hands its partial sums to the member's last work-group within
+// one launch.  Only the partials cross work-groups inside a launch (the
+// updated state is read by the next launch), so instead of a release fence,
+// which writes back the whole L2 of this XCD, the partials are stored as
+// agent-scope atomic stores (written through to the coherence point), the
+// wave waits until they have completed (vmcnt(0)), and only then counts the
+// item on the member's counter; the last work-group reads them with
+// agent-scope atomic loads.  Returns the counter's previous value.
+template <int NV>
+__device__ __forceinline__ unsigned publish_partials(double* const (&dst)[NV], const double (&v)[NV][5],
+                                                     unsigned* counter) {
+#pragma unroll
+  for (int i = 0; i < NV; ++i)
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+      __hip_atomic_store(&dst[i][q], v[i][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unconstrained
+  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Last work-group of member m: record the step's sums, set the scale of the
 // next update, advance the step counter, flag non-finite sums, re-arm the
 // completion counter and, last, publish the step as finalised (release).
@@ -661,7 +681,11 @@ struct StepBody {
 // work-group finalise the step.  Member state is read with atomic loads: in
 // the persistent kernel another work-group may have changed it since this
 // one last looked, and the loads must not come from a stale scalar cache.
-template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false, int OUT = FDTD_AUX_OUT>
+// FENCE: the persistent kernel, where the next step's work items (on any
+// XCD) read this item's updated state within the same launch, publishes with
+// a full release fence; one launch per step only needs the partials to cross.
+template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false, int OUT = FDTD_AUX_OUT,
+          bool FENCE = false>
 __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, int src,
                                          double (&s_red)[BT / 64][5], int& s_last) {
   using Body = StepBody<DT, VZ, RY, UPD, FV, OUT>;
@@ -773,20 +797,27 @@ __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, in
     block_sum<5, BT / 64>(acc, s_red);
     if (tid == 0) {
       double* part = A.partials + (long long)item.slot * kRec;
+      unsigned int done;
+      if constexpr (FENCE) {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) part[k] = acc[k];
-      __threadfence();
-      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+        for (int k = 0; k < 5; ++k) part[k] = acc[k];
+        __threadfence();
+        done = atomicAdd(&A.states[m].counter, 1u);
+      } else {
+        double* const dst[1] = {part};
+        const double v[1][5] = {{acc[0], acc[1], acc[2], acc[3], acc[4]}};
+        done = publish_partials<1>(dst, v, &A.states[m].counter);
+      }
       s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();
+      if constexpr (FENCE) __threadfence();
       double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int i = M.item_begin + tid; i < M.item_end; i += BT) {
         const double* part = A.partials + (long long)i * kRec;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) tot[k] += part[k];
+        for (int k = 0; k < 5; ++k) tot[k] += FENCE ? part[k] : ld_agent(part[k]);
       }
       block_sum<5, BT / 64>(tot, s_red);
       if (tid == 0) finalize(A, M, m, tot, UPD);
@@ -847,7 +878,7 @@ __global__ __launch_bounds__(BT, FDTD_STEP_MIN_WAVES) void k_step_persist(StepAr
     const int tk = s_tk;
     if (tk >= total) break;
     const int t = tk / A.n_items;
-    run_item<DT, VZ, RY, true, D, BT, FV>(A, A.items[tk % A.n_items], A.src ^ (t & 1), s_red,
+    run_item<DT, VZ, RY, true, D, BT, FV, FDTD_AUX_OUT, true>(A, A.items[tk % A.n_items], A.src ^ (t & 1), s_red,
                                           s_last);
   }
 }
@@ -1154,26 +1185,22 @@ __global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
     if (tid == 0) {
       double* p1 = A.partials + (long long)item.slot * kRec;
       double* p2 = A.partials + (long long)(A.slot_stride + item.slot) * kRec;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        p1[q] = acc1[q];
-        p2[q] = acc2[q];
-      }
-      __threadfence();
-      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+      double* const dst[2] = {p1, p2};
+      const double v[2][5] = {{acc1[0], acc1[1], acc1[2], acc1[3], acc1[4]},
+                              {acc2[0], acc2[1], acc2[2], acc2[3], acc2[4]}};
+      const unsigned int done = publish_partials<2>(dst, v, &A.states[m].counter);
       s_last = (done + 1u == (unsigned int)(M.tb_end - M.tb_begin));
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();
       double t1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, t2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int i = M.tb_begin + tid; i < M.tb_end; i += BT) {
         const double* p1 = A.partials + (long long)i * kRec;
         const double* p2 = A.partials + (long long)(A.slot_stride + i) * kRec;
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          t1[q] += p1[q];
-          t2[q] += p2[q];
+          t1[q] += ld_agent(p1[q]);
+          t2[q] += ld_agent(p2[q]);
         }
       }
       block_sum<5, BT / 64>(t1, s_red);
@@ -1380,20 +1407,18 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
     block_sum<5, kTB / 64>(acc, s_red);
     if (tid == 0) {
       double* part = A.partials + (long long)item.slot * kRec;
-#pragma unroll
-      for (int kk = 0; kk < 5; ++kk) part[kk] = acc[kk];
-      __threadfence();
-      const unsigned int done = atomicAdd(&A.states[m].counter, 1u);
+      double* const dst[1] = {part};
+      const double v[1][5] = {{acc[0], acc[1], acc[2], acc[3], acc[4]}};
+      const unsigned int done = publish_partials<1>(dst, v, &A.states[m].counter);
       s_last = (done + 1u == (unsigned int)(M.item_end - M.item_begin));
     }
     __syncthreads();
     if (s_last) {
-      __threadfence();
       double tot[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int i = M.item_begin + tid; i < M.item_end; i += kTB) {
         const double* part = A.partials + (long long)i * kRec;
 #pragma unroll
-        for (int kk = 0; kk < 5; ++kk) tot[kk] += part[kk];
+        for (int kk = 0; kk < 5; ++kk) tot[kk] += ld_agent(part[kk]);
       }
       block_sum<5, kTB / 64>(tot, s_red);
       if (tid == 0) finalize(A, M, m, tot, UPD);
