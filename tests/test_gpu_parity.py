@@ -160,6 +160,32 @@ def test_fp32_state_is_independent_of_launch_shape(tuning):
     assert np.array_equal(s.state(), ref.state())
 
 
+def test_reductions_agree_across_work_item_counts():
+    """Each work item hands its partial sums to the member's last work-group
+    inside the launch.  With a rescale every step the state depends on every
+    step's sums, so a partial read before it landed would show at once: the
+    histories of launch shapes with 18 to 1152 work items per step (and a grid
+    smaller than the item count) must agree to FP32 grouping rounding, and
+    the result must match the oracle."""
+    say("case: reductions across work-item counts")
+    N, L, T = 96, 12.0, 300
+    params = W.random_wells(np.random.default_rng(2))
+    runs, final = [], []
+    for tun in [(4, 2, 0, 0, 1, 1), (4, 1, 4, 0, 1, 2), (4, 2, 8, 7, 0, 1), (4, 1, 2, 0, 1, 1, 3)]:
+        s, *_ = gpu_run(N, L, "f32", F.POT_WELLS, params, 8, T, tuning=tun)
+        runs.append(s.history(0, T))
+        final.append(s.observables()[0]["energy"])
+        s.close()
+    for h in runs[1:]:
+        for a, b in zip(h, runs[0]):
+            assert a["step"] == b["step"]
+            assert a["energy"] == pytest.approx(b["energy"], rel=1e-6), a["step"]
+            assert a["norm2"] == pytest.approx(b["norm2"], rel=1e-6), a["step"]
+    assert final[1:] == pytest.approx([final[0]] * 3, rel=1e-6)
+    psi, V, *_ = oracle_run(N, L, orc.POT_WELLS, params, 8, T)
+    assert final[0] == pytest.approx(orc.observables(psi, V, L)["energy"], rel=1e-5)
+
+
 @pytest.mark.parametrize("N,tunings", [
     (40, [(8, 1, 0, 0, 1, 2), (8, 1, 5, 0, 0, 1), (8, 1, 3, 0, 1, 3), (1, 4, 9, 0, 1, 1),
           (1, 1, 0, 0, 1, 1), (8, 1, 0, 0, 1, 1, 1), (1, 1, 7, 0, 1, 1, 2), (8, 1, 0, 0, 1, 2, 3)]),
