@@ -115,22 +115,43 @@ def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
           f"kernel avg {avg_ns / 1e3 if avg_ns else float('nan'):.1f} us |")
 
 
-def cpu_baseline(N, L, params, steps):
-    """The FP64 oracle on the same lattice: setup untimed, `steps` steps timed."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, L, params, steps, steps_1t=8):
+    """The FP64 oracle on the same lattice: setup untimed, `steps` sweeps timed
+    with all the threads OpenMP uses, then `steps_1t` sweeps on one thread."""
     import oracle as orc
 
     a = L / N
     V = orc.potential(orc.POT_CORNELL, params, N, L)
     psi = orc.initial(N, 3)
     orc.step(psi, V, L, a * a / 8)  # first touch / thread start-up
+    cores = orc.num_threads()
     t0 = time.perf_counter()
     for _ in range(steps):
         psi = orc.step(psi, V, L, a * a / 8)
     dt = time.perf_counter() - t0
-    return {"value": N**3 * steps / dt, "unit": "site-updates/s", "cores": orc.num_threads(),
+    orc.set_num_threads(1)
+    t0 = time.perf_counter()
+    for _ in range(steps_1t):
+        psi = orc.step(psi, V, L, a * a / 8)
+    dt1 = time.perf_counter() - t0
+    orc.set_num_threads(cores)
+    return {"value": N**3 * steps / dt, "unit": "site-updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{steps} FP64 oracle update sweeps of the same {N}^3 Cornell lattice "
-                      f"({dt:.1f} s; potential and noise set-up untimed)"}
+                      f"({dt:.1f} s; potential and noise set-up untimed)",
+            "value_1_thread": N**3 * steps_1t / dt1,
+            "sample_1_thread": f"{steps_1t} sweeps on one thread ({dt1:.1f} s)",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def note(msg):

@@ -74,6 +74,8 @@ def lib():
         L.orc_wells_dv.restype = C.c_int
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -199,6 +201,11 @@ def wells_dv(params, N: int, L: float, j: int) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later sweeps (timing only; results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def normalized(psi: np.ndarray, L: float) -> np.ndarray:

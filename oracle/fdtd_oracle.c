@@ -510,3 +510,14 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of later sweeps (for timing the oracle at
+ * one thread and at all cores); no effect without OpenMP. */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
