@@ -201,6 +201,33 @@ def plain_fp64_to_e(N=512, max_s=75.0):
     return rows, e_star
 
 
+def plain_fp32_to_e(e_star, N=512, max_s=30.0):
+    """The plain FP32 path on the same lattice from the same noise, one
+    precision and one level, checked every 100 steps until E is within 1e-6
+    of e_star.  Returns its (seconds since start, steps, energy) rows."""
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    lat = W.cornell(N)
+    K = 100
+    s = Solver(N, lat.L, dtype="f32")
+    s.set_potential(F.POT_CORNELL, lat.pot_params)
+    t0 = _timer()
+    s.set_initial(lat.seed)
+    rows = []
+    steps = 0
+    while True:
+        s.evolve(K, check_every=0, use_graph=True)
+        steps += K
+        e = s.history(0, 1)[0]["energy"]
+        rows.append((time.perf_counter() - t0, steps, e))
+        if abs(e - e_star) <= 1e-6 * abs(e_star) or time.perf_counter() - t0 > max_s:
+            break
+    s.close()
+    return rows
+
+
 def multires_to_e(e_star, N_levels=(128, 256, 512), coarse_steps=(3000, 6000), max_s=75.0):
     """The multi-resolution chain on the Cornell lattice: BF16 storage on the
     coarse levels, each relaxed for a fixed number of steps (an energy-change
@@ -262,14 +289,18 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
     """Wall time to reach the ground-state energy to 1e-6 relative on the
     Cornell lattice at 512^3 (L = 30, dt = a^2/8): the plain FP64 path from
     noise on 512^3, against the multi-resolution chain (BF16 128^3 -> BF16
-    256^3 -> FP32 512^3, trilinear reseeding, graph-captured steps).  The
-    reference E* is the plain FP64 run carried on to a change below 1e-12 per
-    100 steps, then Aitken-extrapolated."""
+    256^3 -> FP32 512^3, trilinear reseeding, graph-captured steps), and the
+    plain FP32 path from the same noise.  The reference E* is the plain FP64
+    run carried on to a change below 1e-12 per 100 steps, then
+    Aitken-extrapolated."""
     plain, e_star = plain_fp64_to_e(N_levels[-1], max_plain_s)
     note(f"plain FP64 to E: {len(plain)} checks")
     t_plain, n_plain = _first_within(plain, e_star, 1e-6)
     multi, level_log = multires_to_e(e_star, N_levels, coarse_steps, max_plain_s)
     t_multi, n_multi = _first_within(multi, e_star, 1e-6)
+    p32 = plain_fp32_to_e(e_star, N_levels[-1])
+    note(f"plain FP32 to E: {len(p32)} checks")
+    t_p32, n_p32 = _first_within(p32, e_star, 1e-6)
     return {
         "workload": f"cornell_L30_{'->'.join(str(n) for n in N_levels)}",
         "e_star": e_star,
@@ -280,6 +311,7 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
         "multires_levels": level_log,
         "multires_final_energy": multi[-1][2] if multi else None,
         "speedup": (t_plain / t_multi) if (t_plain and t_multi) else None,
+        "plain_fp32_seconds": t_p32, "plain_fp32_steps": n_p32,
     }
 
 
