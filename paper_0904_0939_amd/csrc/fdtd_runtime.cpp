@@ -343,15 +343,22 @@ long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
 }
 
 // Longest x-stream (fewest re-read halo planes, least per-item start-up)
-// that still gives each of the 256 CUs a work item.  Measured: at 512^3 one
-// long-streaming work-group per CU beats more, shorter ones; on the batch of
-// 64 lattices of side 48..160, whole-N items handed out longest first beat
-// every shorter split (item start-up outweighs the better balance).
+// that still keeps the CUs busy.  Measured (FP32, one step per pass): a
+// single lattice wants about one long-streaming work-group per CU, and a few
+// CUs idle beat twice as many shorter items (384^3: 216 items of 128 planes
+// 132 us, 432 of 64 planes 145 us; 512^3: 256 of 256 planes 274 us, 512 of
+// 128 planes 341 us), so it takes the longest stream giving at least 80% of
+// the CUs an item.  On a batch, items of uneven length are handed out longest
+// first and about two per CU balance best (64 lattices of side 48..160: 530
+// items of at most 128 planes 234 us, 374 whole-N items 258 us, 850 of 64
+// planes 244 us).  Two-step tiles keep one item per CU.
 int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
+  const long long cu = std::max(1, h->n_cu);
+  const long long need = t.tblock == 2 ? cu : (h->count > 1 ? 2 * cu : (4 * cu + 4) / 5);
   for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;
     for (const auto& m : h->mem) items += plane_items(h, t, m.N) * x_parts(m.N, xc);
-    if (items >= 256) return xc;
+    if (items >= need) return xc;
   }
   return 8;
 }
