@@ -400,6 +400,90 @@ def batch64(loop=4000, autotune=True):
             "energy_range": [min(o["energy"] for o in obs), max(o["energy"] for o in obs)]}
 
 
+def hbm_ceiling(N=512, reps=20):
+    """Plain library kernels over the same bytes as the FP32 step, timed the
+    same way: torch's device copy (1 read + 1 write of N^3 FP32) and an add
+    of two N^3 FP32 arrays into a third (2 reads + 1 write, the step's mix).
+    Context for the roofline fraction: the rate an HBM-bound kernel with
+    this access mix reaches on this device."""
+    import torch
+
+    n = N ** 3
+    a = torch.rand(n, device="cuda")
+    b = torch.rand(n, device="cuda")
+    c = torch.empty(n, device="cuda")
+
+    def rate(fn, nbytes):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return ms, nbytes / (ms * 1e-3) / 1e9
+
+    ms_c, gb_c = rate(lambda: c.copy_(a), 8 * n)
+    ms_a, gb_a = rate(lambda: torch.add(a, b, out=c), 12 * n)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"copy_ms": ms_c, "copy_GBs": gb_c, "add_2r1w_ms": ms_a, "add_2r1w_GBs": gb_a,
+            "note": f"torch copy_ and add over {N}^3 FP32 arrays ({4 * n >> 20} MiB each), "
+                    "HIP events on the current stream, mean of {reps} launches".replace("{reps}", str(reps))}
+
+
+def host_handover(N=512, steps=400):
+    """The rate when the caller hands over host buffers: V and psi uploaded
+    from pinned host memory, the steps, psi downloaded back, all timed
+    (PCIe included).  One step per hand-over, and the same with many steps."""
+    import torch
+
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    lat = W.cornell(N)
+    s = Solver(N, lat.L, dtype="f32")
+    s.set_potential(F.POT_CORNELL, lat.pot_params)
+    t = s.tuning()
+    t["vfuse"] = 0
+    s.set_tuning(**t)
+    s.set_initial(lat.seed)
+    V = torch.empty((N, N, N), dtype=torch.float32, pin_memory=True)
+    psi = torch.empty((N, N, N), dtype=torch.float32, pin_memory=True)
+    out = torch.empty((N, N, N), dtype=torch.float32, pin_memory=True)
+    psi.copy_(s.psi_tensor().cpu())  # the seeded noise start
+    V.uniform_(0.0, 1.0)  # any bounded V: the step's cost does not depend on it
+    s.evolve(64, check_every=0)  # captures the graph
+
+    def round_trip(k):
+        t0 = _timer()
+        s.set_potential_array(V)
+        s.set_initial_array(psi)
+        t1 = _timer()
+        s.evolve(k, check_every=0)
+        t2 = _timer()
+        F.fdtd_get_state(s.h, 0, out.data_ptr(), 0)
+        t3 = _timer()
+        return t1 - t0, t2 - t1, t3 - t2
+
+    round_trip(1)
+    up, st, down = round_trip(1)
+    up_k, st_k, down_k = round_trip(steps)
+    s.close()
+    sites = N ** 3
+    return {"workload": f"cornell_{N}^3_f32", "host_memory": "pinned",
+            "upload_V_psi_s": up, "download_psi_s": down,
+            "one_step_per_handover": {"step_s": st, "site_updates_per_s": sites / (up + st + down)},
+            f"{steps}_steps_per_handover": {"steps_s": st_k,
+                                            "site_updates_per_s": sites * steps / (up_k + st_k + down_k)},
+            "note": "set_potential / set_initial from host FP32 arrays (FP64 V and psi are converted "
+                    "on the device), evolve, get_state to host; synchronous calls, wall clock"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,7 +501,8 @@ def main():
                     help="vz,ry,xchunk,grid,xcd_remap,depth,variant,persist[,vfuse,tblock]")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-E and batch measurements")
-    ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64", "gradient_256"])
+    ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64", "gradient_256",
+                                                   "hbm_ceiling", "host_handover"])
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV"),
                     help="turn rocprofv3 counter runs of this bench into profiles/step_traffic.json")
     args = ap.parse_args()
@@ -447,6 +532,12 @@ def main():
         return
     if args.only == "gradient_256":
         print(json.dumps(gradient_256()), flush=True)
+        return
+    if args.only == "hbm_ceiling":
+        print(json.dumps(hbm_ceiling(args.n)), flush=True)
+        return
+    if args.only == "host_handover":
+        print(json.dumps(host_handover(args.n)), flush=True)
         return
     lat = W.cornell(args.n)
     N, L = lat.N, lat.L
@@ -565,6 +656,12 @@ def main():
         note("batch of 64 done")
         out["gradient_256"] = gradient_256()
         note("gradient done")
+    if not args.no_extras:
+        out["hbm_ceiling_torch"] = hbm_ceiling(N)
+        out["hbm_ceiling_torch"]["step_vs_add_2r1w"] = achieved / out["hbm_ceiling_torch"]["add_2r1w_GBs"]
+        note("library copy / add rates done")
+        out["host_handover"] = host_handover(N)
+        note("host hand-over done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, L, lat.pot_params, args.cpu_steps)
         note("cpu baseline done")
