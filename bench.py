@@ -484,6 +484,38 @@ def host_handover(N=512, steps=400):
                     "on the device), evolve, get_state to host; synchronous calls, wall clock"}
 
 
+def upsample_256_512(calls=10):
+    """The multi-resolution hand-over at its largest level: a BF16 256^3
+    Cornell state spread trilinearly onto the FP32 512^3 lattice of the same
+    box, then renormalised (one reduction pass over the fine state).  Wall
+    time per call (the kernel's own time comes from a trace of this leg)."""
+    from paper_0904_0939_amd import fdtd as F
+    from paper_0904_0939_amd import workloads as W
+    from paper_0904_0939_amd.solver import Solver
+
+    lat = W.cornell(512)
+    c = Solver(256, lat.L, dtype="bf16")
+    c.set_potential(F.POT_CORNELL, lat.pot_params)
+    c.set_initial(lat.seed)
+    c.evolve(100, check_every=0)
+    f = Solver(512, lat.L, dtype="f32")
+    f.set_potential(F.POT_CORNELL, lat.pot_params)
+    F.fdtd_upsample(c.h, 0, f.h, 0)
+    t0 = _timer()
+    for _ in range(calls):
+        F.fdtd_upsample(c.h, 0, f.h, 0)
+    t1 = _timer()
+    e = f.observables()[0]["energy"]
+    c.close()
+    f.close()
+    fine, coarse = 512 ** 3, 256 ** 3
+    return {"workload": "cornell_bf16_256^3_to_f32_512^3", "calls": calls,
+            "ms_per_call": (t1 - t0) / calls * 1e3,
+            "algorithmic_bytes": 4 * fine + 2 * coarse, "energy_after": e,
+            "note": "wall clock per fdtd_upsample call: the interpolation kernel, the reduction "
+                    "pass that renormalises the fine state, and the synchronisations"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -502,7 +534,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-E and batch measurements")
     ap.add_argument("--only", default="", choices=["", "time_to_e", "batch64", "gradient_256",
-                                                   "hbm_ceiling", "host_handover"])
+                                                   "hbm_ceiling", "host_handover", "upsample_256_512"])
     ap.add_argument("--summarize-rocprof", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "STATS_CSV"),
                     help="turn rocprofv3 counter runs of this bench into profiles/step_traffic.json")
     args = ap.parse_args()
@@ -538,6 +570,9 @@ def main():
         return
     if args.only == "host_handover":
         print(json.dumps(host_handover(args.n)), flush=True)
+        return
+    if args.only == "upsample_256_512":
+        print(json.dumps(upsample_256_512()), flush=True)
         return
     lat = W.cornell(args.n)
     N, L = lat.N, lat.L
@@ -662,6 +697,8 @@ def main():
         note("library copy / add rates done")
         out["host_handover"] = host_handover(N)
         note("host hand-over done")
+        out["upsample_256_512"] = upsample_256_512()
+        note("upsample done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, L, lat.pot_params, args.cpu_steps)
         note("cpu baseline done")

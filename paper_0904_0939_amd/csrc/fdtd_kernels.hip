@@ -1592,44 +1592,132 @@ __device__ __forceinline__ double fetch_c(const CS* __restrict__ pc, int N, int 
 // Trilinear spread of a coarse state onto a finer lattice of the same box
 // (Sec. VI).  Interpolates along z, then y, then x; each 1-d step adds the
 // two weighted ends, so mirrored fine sites see the same sums.
+// A thread owns kUpVZ consecutive fine z sites of one fine row y and streams
+// kUpXC fine planes.  The (z, y) interpolation of a coarse plane at the
+// thread's sites does not depend on the fine x, so it is formed once per
+// coarse plane and serves every fine plane between that coarse plane and the
+// next: a fine site then costs one lerp along x (and, at a 2x ratio, half of
+// a plane's two z lerps and one y lerp).  The fine coordinate of an axis maps
+// into coarse index space as ((2 j - (Nf - 1)) haf) / ac + (Nc - 1) / 2; the
+// plane weights of the block's x-range are formed once, in LDS.
+constexpr int kUpVZ = 4;   // fine z sites per thread
+constexpr int kUpXC = 32;  // fine planes per thread
+
+__device__ __forceinline__ void up_weight(int j, double cNf, double haf, double ac, double halfc,
+                                          int& i0, double& w) {
+  const double t = ((2.0 * j - cNf) * haf) / ac + halfc;
+  const double fl = floor(t);
+  i0 = (int)fl;
+  w = t - fl;
+}
+
 template <typename CS, typename FS>
-__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc,
-                                                     double hac, double ac,
+__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc, double ac,
                                                      FS* __restrict__ pf, int Nf, double haf) {
-  const long long n3 = (long long)Nf * Nf * Nf;
+  __shared__ int s_i0[kUpXC];
+  __shared__ double s_w[kUpXC], s_w1[kUpXC];
   const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
-  (void)hac;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (long long)gridDim.x * blockDim.x) {
-    int j[3];
-    j[2] = (int)(s % Nf);
-    const long long q = s / Nf;
-    j[1] = (int)(q % Nf);
-    j[0] = (int)(q / Nf);
-    int i0[3];
-    double w[3];
+  const int x0 = blockIdx.y * kUpXC;
+  const int nx = min(kUpXC, Nf - x0);
+  if ((int)threadIdx.x < nx) {
+    int i0;
+    double w;
+    up_weight(x0 + threadIdx.x, cNf, haf, ac, halfc, i0, w);
+    s_i0[threadIdx.x] = i0;
+    s_w[threadIdx.x] = w;
+    s_w1[threadIdx.x] = 1.0 - w;
+  }
+  __syncthreads();
+  const int nzv = (Nf + kUpVZ - 1) / kUpVZ;
+  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= (long long)Nf * nzv) return;
+  const int y = (int)(col / nzv);
+  const int z0 = (int)(col - (long long)y * nzv) * kUpVZ;
+  int iy, iz[kUpVZ];
+  double wy, wy1, wz[kUpVZ], wz1[kUpVZ];
+  up_weight(y, cNf, haf, ac, halfc, iy, wy);
+  wy1 = 1.0 - wy;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double t = ((2.0 * j[d] - cNf) * haf) / ac + halfc;
-      const double fl = floor(t);
-      i0[d] = (int)fl;
-      w[d] = t - fl;
-    }
-    double vy[2];
+  for (int j = 0; j < kUpVZ; ++j) {
+    up_weight(min(z0 + j, Nf - 1), cNf, haf, ac, halfc, iz[j], wz[j]);
+    wz1[j] = 1.0 - wz[j];
+  }
+  // (z, y) interpolation of coarse plane c at the thread's sites.  Plane c
+  // is one buffer resource (empty outside the lattice); a coarse site whose
+  // row or column lies outside the lattice gets an offset past the plane.
+  // Both read 0: the zero ghosts cost no branches and no traffic.
+  const unsigned dead = kDeadLane * (unsigned)sizeof(CS);
+  unsigned off[2][kUpVZ][2];
 #pragma unroll
-    for (int cx = 0; cx < 2; ++cx) {
-      double vz[2];
+  for (int cy = 0; cy < 2; ++cy) {
+    const int yy = iy + cy;
 #pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        const double lo = fetch_c(pc, Nc, i0[0] + cx, i0[1] + cy, i0[2]);
-        const double hi = fetch_c(pc, Nc, i0[0] + cx, i0[1] + cy, i0[2] + 1);
-        vz[cy] = (1.0 - w[2]) * lo + w[2] * hi;
+    for (int j = 0; j < kUpVZ; ++j)
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz) {
+        const int zz = iz[j] + cz;
+        const bool ok = yy >= 0 && yy < Nc && zz >= 0 && zz < Nc;
+        off[cy][j][cz] = ok ? (unsigned)(yy * Nc + zz) * (unsigned)sizeof(CS) : dead;
       }
-      vy[cx] = (1.0 - w[1]) * vz[0] + w[1] * vz[1];
+  }
+  const unsigned pbytes = (unsigned)Nc * (unsigned)Nc * (unsigned)sizeof(CS);
+  // coarse values as loaded (FP64 coarse states stay FP64)
+  using CE = typename std::conditional<sizeof(CS) == 8, double, float>::type;
+  auto plane = [&](int c, double (&o)[kUpVZ]) {
+    const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, c, Nc, pbytes);
+    CE e[2][kUpVZ][2];
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int j = 0; j < kUpVZ; ++j)
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+          CE q[1];
+          bload<CS, 1, CE>(rp, off[cy][j][cz], q);
+          e[cy][j][cz] = q[0];
+        }
+    double v[2][kUpVZ];
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int j = 0; j < kUpVZ; ++j)
+        v[cy][j] = wz1[j] * (double)e[cy][j][0] + wz[j] * (double)e[cy][j][1];
+#pragma unroll
+    for (int j = 0; j < kUpVZ; ++j) o[j] = wy1 * v[0][j] + wy * v[1][j];
+  };
+  double lo[kUpVZ], hi[kUpVZ];
+  int cur = uni(s_i0[0]);  // the block's planes: uniform
+  plane(cur, lo);
+  plane(cur + 1, hi);
+  const bool full = z0 + kUpVZ <= Nf && (Nf % kUpVZ) == 0;
+  for (int i = 0; i < nx; ++i) {
+    const int ix = uni(s_i0[i]);
+    if (ix != cur) {
+      if (ix == cur + 1) {
+#pragma unroll
+        for (int j = 0; j < kUpVZ; ++j) lo[j] = hi[j];
+      } else {
+        plane(ix, lo);
+      }
+      plane(ix + 1, hi);
+      cur = ix;
     }
-    const double v = (1.0 - w[0]) * vy[0] + w[0] * vy[1];
-    if constexpr (sizeof(FS) == 2) pf[s] = f32_to_bf16((float)v);
-    else pf[s] = (FS)v;
+    const double wx = s_w[i], wx1 = s_w1[i];
+    Pack<FS, kUpVZ> o;
+#pragma unroll
+    for (int j = 0; j < kUpVZ; ++j) {
+      const double v = wx1 * lo[j] + wx * hi[j];
+      if constexpr (sizeof(FS) == 2) o.v[j] = f32_to_bf16((float)v);
+      else o.v[j] = (FS)v;
+    }
+    FS* dst = pf + ((long long)(x0 + i) * Nf + y) * Nf + z0;
+    if (full) {
+      *reinterpret_cast<Pack<FS, kUpVZ>*>(dst) = o;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kUpVZ; ++j)
+        if (z0 + j < Nf) dst[j] = o.v[j];
+    }
   }
 }
 
@@ -2236,11 +2324,14 @@ hipError_t convert_to(const SS* src, int ddtype, void* dst, long long n, double 
 template <typename CS>
 hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, void* pf, int Nf,
                        double haf, hipStream_t s) {
-  const int g = grid_for((long long)Nf * Nf * Nf);
+  (void)hac;
+  // (y, z-vector) columns of the fine lattice x fine x-ranges of kUpXC planes
+  const long long cols = (long long)Nf * ((Nf + kUpVZ - 1) / kUpVZ);
+  const dim3 g((unsigned)((cols + kBlock - 1) / kBlock), (unsigned)((Nf + kUpXC - 1) / kUpXC));
   switch (fdtype) {
-    case kF64: hipLaunchKernelGGL((k_upsample<CS, double>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (double*)pf, Nf, haf); break;
-    case kF32: hipLaunchKernelGGL((k_upsample<CS, float>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (float*)pf, Nf, haf); break;
-    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t>), dim3(g), dim3(kBlock), 0, s, pc, Nc, hac, ac, (uint16_t*)pf, Nf, haf); break;
+    case kF64: hipLaunchKernelGGL((k_upsample<CS, double>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
+    case kF32: hipLaunchKernelGGL((k_upsample<CS, float>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
+    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
