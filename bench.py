@@ -394,9 +394,14 @@ def batch64(loop=4000, autotune=True):
     sites = sum(l.sites for l in lats)
     obs = b.observables()
     b.close()
+    # HBM bytes per site and step: psi and V read, psi' written once per pass
+    # (one step per pass, or two with tblock = 2)
+    bps = 12 / (2 if tun.get("tblock", 0) == 2 else 1)
     return {"workload": "wells_batch64_f32", "members": len(lats), "sites": sites,
             "graph_steps": loop, "ms_per_step": ms, "site_updates_per_s": sites / (ms * 1e-3),
-            "achieved_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": tun,
+            "hbm_bytes_per_site_step": bps,
+            "achieved_GBs": bps * sites / (ms * 1e-3) / 1e9,
+            "one_step_equivalent_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": tun,
             "energy_range": [min(o["energy"] for o in obs), max(o["energy"] for o in obs)]}
 
 
