@@ -324,6 +324,33 @@ def test_upsample_fp64_dyadic_and_general_ratio():
         assert f.observables()[0]["step"] == 0
 
 
+@pytest.mark.parametrize("Nc,cd,Nf,fd", [(33, "f64", 65, "f64"), (50, "f64", 77, "f64"),
+                                         (40, "f64", 24, "f64"), (31, "bf16", 62, "f64"),
+                                         (26, "f32", 45, "f32")])
+def test_upsample_ragged_sides_and_coarser_targets(Nc, cd, Nf, fd):
+    """Fine sides that are not a multiple of the kernel's 4-site vectors,
+    non-integer ratios, and a target coarser than the source (several
+    coarse planes between two fine ones)."""
+    say(f"case: upsample {Nc} {cd} -> {Nf} {fd}")
+    L = 9.0
+    c = Solver(Nc, L, dtype=cd)
+    c.set_potential(F.POT_HO, [1, 1, 1])
+    c.set_initial(13)
+    f = Solver(Nf, L, dtype=fd)
+    f.set_potential(F.POT_HO, [1, 1, 1])
+    F.fdtd_upsample(c.h, 0, f.h, 0)
+    coarse = orc.initial(Nc, 13)
+    if cd == "bf16":
+        coarse = bf16_round(coarse)
+    elif cd == "f32":
+        coarse = coarse.astype(np.float32).astype(np.float64)
+    ref = orc.upsample(coarse, Nf, L)
+    tol = 1e-12 if fd == "f64" else 1e-6
+    np.testing.assert_allclose(f.psi(), ref, rtol=0, atol=tol * np.abs(ref).max())
+    c.close()
+    f.close()
+
+
 def test_upsample_from_bf16_and_parity():
     say("case: upsample bf16 -> f32")
     Nc, Nf, L = 32, 64, 10.0
