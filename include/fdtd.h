@@ -306,8 +306,9 @@ fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out);
 fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
 
 /* Time every valid launch shape of the step kernel on this handle with HIP
- * events, keep the fastest, and cache it per (device, dtype, lattice sizes)
- * for later handles of this process.  The state, step counters and history
+ * events, keep the fastest, and cache it per (device architecture and CU
+ * count, dtype, lattice sizes) for later handles of this process (and, through
+ * fdtd_tune_cache_save / _load, of later processes).  The state, step counters and history
  * are saved first and restored after (the trials step the lattice).  A shape
  * found in the cache is set without timing; best_ms then receives -1.
  * The shapes include two-step passes (tblock = 2), which move a rescale due
@@ -315,6 +316,21 @@ fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
  * chosen (optional) receives the shape; best_ms (optional) its time per step. */
 fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen,
                           double* best_ms);
+
+/* The autotuner's cache as a text file, so that a later process starts from
+ * the shapes an earlier one measured.  One line per entry: the key (no
+ * spaces; e.g. gfx950/256cu:1:512 for one F32 lattice of side 512), then the
+ * ten fdtd_tuning fields in their declaration order; lines starting with '#'
+ * are comments.
+ * save: writes every entry of this process's cache to `path` (created or
+ *   truncated).  EINVAL if the file cannot be written.
+ * load: replaces this process's cache with the entries of `path`.  EINVAL
+ *   (cache unchanged) if the file cannot be read or a line is malformed.  An
+ *   entry is checked only when fdtd_autotune finds it: one the handle rejects
+ *   (fdtd_set_tuning fails) is dropped and the shapes are timed anew.
+ * Neither touches the GPU; both are thread-safe. */
+fdtd_status fdtd_tune_cache_save(const char* path);
+fdtd_status fdtd_tune_cache_load(const char* path);
 
 /* ---- misc -------------------------------------------------------------------*/
 

@@ -9,9 +9,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -113,6 +115,7 @@ struct fdtd_ctx {
   bool tuned = false;
   bool table_v_only = false;  // set while the gradient driver recomputes the forward
   int n_cu = 256;  // compute units of the device: work-groups of a persistent launch
+  std::string arch = "gfx";  // the device's architecture name (gfx950 ...), for tuning keys
   unsigned spin_limit = 1u << 22;  // polls of a persistent dependency wait
 
   // pinned host staging for small readbacks
@@ -254,6 +257,11 @@ fdtd_status set_device(fdtd_ctx* h) {
   int cu = 0;
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && cu > 0)
     h->n_cu = cu;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+    std::string a(prop.gcnArchName);
+    h->arch = a.substr(0, a.find(':'));  // drop the feature suffixes
+  }
   return FDTD_OK;
 }
 
@@ -740,8 +748,10 @@ fdtd_status start_state(fdtd_ctx* h, int m) {
 std::mutex g_tune_mu;
 std::map<std::string, fdtd_tuning> g_tune_cache;
 
+// Cache key of a launch shape: the device's architecture and CU count, the
+// dtype and every member's side (no spaces: one token of the cache file).
 std::string tune_key(const fdtd_ctx* h) {
-  std::string k = std::to_string(h->device) + ":" + std::to_string(h->dtype);
+  std::string k = h->arch + "/" + std::to_string(h->n_cu) + "cu:" + std::to_string(h->dtype);
   for (auto& m : h->mem) k += ":" + std::to_string(m.N);
   return k;
 }
@@ -1202,10 +1212,12 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      ST_TRY(fdtd_set_tuning(h, &it->second));
-      if (chosen) *chosen = it->second;
-      if (best_ms) *best_ms = -1.0;
-      return FDTD_OK;
+      if (fdtd_set_tuning(h, &it->second) == FDTD_OK) {
+        if (chosen) *chosen = it->second;
+        if (best_ms) *best_ms = -1.0;
+        return FDTD_OK;
+      }
+      g_tune_cache.erase(it);  // a loaded entry this handle rejects: tune anew
     }
   }
   // save what the trial steps overwrite: the current field of every member,
@@ -1320,6 +1332,59 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   }
   if (chosen) *chosen = best;
   if (best_ms) *best_ms = best_t;
+  return FDTD_OK;
+}
+
+// ------------------------------------------------------ launch-shape cache --
+namespace {
+constexpr const char* kTuneHeader =
+    "# fdtd launch shapes: key vz ry xchunk grid xcd_remap depth variant persist vfuse tblock";
+}
+
+extern "C" fdtd_status fdtd_tune_cache_save(const char* path) {
+  if (!path) return fail(FDTD_EINVAL, "tune_cache_save: null path");
+  std::map<std::string, fdtd_tuning> copy;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    copy = g_tune_cache;
+  }
+  std::ofstream f(path, std::ios::trunc);
+  if (!f) return fail(FDTD_EINVAL, std::string("tune_cache_save: cannot open ") + path);
+  f << kTuneHeader << "\n";
+  for (const auto& kv : copy) {
+    const fdtd_tuning& t = kv.second;
+    f << kv.first << ' ' << t.vz << ' ' << t.ry << ' ' << t.xchunk << ' ' << t.grid << ' '
+      << t.xcd_remap << ' ' << t.depth << ' ' << t.variant << ' ' << t.persist << ' ' << t.vfuse
+      << ' ' << t.tblock << "\n";
+  }
+  f.flush();
+  if (!f) return fail(FDTD_EINVAL, std::string("tune_cache_save: write failed on ") + path);
+  return FDTD_OK;
+}
+
+extern "C" fdtd_status fdtd_tune_cache_load(const char* path) {
+  if (!path) return fail(FDTD_EINVAL, "tune_cache_load: null path");
+  std::ifstream f(path);
+  if (!f) return fail(FDTD_EINVAL, std::string("tune_cache_load: cannot open ") + path);
+  std::map<std::string, fdtd_tuning> got;
+  std::string line;
+  int no = 0;
+  while (std::getline(f, line)) {
+    ++no;
+    const size_t b = line.find_first_not_of(" \t\r");
+    if (b == std::string::npos || line[b] == '#') continue;
+    std::istringstream in(line);
+    std::string key, extra;
+    fdtd_tuning t{};
+    if (!(in >> key >> t.vz >> t.ry >> t.xchunk >> t.grid >> t.xcd_remap >> t.depth >> t.variant >>
+          t.persist >> t.vfuse >> t.tblock) ||
+        (in >> extra))
+      return fail(FDTD_EINVAL, "tune_cache_load: " + std::string(path) + " line " +
+                                   std::to_string(no) + ": expected a key and 10 integers");
+    got[key] = t;
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.swap(got);
   return FDTD_OK;
 }
 

@@ -95,6 +95,8 @@ _SIGS = {
     "fdtd_get_tuning": [_P, C.POINTER(fdtd_tuning)],
     "fdtd_set_tuning": [_P, C.POINTER(fdtd_tuning)],
     "fdtd_autotune": [_P, C.c_int32, C.POINTER(fdtd_tuning), C.POINTER(C.c_double)],
+    "fdtd_tune_cache_save": [C.c_char_p],
+    "fdtd_tune_cache_load": [C.c_char_p],
     "fdtd_synchronize": [_P],
     "fdtd_info": [_P, C.POINTER(C.c_int32), C.POINTER(_P)],
 }
@@ -246,6 +248,14 @@ def fdtd_autotune(h, steps_per_trial: int = 10):
     ms = C.c_double()
     _call("fdtd_autotune", h, steps_per_trial, C.byref(t), C.byref(ms))
     return t, ms.value
+
+
+def fdtd_tune_cache_save(path: str):
+    _call("fdtd_tune_cache_save", os.fsencode(path))
+
+
+def fdtd_tune_cache_load(path: str):
+    _call("fdtd_tune_cache_load", os.fsencode(path))
 
 
 def fdtd_synchronize(h):

@@ -234,3 +234,38 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
                 assert "liboracle" not in text and "fdtd_oracle" not in text, fn
+
+
+def test_tune_cache_file_round_trip_and_errors(tmp_path):
+    """The autotuner's cache file is written and read back without a GPU;
+    a malformed line is rejected and leaves the cache as it was; an empty
+    file clears it."""
+    entries = ["gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0",
+               "gfx950/256cu:0:64:96 2 1 128 0 1 2 0 64 1 2"]
+    good = tmp_path / "good.txt"
+    good.write_text("# shapes\n" + entries[0] + "\n\n   \n" + entries[1] + "\n")
+    F.fdtd_tune_cache_load(str(good))
+    out = tmp_path / "out.txt"
+
+    def saved():
+        F.fdtd_tune_cache_save(str(out))
+        text = out.read_text().splitlines()
+        assert text[0].startswith("#")
+        return sorted(line for line in text if line and not line.startswith("#"))
+
+    assert saved() == sorted(entries)
+    bad = tmp_path / "bad.txt"
+    for text in ("gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1\n",      # a field missing
+                 "gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0 7\n",  # one too many
+                 "gfx950/256cu:1:512 4 x 0 0 1 1 3 0 1 0\n"):   # not an integer
+        bad.write_text(entries[0] + "\n" + text)
+        assert status_of("fdtd_tune_cache_load", os.fsencode(str(bad))) == F.EINVAL
+        assert "line 2" in F.lib().fdtd_last_error().decode()
+    assert saved() == sorted(entries)
+    assert status_of("fdtd_tune_cache_load", os.fsencode(str(tmp_path / "missing.txt"))) == F.EINVAL
+    assert status_of("fdtd_tune_cache_save", os.fsencode(str(tmp_path / "no" / "dir.txt"))) == F.EINVAL
+    assert status_of("fdtd_tune_cache_load", None) == F.EINVAL
+    empty = tmp_path / "empty.txt"
+    empty.write_text("")
+    F.fdtd_tune_cache_load(str(empty))
+    assert saved() == []

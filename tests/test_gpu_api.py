@@ -86,6 +86,49 @@ def test_autotune_leaves_state_step_and_history_untouched():
     assert s.observables()[0]["step"] == 40
 
 
+def test_autotune_cache_file_carries_shapes_to_a_new_cache(tmp_path):
+    """Shapes timed by one autotune call, saved to a file, cleared from the
+    cache and loaded back, are set by a later autotune call without timing;
+    an entry the handle rejects is dropped and the shapes are timed anew."""
+    say("case: autotune cache file fp32 40^3")
+    empty = tmp_path / "empty.txt"
+    empty.write_text("")
+
+    def solver():
+        s = Solver(40, 10.0, dtype="f32")
+        s.set_potential(F.POT_HO, [1, 1, 1])
+        s.set_initial(9)
+        return s
+
+    F.fdtd_tune_cache_load(str(empty))
+    s = solver()
+    t1, ms1 = s.autotune(3)
+    assert ms1 > 0
+    s.close()
+    path = tmp_path / "shapes.txt"
+    F.fdtd_tune_cache_save(str(path))
+    lines = [line for line in path.read_text().splitlines() if not line.startswith("#")]
+    assert len(lines) == 1 and lines[0].split()[0].endswith(f"cu:{F.F32}:40")
+    assert lines[0].startswith("gfx950/")
+    F.fdtd_tune_cache_load(str(empty))
+    F.fdtd_tune_cache_load(str(path))
+    s = solver()
+    t2, ms2 = s.autotune(3)
+    assert ms2 == -1.0 and t2 == t1 and s.tuning() == t1
+    s.close()
+    # vz = 3 fits no dtype: the entry is dropped, the shapes timed again
+    key = lines[0].split()[0]
+    bad = tmp_path / "bad.txt"
+    bad.write_text(f"{key} 3 1 0 0 1 1 0 0 1 0\n")
+    F.fdtd_tune_cache_load(str(bad))
+    s = solver()
+    t3, ms3 = s.autotune(3)
+    assert ms3 > 0
+    s.evolve(20)
+    assert s.observables()[0]["step"] == 20
+    s.close()
+
+
 def test_history_ring_keeps_the_last_records():
     """A 16-record ring after 50 FP64 steps holds steps 34..49, each the
     oracle's energy of the state entering that step."""
