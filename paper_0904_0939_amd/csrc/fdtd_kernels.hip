@@ -1611,9 +1611,22 @@ __device__ __forceinline__ void up_weight(int j, double cNf, double haf, double 
   w = t - fl;
 }
 
-template <typename CS, typename FS>
+// Coarse planes whose loads a thread issues together (FP64 coarse states:
+// half as many, for registers).
+#ifndef FDTD_UP_GROUP
+#define FDTD_UP_GROUP 4
+#endif
+
+// PAIR: a BF16 coarse lattice of even side under a fine side at least twice
+// as large.  A thread's coarse z indices then lie within six consecutive
+// values from an even start, read as three dwords per coarse row (a dword
+// holds an aligned pair of sites and never straddles a row), 6 loads per
+// coarse plane instead of 16 single-site loads.  Single-site loads are what
+// bound the kernel: they keep the texture addresser busy.
+template <typename CS, typename FS, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc, double ac,
                                                      FS* __restrict__ pf, int Nf, double haf) {
+  static_assert(!PAIR || sizeof(CS) == 2, "pair loads are for BF16 coarse states");
   __shared__ int s_i0[kUpXC];
   __shared__ double s_w[kUpXC], s_w1[kUpXC];
   const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
@@ -1661,21 +1674,66 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
       }
   }
   const unsigned pbytes = (unsigned)Nc * (unsigned)Nc * (unsigned)sizeof(CS);
+  // PAIR: dword m of row cy holds coarse sites zs + 2m, zs + 2m + 1; site j
+  // takes its two coarse values at dz[j], dz[j] + 1 of those six (<= 4 + 1:
+  // the fine sites of a thread span at most 1.5 coarse spacings)
+  unsigned poff[2][3];
+  int dz[kUpVZ];
+  if constexpr (PAIR) {
+    const int zs = iz[0] - (iz[0] & 1);  // down to even (iz[0] >= -1)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      const int yy = iy + cy;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int zz = zs + 2 * m;  // even: the pair lies wholly inside or outside [0, Nc)
+        const bool ok = yy >= 0 && yy < Nc && zz >= 0 && zz < Nc;
+        poff[cy][m] = ok ? (unsigned)(yy * Nc + zz) * 2u : dead;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kUpVZ; ++j) dz[j] = iz[j] - zs;
+  }
   // coarse values as loaded (FP64 coarse states stay FP64)
   using CE = typename std::conditional<sizeof(CS) == 8, double, float>::type;
-  auto plane = [&](int c, double (&o)[kUpVZ]) {
+  // loads of coarse plane c at the thread's sites, and their (z, y) lerps
+  auto load_plane = [&](int c, CE (&e)[2][kUpVZ][2]) {
     const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, c, Nc, pbytes);
-    CE e[2][kUpVZ][2];
+    if constexpr (PAIR) {
 #pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
+      for (int cy = 0; cy < 2; ++cy) {
+        float v[6];
 #pragma unroll
-      for (int j = 0; j < kUpVZ; ++j)
-#pragma unroll
-        for (int cz = 0; cz < 2; ++cz) {
-          CE q[1];
-          bload<CS, 1, CE>(rp, off[cy][j][cz], q);
-          e[cy][j][cz] = q[0];
+        for (int m = 0; m < 3; ++m) {
+          const unsigned wd = __builtin_amdgcn_raw_buffer_load_b32(rp, (int)poff[cy][m], 0, 0);
+          v[2 * m] = __uint_as_float(wd << 16);
+          v[2 * m + 1] = __uint_as_float(wd & 0xffff0000u);
         }
+#pragma unroll
+        for (int j = 0; j < kUpVZ; ++j)
+#pragma unroll
+          for (int cz = 0; cz < 2; ++cz) {
+            const int k = dz[j] + cz;
+            float r = v[0];
+#pragma unroll
+            for (int q = 1; q < 6; ++q) r = k == q ? v[q] : r;
+            e[cy][j][cz] = r;
+          }
+      }
+    } else {
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int j = 0; j < kUpVZ; ++j)
+#pragma unroll
+          for (int cz = 0; cz < 2; ++cz) {
+            CE q[1];
+            bload<CS, 1, CE>(rp, off[cy][j][cz], q);
+            e[cy][j][cz] = q[0];
+          }
+    }
+  };
+  auto interp = [&](const CE (&e)[2][kUpVZ][2], double (&o)[kUpVZ]) {
     double v[2][kUpVZ];
 #pragma unroll
     for (int cy = 0; cy < 2; ++cy)
@@ -1685,23 +1743,14 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
 #pragma unroll
     for (int j = 0; j < kUpVZ; ++j) o[j] = wy1 * v[0][j] + wy * v[1][j];
   };
-  double lo[kUpVZ], hi[kUpVZ];
-  int cur = uni(s_i0[0]);  // the block's planes: uniform
-  plane(cur, lo);
-  plane(cur + 1, hi);
+  // A window of G + 1 consecutive coarse planes, base .. base + G (w[k] is
+  // plane base + k), advanced G planes at a time: the loads of the G new
+  // planes are issued together, one memory round trip per G coarse planes.
+  // Fine planes are emitted in order; fine plane i lies between coarse
+  // planes s_i0[i] and s_i0[i] + 1 (non-decreasing in i; uniform).
+  constexpr int G = sizeof(CE) == 8 ? (FDTD_UP_GROUP + 1) / 2 : FDTD_UP_GROUP;
   const bool full = z0 + kUpVZ <= Nf && (Nf % kUpVZ) == 0;
-  for (int i = 0; i < nx; ++i) {
-    const int ix = uni(s_i0[i]);
-    if (ix != cur) {
-      if (ix == cur + 1) {
-#pragma unroll
-        for (int j = 0; j < kUpVZ; ++j) lo[j] = hi[j];
-      } else {
-        plane(ix, lo);
-      }
-      plane(ix + 1, hi);
-      cur = ix;
-    }
+  auto emit = [&](int i, const double (&lo)[kUpVZ], const double (&hi)[kUpVZ]) {
     const double wx = s_w[i], wx1 = s_w1[i];
     Pack<FS, kUpVZ> o;
 #pragma unroll
@@ -1718,6 +1767,33 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
       for (int j = 0; j < kUpVZ; ++j)
         if (z0 + j < Nf) dst[j] = o.v[j];
     }
+  };
+  double w[G + 1][kUpVZ];
+  int base = uni(s_i0[0]);  // the block's planes: uniform
+  {
+    CE e[G + 1][2][kUpVZ][2];
+#pragma unroll
+    for (int k = 0; k <= G; ++k) load_plane(base + k, e[k]);
+#pragma unroll
+    for (int k = 0; k <= G; ++k) interp(e[k], w[k]);
+  }
+  int i = 0;
+  while (true) {
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+      while (i < nx && uni(s_i0[i]) == base + k) {
+        emit(i, w[k], w[k + 1]);
+        ++i;
+      }
+    if (i >= nx) break;
+    base += G;
+#pragma unroll
+    for (int j = 0; j < kUpVZ; ++j) w[0][j] = w[G][j];
+    CE e[G][2][kUpVZ][2];
+#pragma unroll
+    for (int k = 0; k < G; ++k) load_plane(base + 1 + k, e[k]);
+#pragma unroll
+    for (int k = 0; k < G; ++k) interp(e[k], w[k + 1]);
   }
 }
 
@@ -2328,10 +2404,21 @@ hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, 
   // (y, z-vector) columns of the fine lattice x fine x-ranges of kUpXC planes
   const long long cols = (long long)Nf * ((Nf + kUpVZ - 1) / kUpVZ);
   const dim3 g((unsigned)((cols + kBlock - 1) / kBlock), (unsigned)((Nf + kUpXC - 1) / kUpXC));
+  if constexpr (sizeof(CS) == 2) {
+    if (Nc % 2 == 0 && Nf >= 2 * Nc) {
+      switch (fdtype) {
+        case kF64: hipLaunchKernelGGL((k_upsample<CS, double, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
+        case kF32: hipLaunchKernelGGL((k_upsample<CS, float, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
+        case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (fdtype) {
-    case kF64: hipLaunchKernelGGL((k_upsample<CS, double>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
-    case kF32: hipLaunchKernelGGL((k_upsample<CS, float>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
-    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
+    case kF64: hipLaunchKernelGGL((k_upsample<CS, double, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
+    case kF32: hipLaunchKernelGGL((k_upsample<CS, float, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
+    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

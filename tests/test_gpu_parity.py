@@ -326,11 +326,13 @@ def test_upsample_fp64_dyadic_and_general_ratio():
 
 @pytest.mark.parametrize("Nc,cd,Nf,fd", [(33, "f64", 65, "f64"), (50, "f64", 77, "f64"),
                                          (40, "f64", 24, "f64"), (31, "bf16", 62, "f64"),
-                                         (26, "f32", 45, "f32")])
+                                         (26, "f32", 45, "f32"), (40, "bf16", 90, "f64"),
+                                         (34, "bf16", 100, "f32"), (2, "bf16", 9, "f64")])
 def test_upsample_ragged_sides_and_coarser_targets(Nc, cd, Nf, fd):
     """Fine sides that are not a multiple of the kernel's 4-site vectors,
-    non-integer ratios, and a target coarser than the source (several
-    coarse planes between two fine ones)."""
+    non-integer ratios, a target coarser than the source (several coarse
+    planes between two fine ones), and BF16 sources of even side under fine
+    sides of at least twice theirs (the coarse rows read as site pairs)."""
     say(f"case: upsample {Nc} {cd} -> {Nf} {fd}")
     L = 9.0
     c = Solver(Nc, L, dtype=cd)
