@@ -474,6 +474,36 @@ def test_gradient_field_matches_oracle_across_launch_shapes(dtype, N):
 
 
 # ----------------------------------------------------------- error paths ----
+@pytest.mark.parametrize("dtype,N", [("f64", 2), ("f64", 3), ("f32", 2), ("f32", 5), ("f32", 4),
+                                     ("bf16", 2), ("bf16", 7)])
+def test_smallest_lattices_against_oracle(dtype, N):
+    """Lattices of a few sites per side: most neighbours are the zero ghosts,
+    a lane's vector is partly or wholly outside the lattice, an odd side has
+    its midplane site at the centre."""
+    say(f"case: smallest lattice {dtype} N={N}")
+    L, T, p = 4.0, 40, [1.0, 1.2, 0.8]
+    s = Solver(N, L, dtype=dtype)
+    s.set_potential(F.POT_HO, p)
+    s.set_initial(5)
+    s.evolve(T)
+    ob = s.observables()[0]
+    V = orc.potential(orc.POT_HO, p, N, L)
+    psi = orc.initial(N, 5)
+    orc.evolve(psi, V, L, (L / N) ** 2 / 8, T)
+    e = orc.observables(psi, V, L)["energy"]
+    assert ob["step"] == T
+    if dtype == "bf16":
+        # stochastically rounded 8-bit significands: the relaxation agrees
+        # to the storage precision
+        assert ob["energy"] == pytest.approx(e, rel=2e-2)
+        return
+    tol = {"f64": 1e-10, "f32": 1e-5}[dtype]
+    assert ob["energy"] == pytest.approx(e, rel=tol)
+    ref = orc.normalized(psi, L)
+    np.testing.assert_allclose(s.psi(), ref, rtol=0, atol=tol * np.abs(ref).max())
+    s.close()
+
+
 def test_nonfinite_initial_state_is_reported():
     s = Solver(16, 8.0, dtype="f32")
     s.set_potential(F.POT_HO, [1, 1, 1])
