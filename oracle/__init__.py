@@ -72,6 +72,8 @@ def lib():
         L.orc_energy_grad_v.restype = C.c_double
         L.orc_wells_dv.argtypes = [_dp, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
         L.orc_wells_dv.restype = C.c_int
+        L.orc_potential_dv.argtypes = [C.c_int, _dp, C.c_int, C.c_int, C.c_double, C.c_int, _dp]
+        L.orc_potential_dv.restype = C.c_int
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
@@ -196,6 +198,16 @@ def wells_dv(params, N: int, L: float, j: int) -> np.ndarray:
     out = _field(N)
     if lib().orc_wells_dv(_ptr(p), int(p.size), int(N), float(L), int(j), _ptr(out)) != 0:
         raise ValueError("oracle: bad well-parameter index")
+    return out
+
+
+def potential_dv(kind: int, params, N: int, L: float, j: int) -> np.ndarray:
+    """dV/dparams[j] at every site for an analytic potential kind."""
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1))
+    out = _field(N)
+    if lib().orc_potential_dv(int(kind), _ptr(p), int(p.size), int(N), float(L), int(j),
+                              _ptr(out)) != 0:
+        raise ValueError("oracle: the potential kind has no parameter j")
     return out
 
 

@@ -479,26 +479,78 @@ double orc_energy_grad_v(int N, double L, double mass, double dt, const double* 
   return E;
 }
 
-/* Derivative of the Gaussian-well potential (kind ORC_POT_WELLS) with respect
- * to its parameter p[j], for the well amplitude A_k (j = 3 + 5k) and width
- * s_k (j = 7 + 5k):  dV/dA_k = -e_k,  dV/ds_k = -A_k e_k d_k^2 / s_k^3 with
- * e_k = exp(-d_k^2 / (2 s_k^2)).  Returns -1 for any other j. */
-int orc_wells_dv(const double* p, int np, int N, double L, int j, double* out) {
+/* Derivative dV/dp[j] of the analytic potential of kind `kind`, as
+ * orc_potential evaluates it, at every site (the Sec. VII potentials and the
+ * Gaussian wells):
+ *   CONST        dV/dp0 = 1;
+ *   HO           dV/dp_d = p_d x_d^2 (x_0 = x, x_1 = y, x_2 = z);
+ *   COULOMB      dV/dp0 = -1/r;
+ *   COULOMB_REG  dV/dp0 = 1/a - 1/r for r >= a, 0 inside r < a;
+ *   CORNELL      dV/dp0 = -1/r, dV/dp1 = r, dV/dp2 = z^2;
+ *   WELLS        the oscillator part as HO for j < 3; for well k, with
+ *                e = exp(-d^2 / (2 s^2)) and d the distance to its centre c,
+ *                dV/dA = -e, dV/dc_d = -A e (x_d - c_d) / s^2,
+ *                dV/ds = -A e d^2 / s^3;
+ *   DODECA       dV/dp0 = 1 inside the solid, 0 outside.
+ * Returns -1 for a parameter the kind does not have. */
+int orc_potential_dv(int kind, const double* p, int np, int N, double L, int j, double* out) {
   const double a = L / (double)N;
-  if (np < 8 || (np - 3) % 5 != 0 || j < 3 || j >= np) return -1;
-  const int k = (j - 3) / 5, r = (j - 3) % 5;
-  if (r != 0 && r != 4) return -1;
-  const double* w = p + 3 + 5 * k;
+  if (N < 1 || j < 0 || j >= np) return -1;
+  switch (kind) {
+    case ORC_POT_CONST: case ORC_POT_COULOMB: case ORC_POT_COULOMB_REG: case ORC_POT_DODECA:
+      if (j != 0) return -1;
+      break;
+    case ORC_POT_HO: case ORC_POT_CORNELL:
+      if (np < 3 || j > 2) return -1;
+      break;
+    case ORC_POT_WELLS:
+      if (np < 3 || (np - 3) % 5 != 0) return -1;
+      break;
+    default: return -1;
+  }
+  const double half = 0.5 * (double)(N - 1) * a;
   for (int ix = 0; ix < N; ++ix)
     for (int iy = 0; iy < N; ++iy)
       for (int iz = 0; iz < N; ++iz) {
-        const double dx = orc_coord(ix, N, a) - w[1], dy = orc_coord(iy, N, a) - w[2],
-                     dz = orc_coord(iz, N, a) - w[3];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const double e = exp(-d2 / (2.0 * w[4] * w[4]));
-        out[ORC_IDX(N, ix, iy, iz)] = (r == 0) ? -e : -w[0] * e * d2 / (w[4] * w[4] * w[4]);
+        const double xs[3] = {orc_coord(ix, N, a), orc_coord(iy, N, a), orc_coord(iz, N, a)};
+        const double r = sqrt(xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2]);
+        double d = 0.0;
+        switch (kind) {
+          case ORC_POT_CONST: d = 1.0; break;
+          case ORC_POT_HO: d = p[j] * xs[j] * xs[j]; break;
+          case ORC_POT_COULOMB: d = -1.0 / r; break;
+          case ORC_POT_COULOMB_REG: d = (r < a) ? 0.0 : (1.0 / a - 1.0 / r); break;
+          case ORC_POT_CORNELL: d = (j == 0) ? -1.0 / r : (j == 1 ? r : xs[2] * xs[2]); break;
+          case ORC_POT_WELLS:
+            if (j < 3) {
+              d = p[j] * xs[j] * xs[j];
+            } else {
+              const double* w = p + 3 + 5 * ((j - 3) / 5);
+              const int q = (j - 3) % 5;
+              const double dx = xs[0] - w[1], dy = xs[1] - w[2], dz = xs[2] - w[3];
+              const double d2 = dx * dx + dy * dy + dz * dz;
+              const double e = exp(-d2 / (2.0 * w[4] * w[4]));
+              if (q == 0) d = -e;
+              else if (q == 4) d = -w[0] * e * d2 / (w[4] * w[4] * w[4]);
+              else d = -w[0] * e * (xs[q - 1] - w[q]) / (w[4] * w[4]);
+            }
+            break;
+          case ORC_POT_DODECA:
+            d = (N > 1 && orc_dodeca_inside(xs[0] / half, xs[1] / half, xs[2] / half)) ? 1.0 : 0.0;
+            break;
+        }
+        out[ORC_IDX(N, ix, iy, iz)] = d;
       }
   return 0;
+}
+
+/* The Gaussian-well derivatives for the amplitudes A_k (j = 3 + 5k) and widths
+ * s_k (j = 7 + 5k) only; -1 for any other j. */
+int orc_wells_dv(const double* p, int np, int N, double L, int j, double* out) {
+  if (np < 8 || (np - 3) % 5 != 0 || j < 3 || j >= np) return -1;
+  const int r = (j - 3) % 5;
+  if (r != 0 && r != 4) return -1;
+  return orc_potential_dv(ORC_POT_WELLS, p, np, N, L, j, out);
 }
 
 /* Number of OpenMP threads the sweeps use (1 when built without OpenMP). */

@@ -389,6 +389,37 @@ def test_adjoint_gradient_wrt_well_parameters():
         np.testing.assert_allclose(orc.wells_dv(p, N, L, j), dv, atol=1e-8)
 
 
+@pytest.mark.parametrize("kind,params,N", [
+    (orc.POT_CONST, [0.3], 6),
+    (orc.POT_HO, [1.0, 1.3, 0.7], 7),
+    (orc.POT_COULOMB, [1.2], 8),
+    (orc.POT_COULOMB_REG, [0.9], 8),
+    (orc.POT_CORNELL, [0.4, 0.2, 0.05], 8),
+    (orc.POT_WELLS, [1.0, 0.8, 1.2, 2.0, 0.5, -0.3, 0.2, 0.9, 1.1, -1.0, 0.4, 0.0, 0.6], 7),
+    (orc.POT_DODECA, [-5.0], 9),
+])
+def test_potential_parameter_derivatives_against_differences(kind, params, N):
+    """dV/dp_j of every analytic kind, every parameter, against central
+    differences of the potential itself; indices a kind does not have are
+    refused."""
+    L = 6.0
+    p = np.array(params, dtype=np.float64)
+    for j in range(p.size):
+        h = 1e-5 * max(1.0, abs(p[j]))
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd = (orc.potential(kind, pp, N, L) - orc.potential(kind, pm, N, L)) / (2 * h)
+        dv = orc.potential_dv(kind, p, N, L, j)
+        np.testing.assert_allclose(dv, fd, rtol=1e-6, atol=1e-8 * max(1.0, np.abs(fd).max()))
+        assert np.abs(dv).max() > 0
+    with pytest.raises(ValueError):
+        orc.potential_dv(kind, p, N, L, p.size)
+    if kind in (orc.POT_HO, orc.POT_CORNELL):
+        with pytest.raises(ValueError):
+            orc.potential_dv(kind, np.append(p, 1.0), N, L, 3)
+
+
 def test_hellmann_feynman_limit_at_convergence():
     """For a converged state and small dt the gradient approaches the
     Hellmann-Feynman integral sum psi^2 dV/dtheta / sum psi^2."""
