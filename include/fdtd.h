@@ -291,9 +291,14 @@ fdtd_status fdtd_upsample(fdtd_t coarse, int32_t coarse_member, fdtd_t fine, int
  * forward states checkpointed every `checkpoint_every` steps and recomputed
  * segment by segment.  Outputs (each optional):
  *   dE_dV     device FP64 N^3 field dE/dV_i;
- *   dE_dtheta for an FDTD_POT_WELLS potential with parameters theta[ntheta]
- *             (which must be the ones V was set from), the derivatives with
- *             respect to theta[wrt[k]] for k < nwrt (A_k and s_k entries only);
+ *   dE_dtheta for a potential set by fdtd_set_potential_analytic, with
+ *             parameters theta[ntheta] (the ones V was set from: EINVAL
+ *             otherwise), the derivatives with respect to theta[wrt[k]] for
+ *             k < nwrt <= 64: dE/dtheta_j = sum_i (dE/dV_i) dV_i/dtheta_j with
+ *             the analytic dV/dtheta_j of the kind (CONST, COULOMB,
+ *             COULOMB_REG, DODECA: j = 0; HO, CORNELL: j < 3; WELLS: every
+ *             entry: oscillator frequencies, well amplitudes, centres and
+ *             widths);
  *   energy    E after `steps` steps.
  * The handle's state is advanced by `steps` steps, as fdtd_evolve would. */
 fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,

@@ -178,9 +178,10 @@ struct AdjInitArgs {
 };
 hipError_t launch_adjoint_init(int dtype, const AdjInitArgs& a, hipStream_t s);
 
-// dE/dtheta_j = sum_i G_i dV_i/dtheta_j for Gaussian-well parameters.
-hipError_t launch_wells_contract(const double* G, int N, double ha, const double* p_dev, int np,
-                                 const int* wrt_dev, int nwrt, double* partials, int nblocks,
-                                 double* out_dev, hipStream_t s);
+// dE/dtheta_j = sum_i G_i dV_i/dtheta_j for the parameters of an analytic
+// potential of kind `kind` (the FDTD_POT_* numbering), lattice spacing a.
+hipError_t launch_param_contract(const double* G, int N, double ha, double a, int kind,
+                                 const double* p_dev, int np, const int* wrt_dev, int nwrt,
+                                 double* partials, int nblocks, double* out_dev, hipStream_t s);
 
 }  // namespace fdtd

@@ -1977,18 +1977,47 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_init(AdjInitArgs a) {
   }
 }
 
-// Contraction of dE/dV with the analytic derivatives of the Gaussian wells:
-// dV/dA_k = -e_k, dV/ds_k = -A_k e_k d_k^2 / s_k^3, e_k = exp(-d_k^2 / 2 s_k^2).
+// Contraction of dE/dV with the analytic derivatives of the potential's
+// parameters (kinds numbered as in k_potential, which defines each V):
+//   CONST 1; HO p_d x_d^2; COULOMB -1/r; COULOMB_REG 1/a - 1/r (0 for r < a);
+//   CORNELL -1/r, r, z^2; WELLS p_d x_d^2 for the oscillator (j < 3), and for
+//   well k with e = exp(-d^2 / 2 s^2): A -e, centre c_d -A e (x_d - c_d) / s^2,
+//   width s -A e d^2 / s^3; DODECA 1 inside the solid.
 constexpr int kMaxWrt = 64;
 
-__global__ __launch_bounds__(kBlock) void k_wells_contract(const double* __restrict__ G, int N,
-                                                           double ha,
-                                                           const double* __restrict__ p, int np,
+__device__ __forceinline__ double param_dv(int kind, const double* __restrict__ p, int j,
+                                           const double (&xs)[3], double r, double a, int N,
+                                           double half) {
+  switch (kind) {
+    case 0: return 1.0;
+    case 1: return p[j] * xs[j] * xs[j];
+    case 2: return -1.0 / r;
+    case 3: return (r < a) ? 0.0 : (1.0 / a - 1.0 / r);
+    case 4: return j == 0 ? -1.0 / r : (j == 1 ? r : xs[2] * xs[2]);
+    case 5: {
+      if (j < 3) return p[j] * xs[j] * xs[j];
+      const double* w = p + 3 + 5 * ((j - 3) / 5);
+      const int q = (j - 3) % 5;
+      const double dx = xs[0] - w[1], dy = xs[1] - w[2], dz = xs[2] - w[3];
+      const double d2 = dx * dx + dy * dy + dz * dz;
+      const double e = exp(-d2 / (2.0 * w[4] * w[4]));
+      if (q == 0) return -e;
+      if (q == 4) return -w[0] * e * d2 / (w[4] * w[4] * w[4]);
+      return -w[0] * e * (xs[q - 1] - w[q]) / (w[4] * w[4]);
+    }
+    case 6: return (N > 1 && dodeca_inside(xs[0] / half, xs[1] / half, xs[2] / half)) ? 1.0 : 0.0;
+    default: return 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_param_contract(const double* __restrict__ G, int N,
+                                                           double ha, double a, int kind,
+                                                           const double* __restrict__ p,
                                                            const int* __restrict__ wrt, int nwrt,
                                                            double* __restrict__ partials) {
   __shared__ double red[kBlock / 64][8];
   const long long n3 = (long long)N * N * N;
-  const double cN = (double)(N - 1);
+  const double cN = (double)(N - 1), half = 0.5 * (double)(N - 1) * a;
   for (int k0 = 0; k0 < nwrt; k0 += 8) {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
@@ -1997,21 +2026,14 @@ __global__ __launch_bounds__(kBlock) void k_wells_contract(const double* __restr
       const long long q = s / N;
       const int iy = (int)(q % N);
       const int ix = (int)(q / N);
-      const double x = (2.0 * ix - cN) * ha, y = (2.0 * iy - cN) * ha, z = (2.0 * iz - cN) * ha;
+      const double xs[3] = {(2.0 * ix - cN) * ha, (2.0 * iy - cN) * ha, (2.0 * iz - cN) * ha};
+      const double r = sqrt(xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2]);
       const double g = G[s];
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) {
         const int k = k0 + kk;
         if (k >= nwrt) break;
-        const int j = wrt[k];
-        const int base = 3 + ((j - 3) / 5) * 5;
-        const bool is_s = ((j - 3) % 5) == 4;
-        const double dx = x - p[base + 1], dy = y - p[base + 2], dz = z - p[base + 3];
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const double sw = p[base + 4];
-        const double e = exp(-d2 / (2.0 * sw * sw));
-        const double dv = is_s ? -p[base] * e * d2 / (sw * sw * sw) : -e;
-        acc[kk] += g * dv;
+        acc[kk] += g * param_dv(kind, p, wrt[k], xs, r, a, N, half);
       }
     }
     block_sum<8>(acc, red);
@@ -2021,7 +2043,6 @@ __global__ __launch_bounds__(kBlock) void k_wells_contract(const double* __restr
     }
     __syncthreads();
   }
-  (void)np;
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials,
@@ -2530,11 +2551,12 @@ hipError_t launch_adjoint_init(int dtype, const AdjInitArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_wells_contract(const double* G, int N, double ha, const double* p_dev, int np,
-                                 const int* wrt_dev, int nwrt, double* partials, int nblocks,
-                                 double* out_dev, hipStream_t s) {
-  if (nwrt < 1 || nwrt > kMaxWrt || nblocks < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_wells_contract, dim3(nblocks), dim3(kBlock), 0, s, G, N, ha, p_dev, np,
+hipError_t launch_param_contract(const double* G, int N, double ha, double a, int kind,
+                                 const double* p_dev, int np, const int* wrt_dev, int nwrt,
+                                 double* partials, int nblocks, double* out_dev, hipStream_t s) {
+  if (nwrt < 1 || nwrt > kMaxWrt || nblocks < 1 || kind < 0 || kind > 6 || np < 1)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_param_contract, dim3(nblocks), dim3(kBlock), 0, s, G, N, ha, a, kind, p_dev,
                      wrt_dev, nwrt, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

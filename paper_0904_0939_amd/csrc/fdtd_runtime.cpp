@@ -65,6 +65,8 @@ struct MemberHost {
   int tb_begin = 0, tb_end = 0;  // tiles of two-step passes (member order)
   int vkind = -1;  // analytic kind the step may evaluate itself (0..4), -1: table only
   double vp[3] = {0, 0, 0};
+  int pkind = -1;              // analytic kind V was set from (-1: a caller's array)
+  std::vector<double> params;  // its parameters (for the gradient's contraction)
   int nproj = 0;          // states kept for projection (Sec. III)
   void* proj = nullptr;   // nproj * n3 values of the arithmetic type (library-owned)
 };
@@ -856,6 +858,8 @@ fdtd_status fdtd_set_potential(fdtd_t h, int32_t member, const void* v, int32_t 
   ST_TRY(copy_in_field(h, v, dtype, on_device, h->vdtype, h->V(member), h->mem[member].n3));
   h->mem[member].pot_set = true;
   h->mem[member].vkind = -1;
+  h->mem[member].pkind = -1;
+  h->mem[member].params.clear();
   h->items_valid = false;  // re-upload the member table
   drop_graphs(h);
   return FDTD_OK;
@@ -882,6 +886,8 @@ fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, 
     // the table is always filled; kinds 0..4 may also be evaluated in the step
     h->mem[m].vkind = kind <= FDTD_POT_CORNELL ? kind : -1;
     for (int k = 0; k < 3; ++k) h->mem[m].vp[k] = k < np ? p[k] : 0.0;
+    h->mem[m].pkind = kind;
+    h->mem[m].params.assign(p, p + np);
   }
   HIP_TRY(hipStreamSynchronize(h->stream));  // p is the caller's host memory
   h->items_valid = false;  // re-upload the member table
@@ -1399,12 +1405,16 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
   if (steps < 1 || checkpoint_every < 1) return fail(FDTD_EINVAL, "energy_grad: steps and checkpoint_every must be >= 1");
   if (nwrt > 0) {
     if (!theta || !wrt || !dE_dtheta || nwrt > 64) return fail(FDTD_EINVAL, "energy_grad: theta, wrt and dE_dtheta needed (nwrt <= 64)");
-    if (ntheta < 8 || (ntheta - 3) % 5 != 0 || ntheta > kMaxParams) return fail(FDTD_EINVAL, "energy_grad: theta must be a wells parameter vector");
-    for (int k = 0; k < nwrt; ++k) {
-      const int j = wrt[k];
-      if (j < 3 || j >= ntheta || ((j - 3) % 5 != 0 && (j - 3) % 5 != 4))
-        return fail(FDTD_EINVAL, "energy_grad: wrt entries must index A_k or s_k");
-    }
+    const MemberHost& m0 = h->mem[0];
+    if (m0.pkind < 0) return fail(FDTD_EINVAL, "energy_grad: dE_dtheta needs a potential set by fdtd_set_potential_analytic");
+    if (ntheta != (int)m0.params.size() || !std::equal(theta, theta + ntheta, m0.params.begin()))
+      return fail(FDTD_EINVAL, "energy_grad: theta must be the parameters the potential was set from");
+    // parameters each kind has (the rest of theta, if any, does not enter V)
+    const int nparam = (m0.pkind == FDTD_POT_HO || m0.pkind == FDTD_POT_CORNELL) ? 3
+                       : m0.pkind == FDTD_POT_WELLS ? ntheta : 1;
+    for (int k = 0; k < nwrt; ++k)
+      if (wrt[k] < 0 || wrt[k] >= nparam)
+        return fail(FDTD_EINVAL, "energy_grad: a wrt entry is not a parameter of the potential's kind");
   }
   ST_TRY(require_ready(h));
   ST_TRY(ensure_memory(h));
@@ -1545,7 +1555,8 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
     HIP_TRY(hipMemcpyAsync(p_dev, theta, sizeof(double) * ntheta, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(wrt_dev, wrt, sizeof(int) * nwrt, hipMemcpyHostToDevice, h->stream));
     const int nb = 512;
-    HIP_TRY(launch_wells_contract(G, m.N, m.ha, p_dev, ntheta, wrt_dev, nwrt, part, nb, out_dev, h->stream));
+    HIP_TRY(launch_param_contract(G, m.N, m.ha, m.a, m.pkind, p_dev, ntheta, wrt_dev, nwrt, part, nb,
+                                  out_dev, h->stream));
     HIP_TRY(hipMemcpyAsync(h->h_pin, out_dev, sizeof(double) * nwrt, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int i = 0; i < nwrt; ++i) dE_dtheta[i] = h->h_pin[i];

@@ -452,6 +452,59 @@ def test_gradient_fp32_matches_oracle_adjoint():
         assert gj == pytest.approx(float(np.sum(Go * orc.wells_dv(p, N, L, j))), rel=1e-4)
 
 
+WELLS2 = [1.0, 0.8, 1.2, 2.0, 0.5, -0.3, 0.2, 0.9, 1.1, -1.0, 0.4, 0.0, 0.6]
+
+
+@pytest.mark.parametrize("kind,params,N", [
+    (F.POT_CONST, [0.3], 10),
+    (F.POT_HO, [1.0, 1.3, 0.7], 11),
+    (F.POT_COULOMB, [1.2], 10),
+    (F.POT_COULOMB_REG, [0.9], 10),
+    (F.POT_CORNELL, [0.4, 0.2, 0.05], 10),
+    (F.POT_WELLS, WELLS2, 11),
+    (F.POT_DODECA, [-5.0], 12),
+])
+def test_gradient_wrt_every_parameter_of_every_kind(kind, params, N):
+    """dE/dtheta for every parameter of every analytic kind (FP64), against
+    the oracle's dE/dV contracted with its own dV/dtheta."""
+    say(f"case: gradient kind {kind} N={N}")
+    L, T, k = 8.0, 30, 7
+    s = Solver(N, L, dtype="f64")
+    s.set_potential(kind, params)
+    s.set_initial(15)
+    wrt = list(range(len(params)))
+    E, g, _ = s.energy_grad(T, k, theta=params, wrt=wrt)
+    V = orc.potential(kind, params, N, L)
+    Eo, Go = orc.energy_grad_v(orc.initial(N, 15), V, L, (L / N) ** 2 / 8, T)
+    assert E == pytest.approx(Eo, rel=1e-12)
+    ref = [float(np.sum(Go * orc.potential_dv(kind, params, N, L, j))) for j in wrt]
+    scale = max(abs(r) for r in ref)
+    for j, gj, rj in zip(wrt, g, ref):
+        assert gj == pytest.approx(rj, rel=1e-9, abs=1e-12 * scale), j
+    s.close()
+
+
+def test_gradient_parameter_checks():
+    say("case: gradient parameter checks")
+    s = Solver(10, 8.0, dtype="f64")
+    s.set_potential(F.POT_CORNELL, [0.4, 0.2, 0.05])
+    s.set_initial(1)
+    for theta, wrt in (([0.4, 0.2, 0.06], [0]),      # not the parameters V was set from
+                       ([0.4, 0.2], [0]),            # too few
+                       ([0.4, 0.2, 0.05], [3]),      # not a Cornell parameter
+                       ([0.4, 0.2, 0.05], [-1])):
+        with pytest.raises(F.FdtdError) as ei:
+            s.energy_grad(5, 5, theta=theta, wrt=wrt)
+        assert ei.value.status == F.EINVAL
+    V = orc.potential(orc.POT_CORNELL, [0.4, 0.2, 0.05], 10, 8.0)
+    s.set_potential_array(V)  # a caller's array: no parameters to contract with
+    with pytest.raises(F.FdtdError):
+        s.energy_grad(5, 5, theta=[0.4, 0.2, 0.05], wrt=[0])
+    E, g, G = s.energy_grad(5, 5, want_field=True)  # dE/dV alone still works
+    assert np.isfinite(E) and G is not None
+    s.close()
+
+
 @pytest.mark.parametrize("dtype,N", [("f64", 9), ("f32", 18), ("f32", 40), ("f64", 24)])
 def test_gradient_field_matches_oracle_across_launch_shapes(dtype, N):
     """dE/dV site by site: scalar lanes (N not a multiple of the vector
