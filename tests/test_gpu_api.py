@@ -232,3 +232,21 @@ def test_energy_of_potential_autograd_matches_oracle():
             orc.evolve(p, Vh, L, dt, T)
             e.append(orc.observables(p, Vh, L)["energy"])
         assert g[j] == pytest.approx((e[0] - e[1]) / (2 * h), rel=1e-6, abs=1e-9)
+
+
+def test_readme_python_example_runs(tmp_path, monkeypatch):
+    """The Python example of the README runs as written (in a scratch
+    directory, where it writes its launch-shape file)."""
+    import os
+    import re
+
+    say("case: README example")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "README.md")).read()
+    blocks = re.findall(r"```python\n(.*?)```", text, re.S)
+    assert blocks
+    monkeypatch.chdir(tmp_path)
+    env = {}
+    exec(compile(blocks[0], "README.md", "exec"), env)
+    assert (tmp_path / "shapes.txt").exists()
+    assert env["s"].observables()[0]["energy"] < 1.0
