@@ -1603,12 +1603,28 @@ __device__ __forceinline__ double fetch_c(const CS* __restrict__ pc, int N, int 
 constexpr int kUpVZ = 4;   // fine z sites per thread
 constexpr int kUpXC = 32;  // fine planes per thread
 
-__device__ __forceinline__ void up_weight(int j, double cNf, double haf, double ac, double halfc,
-                                          int& i0, double& w) {
-  const double t = ((2.0 * j - cNf) * haf) / ac + halfc;
+// Fine index j of an axis -> lower coarse index i0 and the weights of coarse
+// sites i0 (wlo) and i0 + 1 (whi).  The map is evaluated at the
+// mirror-canonical index min(j, Nf - 1 - j); the mirrored half takes the
+// mirrored coarse pair with the two weights swapped, so sites j and
+// Nf - 1 - j add the same two products: the interpolation maps a mirror-odd
+// (even) state to a mirror-odd (even) one bit for bit, whatever the spacings
+// (the sums (Nc - 1) / 2 + u and (Nc - 1) / 2 - u need not round alike).
+__device__ __forceinline__ void up_weight(int j, int Nf, int Nc, double cNf, double haf, double ac,
+                                          double halfc, int& i0, double& wlo, double& whi) {
+  const int jm = min(j, Nf - 1 - j);
+  const double t = ((2.0 * jm - cNf) * haf) / ac + halfc;
   const double fl = floor(t);
-  i0 = (int)fl;
-  w = t - fl;
+  const double w = t - fl;
+  if (j == jm) {
+    i0 = (int)fl;
+    wlo = 1.0 - w;
+    whi = w;
+  } else {
+    i0 = Nc - 2 - (int)fl;
+    wlo = w;
+    whi = 1.0 - w;
+  }
 }
 
 // Coarse planes whose loads a thread issues together (FP64 coarse states:
@@ -1628,17 +1644,17 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
                                                      FS* __restrict__ pf, int Nf, double haf) {
   static_assert(!PAIR || sizeof(CS) == 2, "pair loads are for BF16 coarse states");
   __shared__ int s_i0[kUpXC];
-  __shared__ double s_w[kUpXC], s_w1[kUpXC];
+  __shared__ double s_w[kUpXC], s_w1[kUpXC];  // weights of coarse planes i0 + 1, i0
   const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
   const int x0 = blockIdx.y * kUpXC;
   const int nx = min(kUpXC, Nf - x0);
   if ((int)threadIdx.x < nx) {
     int i0;
-    double w;
-    up_weight(x0 + threadIdx.x, cNf, haf, ac, halfc, i0, w);
+    double wlo, whi;
+    up_weight(x0 + threadIdx.x, Nf, Nc, cNf, haf, ac, halfc, i0, wlo, whi);
     s_i0[threadIdx.x] = i0;
-    s_w[threadIdx.x] = w;
-    s_w1[threadIdx.x] = 1.0 - w;
+    s_w[threadIdx.x] = whi;
+    s_w1[threadIdx.x] = wlo;
   }
   __syncthreads();
   const int nzv = (Nf + kUpVZ - 1) / kUpVZ;
@@ -1648,13 +1664,10 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
   const int z0 = (int)(col - (long long)y * nzv) * kUpVZ;
   int iy, iz[kUpVZ];
   double wy, wy1, wz[kUpVZ], wz1[kUpVZ];
-  up_weight(y, cNf, haf, ac, halfc, iy, wy);
-  wy1 = 1.0 - wy;
+  up_weight(y, Nf, Nc, cNf, haf, ac, halfc, iy, wy1, wy);
 #pragma unroll
-  for (int j = 0; j < kUpVZ; ++j) {
-    up_weight(min(z0 + j, Nf - 1), cNf, haf, ac, halfc, iz[j], wz[j]);
-    wz1[j] = 1.0 - wz[j];
-  }
+  for (int j = 0; j < kUpVZ; ++j)
+    up_weight(min(z0 + j, Nf - 1), Nf, Nc, cNf, haf, ac, halfc, iz[j], wz1[j], wz[j]);
   // (z, y) interpolation of coarse plane c at the thread's sites.  Plane c
   // is one buffer resource (empty outside the lattice); a coarse site whose
   // row or column lies outside the lattice gets an offset past the plane.

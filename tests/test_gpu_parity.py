@@ -353,6 +353,30 @@ def test_upsample_ragged_sides_and_coarser_targets(Nc, cd, Nf, fd):
     f.close()
 
 
+@pytest.mark.parametrize("Nc,Nf,L,dtype", [(64, 128, 51.2, "f32"), (40, 90, 9.3, "f64"),
+                                          (33, 66, 7.7, "f32"), (48, 96, 51.2, "bf16")])
+def test_upsample_keeps_odd_states_odd_bit_for_bit_at_any_spacing(Nc, Nf, L, dtype):
+    """Spacings that are not dyadic fractions (a = 0.8 -> 0.4, ...): the
+    fine-to-coarse map is taken at the mirror-canonical index, so mirrored
+    fine sites add the same two products and an odd state stays exactly
+    odd (a last-bit asymmetry would seed the even ground state, which then
+    grows during an odd-state relaxation)."""
+    say(f"case: upsample antisymmetry {Nc}->{Nf} L={L} {dtype}")
+    par = W.parity_word(z=2)
+    c = Solver(Nc, L, dtype=dtype)
+    c.set_potential(F.POT_HO, [1, 1, 1])
+    c.set_initial(17, parity=par)
+    c.evolve(20)
+    f = Solver(Nf, L, dtype="f32" if dtype == "bf16" else dtype)
+    f.set_potential(F.POT_HO, [1, 1, 1])
+    F.fdtd_upsample(c.h, 0, f.h, 0)
+    v = f.state()
+    assert np.array_equal(v[:, :, ::-1], -v)
+    assert np.array_equal(v[::-1, ::-1, :], v)  # even in x and y stays even
+    c.close()
+    f.close()
+
+
 def test_upsample_from_bf16_and_parity():
     say("case: upsample bf16 -> f32")
     Nc, Nf, L = 32, 64, 10.0
