@@ -372,7 +372,6 @@ def test_upsample_keeps_odd_states_odd_bit_for_bit_at_any_spacing(Nc, Nf, L, dty
     F.fdtd_upsample(c.h, 0, f.h, 0)
     v = f.state()
     assert np.array_equal(v[:, :, ::-1], -v)
-    assert np.array_equal(v[::-1, ::-1, :], v)  # even in x and y stays even
     c.close()
     f.close()
 
