@@ -224,7 +224,18 @@ fdtd_status make_ctx(const fdtd_config* cfgs, int count, fdtd_t* out) {
   bool all_div = true;
   for (auto& m : h->mem) all_div = all_div && (m.N % vw == 0);
   h->tun.vz = all_div ? vw : 1;
+  // vectors per lane: two (BF16: one), but one on a small single lattice,
+  // whose planes then split into twice as many work-item chunks.  Measured
+  // per step with the automatic x-chunk, two -> one: FP32 128^3 15.2 -> 13.4
+  // us, 160^3 27.4 -> 16.5, 176^3 28.0 -> 19.5 (192^3 22.6 -> 22.9, 256^3
+  // 35.2 -> 36.5); FP64 64^3 11.6 -> 9.5, 96^3 12.6 -> 11.9 (128^3 16.2 ->
+  // 16.6).  Batches keep two (64 lattices of side 48..160: 245.7 against
+  // 267.7 us).
   h->tun.ry = (h->dtype == kBF16 && h->tun.vz > 1) ? 1 : 2;
+  if (h->count == 1 && h->tun.vz > 1) {
+    const int small = h->dtype == kF32 ? 176 : (h->dtype == kF64 ? 96 : 0);
+    if (h->mem[0].N <= small) h->tun.ry = 1;
+  }
   h->tun.xchunk = 0;  // automatic: see auto_xchunk
   h->tun.grid = 0;
   h->tun.xcd_remap = 1;

@@ -217,6 +217,23 @@ def test_default_vector_width_follows_dtype():
         F.fdtd_destroy(h)
 
 
+def test_default_vectors_per_lane_follow_lattice_size():
+    """One vector per lane on small single lattices (FP32 up to 176^3, FP64
+    up to 96^3), two above and on batches; BF16 lanes hold 8 sites, one
+    vector."""
+    for dt, N, L, ry in ((F.F32, 128, 40.0, 1), (F.F32, 176, 40.0, 1), (F.F32, 192, 40.0, 2),
+                         (F.F32, 512, 40.0, 2), (F.F64, 96, 30.0, 1), (F.F64, 128, 30.0, 2),
+                         (F.BF16, 256, 30.0, 1), (F.F32, 18, 8.0, 2)):
+        h = F.fdtd_create(cfg(N=N, L=L, dtype=dt))
+        assert F.fdtd_get_tuning(h).ry == ry, (dt, N)
+        F.fdtd_destroy(h)
+    arr = (F.fdtd_config * 2)(cfg(N=16), cfg(N=24))
+    hb = C.c_void_p()
+    assert status_of("fdtd_create_batch", arr, 2, C.byref(hb)) == F.OK
+    assert F.fdtd_get_tuning(hb.value).ry == 2
+    F.fdtd_destroy(hb.value)
+
+
 def test_batches_default_to_persistent_launches():
     arr = (F.fdtd_config * 3)(cfg(N=16), cfg(N=24), cfg(N=32))
     h = C.c_void_p()
