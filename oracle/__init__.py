@@ -48,6 +48,8 @@ def lib():
         L.orc_potential.restype = C.c_int
         L.orc_initial.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint32, C.c_int, _dp]
         L.orc_initial.restype = C.c_int
+        L.orc_reimpose.argtypes = [C.c_int, C.c_uint32, _dp]
+        L.orc_reimpose.restype = C.c_int
         L.orc_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, _dp, _dp, _dp]
         L.orc_step.restype = None
         L.orc_hpsi.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
@@ -113,6 +115,14 @@ def initial(N: int, seed: int, kind: int = INIT_UNIFORM, parity: int = 0, member
     if rc != 0:
         raise ValueError("oracle: bad initial-state arguments")
     return psi
+
+
+def reimpose(psi: np.ndarray, parity: int) -> np.ndarray:
+    """The Sec. IV symmetry operators applied to a copy of psi (orc_reimpose)."""
+    out = np.ascontiguousarray(psi, dtype=np.float64).copy()
+    if lib().orc_reimpose(out.shape[0], int(parity), _ptr(out)) != 0:
+        raise ValueError("oracle: bad parity word")
+    return out
 
 
 def step(psi: np.ndarray, V: np.ndarray, L: float, dt: float, mass: float = 1.0) -> np.ndarray:

@@ -150,6 +150,8 @@ static double orc_unit(uint64_t r) { /* [0, 1) with 53 random bits */
   return (double)(r >> 11) * (1.0 / 9007199254740992.0);
 }
 
+int orc_reimpose(int N, uint32_t parity, double* psi);
+
 /* Random initial condition (Sec. III: random numbers of amplitude one) followed
  * by the symmetry operators of Sec. IV.  kind 0: uniform in [-1, 1); kind 1:
  * unit Gaussian (Box-Muller).  parity holds 2 bits per axis (x: bits 0-1,
@@ -171,6 +173,20 @@ int orc_initial(uint64_t seed, uint32_t member, int kind, uint32_t parity, int N
       psi[s] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
     }
   }
+  return orc_reimpose(N, parity, psi);
+}
+
+/* The symmetry operators of Sec. IV applied to a state in place: for each
+ * masked axis in turn (x, then y, then z), the lower half i < N/2 is copied
+ * onto the mirror sites i' = N-1-i, with the sign flipped under A; for odd N
+ * the mid plane is kept under S and zeroed under A.  The same operation makes
+ * the symmetric initial state and, applied again during the relaxation,
+ * reimposes the symmetry ("periodically", Sec. IV).  Returns 0, or -1 on a bad
+ * parity word. */
+int orc_reimpose(int N, uint32_t parity, double* psi) {
+  if (N < 1 || (parity >> 6)) return -1;
+  for (int ax = 0; ax < 3; ++ax)
+    if (((parity >> (2 * ax)) & 3u) == 3u) return -1;
   /* one axis at a time, exactly as the copy is described */
   for (int ax = 0; ax < 3; ++ax) {
     const uint32_t m = (parity >> (2 * ax)) & 3u;
