@@ -30,12 +30,18 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_SITE = {"f64": 24, "f32": 12, "bf16": 8}  # read psi + V, write psi'
 # FP32 adjoint step: read lambda, V, psi_t, psi_t+1 and G (FP64), write lambda and G
 ADJ_BYTES_PER_SITE = 4 * 4 + 8 + 4 + 8
-KERNEL_SRC = os.path.join(ROOT, "paper_0904_0939_amd", "csrc", "fdtd_kernels.hip")
+# the sources the step kernels are built from: a counter file is valid only
+# while their hash is the one it records
+KERNEL_SRC = [os.path.join(ROOT, "paper_0904_0939_amd", "csrc", f)
+              for f in ("fdtd_step.hip", "fdtd_device.h", "fdtd_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(key: str, sites: int):
@@ -597,19 +603,36 @@ def main():
     tun = s.tuning()
     graph = not args.no_graph
 
+    stream = torch.cuda.current_stream()
+    assert (F.fdtd_info(s.h)[1] or 0) == stream.cuda_stream  # the events see the kernels' stream
+
     def timed(steps, warmup):
-        s.evolve(warmup, check_every=0, use_graph=graph)  # also captures the graph
+        """`warmup` untimed steps, then the timed call made once untimed
+        (twice for an odd count: graphs are kept per input buffer), so that
+        every graph the timed call replays is captured before the first
+        event; the timed call only enqueues graph launches (asynchronous
+        evolve: no host synchronisation between the events).  Asserts that
+        no graph was captured and nothing allocated inside the timed region."""
+        if warmup:
+            s.evolve(warmup, check_every=0, use_graph=graph)
+        for _ in range(2 if steps % 2 else 1):
+            s.evolve(steps, check_every=0, use_graph=graph, async_launch=True)
         torch.cuda.synchronize()
-        stream = torch.cuda.current_stream()
+        c0 = s.counters()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        s.evolve(steps, check_every=0, use_graph=graph)
+        s.evolve(steps, check_every=0, use_graph=graph, async_launch=True)
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1), time.perf_counter() - t0
+        wall_s = time.perf_counter() - t0
+        c1 = s.counters()
+        assert c1["graph_captures"] == c0["graph_captures"], "a graph was captured while timed"
+        assert c1["allocations"] == c0["allocations"], "an allocation happened while timed"
+        s.evolve(0)  # synchronous: reports a non-finite step of the timed region
+        return e0.elapsed_time(e1), wall_s, c1["graph_replays"] - c0["graph_replays"]
 
-    gpu_ms, wall = timed(args.steps, args.warmup)
+    gpu_ms, wall, replays = timed(args.steps, args.warmup)
     ms_per_step = gpu_ms / args.steps
     note(f"one step per pass: {ms_per_step:.4f} ms/step")
     sites = N ** 3
@@ -683,6 +706,10 @@ def main():
                      "traffic": traffic},
         "energy_after_timed_steps": ob["energy"],
         "wall_s_timed_region": wall,
+        "timed_region": {"graph_replays": replays, "graph_captures": 0, "allocations": 0,
+                         "host_synchronisations": 0,
+                         "note": "asynchronous evolve between two HIP events on the kernels' "
+                                 "stream; every graph captured by an untimed call first"},
     }
     s.close()
     if in_kernel_v:

@@ -119,7 +119,16 @@ typedef struct {
  *                   against its projection states (fdtd_project), so the
  *                   relaxation converges to the lowest state orthogonal to
  *                   them (Sec. III); 0: never.
+ *  flags            FDTD_EVOLVE_ASYNC: enqueue the steps on the stream and
+ *                   return without waiting for them (check_every must be 0;
+ *                   steps_done = max_steps, converged = 0).  A non-finite
+ *                   reduction is then reported by the next fdtd_evolve
+ *                   without this flag.  For loops that keep the device busy
+ *                   and for timing: the calls between two events launch
+ *                   only kernels (after the first call of a given length,
+ *                   which captures its graphs).  0: wait and check.
  */
+#define FDTD_EVOLVE_ASYNC 1
 typedef struct {
   int64_t max_steps;
   int32_t renorm_every;
@@ -128,8 +137,20 @@ typedef struct {
   int32_t use_graph;
   double rel_tol;
   int32_t project_every;
-  int32_t reserved;  /* 0 */
+  int32_t flags;     /* 0 or FDTD_EVOLVE_ASYNC */
 } fdtd_evolve_opts;
+
+/* Counters of a handle since its creation (fdtd_get_counters).
+ *  graph_captures  HIP graphs captured by fdtd_evolve (use_graph);
+ *  graph_replays   graph launches;
+ *  allocations     device and pinned-host allocations the library made for
+ *                  the handle (workspace, work items, staging, scratch). */
+typedef struct {
+  int64_t graph_captures;
+  int64_t graph_replays;
+  int64_t allocations;
+  int64_t reserved;
+} fdtd_counters;
 
 /* Launch shape of the fused step kernel (see fdtd_autotune).
  *  vz     sites per lane along z, 1 or the dtype's vector width (F64 2,
@@ -228,8 +249,10 @@ fdtd_status fdtd_set_potential_analytic(fdtd_t h, int32_t member, int32_t kind, 
  * output of the stream seeded with `seed`.  The parity word then copies the
  * lower half (i < N/2) of each masked axis onto the upper half, with a sign
  * flip for A_i, zeroing the mid plane of odd N under A_i (Sec. IV).  USER
- * copies N^3 values of `dtype` from `user` (host or device).  Resets the step
- * counter and the history; the state is normalised on entry to the first step. */
+ * copies N^3 values of `dtype` from `user` (host or device) as given: the
+ * parity word is then only recorded, for reimpose_parity_every.  Resets the
+ * step counter and the history; the state is normalised on entry to the first
+ * step (fdtd_checkpoint_load restores a state with its step count). */
 fdtd_status fdtd_set_initial(fdtd_t h, int32_t member, int32_t kind, uint64_t seed,
                              uint32_t parity, const void* user, int32_t dtype, int32_t on_device);
 
@@ -278,6 +301,26 @@ fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int
  * or device), with the number of steps it has taken.  For bit-level checks
  * and checkpoints; fdtd_set_initial(USER) restores such a copy. */
 fdtd_status fdtd_get_state(fdtd_t h, int32_t member, void* dst, int32_t on_device, int64_t* step);
+
+/* Checkpoint and resume.  The paper saves converged wavefunctions and
+ * restarts from them (Sec. VII.G); a checkpoint here carries what a
+ * relaxation needs to continue exactly where it stopped: a header (magic,
+ * version, storage dtype, N, step count, the pending renormalisation scale,
+ * the parity word, L and dt) followed by the stored state as held (storage
+ * dtype, z fastest).  A run split by save / load takes the same bits as an
+ * unsplit one: the step count continues, so tau and the stochastic rounding
+ * of BF16 states continue too.
+ * size: bytes of a record of `member` (80 + N^3 * element size).
+ * save: writes the record to dst (host or device, `size` bytes); synchronises.
+ *   FDTD_ENONFINITE if the member's last step went non-finite.
+ * load: restores a record into `member` of a handle (the same one or another)
+ *   whose member has the same N, dtype, box length and dt (FDTD_EINVAL
+ *   otherwise, or for a header that is not a record).  The member's history
+ *   ring then starts at the record's step.  src (host or device) is read
+ *   before the call returns. */
+fdtd_status fdtd_checkpoint_size(fdtd_t h, int32_t member, size_t* bytes);
+fdtd_status fdtd_checkpoint_save(fdtd_t h, int32_t member, void* dst, int32_t on_device);
+fdtd_status fdtd_checkpoint_load(fdtd_t h, int32_t member, const void* src, int32_t on_device);
 
 /* Multi-resolution reseeding (Sec. VI, Sec. VII.G): trilinear interpolation of
  * the coarse member's state onto the fine member's lattice (same box_len,
@@ -341,6 +384,9 @@ fdtd_status fdtd_tune_cache_load(const char* path);
 
 /* Wait for all work of the handle. */
 fdtd_status fdtd_synchronize(fdtd_t h);
+
+/* The handle's counters (see fdtd_counters); no device work. */
+fdtd_status fdtd_get_counters(fdtd_t h, fdtd_counters* out);
 
 /* Number of members, and the stream the handle launches on. */
 fdtd_status fdtd_info(fdtd_t h, int32_t* count, void** stream);

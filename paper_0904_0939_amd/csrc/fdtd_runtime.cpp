@@ -67,6 +67,7 @@ struct MemberHost {
   double vp[3] = {0, 0, 0};
   int pkind = -1;              // analytic kind V was set from (-1: a caller's array)
   std::vector<double> params;  // its parameters (for the gradient's contraction)
+  long long hist_from = 0;  // first step whose record the history ring holds
   int nproj = 0;          // states kept for projection (Sec. III)
   void* proj = nullptr;   // nproj * n3 values of the arithmetic type (library-owned)
 };
@@ -129,6 +130,11 @@ struct fdtd_ctx {
   // projection scratch: per-work-group partial sums and the coefficients
   double* d_proj = nullptr;
 
+  // counters (fdtd_get_counters)
+  long long n_captures = 0;  // HIP graphs captured
+  long long n_replays = 0;   // HIP graph launches
+  long long n_allocs = 0;    // device and pinned host allocations made for the handle
+
   MemberDev* d_members() { return reinterpret_cast<MemberDev*>(ws + off_members); }
   MemberState* d_states() { return reinterpret_cast<MemberState*>(ws + off_states); }
   double* d_ring() { return reinterpret_cast<double*>(ws + off_ring); }
@@ -140,6 +146,17 @@ struct fdtd_ctx {
 };
 
 namespace {
+
+// Every allocation made for a handle goes through these two (counted).
+hipError_t dev_malloc(fdtd_ctx* h, void** p, size_t bytes) {
+  ++h->n_allocs;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(fdtd_ctx* h, void** p, size_t bytes) {
+  ++h->n_allocs;
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
 
 constexpr int kMaxParams = 3 + 5 * 256;
 
@@ -316,7 +333,7 @@ fdtd_status ensure_memory(fdtd_ctx* h) {
   ST_TRY(set_device(h));
   if (!h->ws) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, h->need_bytes);
+    hipError_t e = dev_malloc(h, &p, h->need_bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "device allocation of the workspace failed");
@@ -329,7 +346,7 @@ fdtd_status ensure_memory(fdtd_ctx* h) {
   }
   if (!h->h_pin) {
     h->h_pin_doubles = (size_t)kRec * (h->count + 8) + 4096;
-    HIP_TRY(hipHostMalloc((void**)&h->h_pin, h->h_pin_doubles * sizeof(double), hipHostMallocDefault));
+    HIP_TRY(host_malloc(h, (void**)&h->h_pin, h->h_pin_doubles * sizeof(double)));
   }
   return FDTD_OK;
 }
@@ -435,8 +452,13 @@ void make_items(fdtd_ctx* h, fdtd_tuning t, bool tiles, std::vector<Item>& phys,
                      [](const Item& a, const Item& b) { return a.xe - a.xb > b.xe - b.xb; });
 }
 
+void drop_graphs(fdtd_ctx* h);
+
 fdtd_status build_items(fdtd_ctx* h) {
   if (h->items_valid) return FDTD_OK;
+  // a captured graph bakes in the item and partial-sum pointers and counts of
+  // the shape it was recorded with; the buffers below may be reallocated
+  drop_graphs(h);
   std::vector<Item> phys, order, tphys, torder;
   std::vector<int> b, e, tb, te;
   make_items(h, h->tun, false, phys, order, b, e);
@@ -461,8 +483,8 @@ fdtd_status build_items(fdtd_ctx* h) {
     // chunk items in member and processing order, then the tiles in
     // processing order; partials: one slot per chunk item, two per tile (a
     // two-step pass keeps both steps' sums)
-    hipError_t e1 = hipMalloc((void**)&h->d_items, sizeof(Item) * (2 * (size_t)cap + (size_t)tcap));
-    hipError_t e2 = hipMalloc((void**)&h->d_partials,
+    hipError_t e1 = dev_malloc(h, (void**)&h->d_items, sizeof(Item) * (2 * (size_t)cap + (size_t)tcap));
+    hipError_t e2 = dev_malloc(h, (void**)&h->d_partials,
                               sizeof(double) * kRec * std::max((size_t)cap, 2 * (size_t)tcap));
     if (e1 != hipSuccess || e2 != hipSuccess) {
       (void)hipGetLastError();
@@ -624,6 +646,7 @@ fdtd_status graph_steps(fdtd_ctx* h, int K, int renorm_every) {
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    ++h->n_captures;
     if (h->graphs.size() >= 8) drop_graphs(h);
     GraphEntry g;
     g.exec = exec;
@@ -636,6 +659,7 @@ fdtd_status graph_steps(fdtd_ctx* h, int K, int renorm_every) {
     ge = &h->graphs.back();
   }
   HIP_TRY(hipGraphLaunch(ge->exec, h->stream));
+  ++h->n_replays;
   h->cur = ge->dst;
   return FDTD_OK;
 }
@@ -694,7 +718,7 @@ fdtd_status copy_in_field(fdtd_ctx* h, const void* src, int sdtype, int on_devic
   const void* dsrc = src;
   void* tmp = nullptr;
   if (!on_device) {
-    hipError_t e = hipMalloc(&tmp, bytes);
+    hipError_t e = dev_malloc(h, &tmp, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "staging allocation failed");
@@ -725,7 +749,7 @@ fdtd_status project_member(fdtd_ctx* h, int m, double* coef) {
   MemberHost& mh = h->mem[m];
   if (mh.nproj == 0) return FDTD_OK;
   if (!h->d_proj) {
-    hipError_t e = hipMalloc((void**)&h->d_proj, sizeof(double) * (project_partials_doubles() + kMaxProj));
+    hipError_t e = dev_malloc(h, (void**)&h->d_proj, sizeof(double) * (project_partials_doubles() + kMaxProj));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "projection scratch allocation failed");
@@ -755,6 +779,7 @@ fdtd_status start_state(fdtd_ctx* h, int m) {
   HIP_TRY(launch_set_state(h->d_states(), m, 1.0, 0, 1, h->stream));
   ST_TRY(observe(h, m, true));
   h->mem[m].init_set = true;
+  h->mem[m].hist_from = 0;
   return FDTD_OK;
 }
 
@@ -957,7 +982,7 @@ fdtd_status fdtd_set_projection_states(fdtd_t h, int32_t member, const void* sta
   if (n == 0) return FDTD_OK;
   const int cdt = h->dtype == kF64 ? FDTD_F64 : FDTD_F32;  // kept in the arithmetic type
   const size_t cs = elem_size(cdt);
-  hipError_t e = hipMalloc(&mh.proj, cs * (size_t)mh.n3 * n);
+  hipError_t e = dev_malloc(h, &mh.proj, cs * (size_t)mh.n3 * n);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     mh.proj = nullptr;
@@ -994,15 +1019,22 @@ fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* o, int64_t* steps_done
       o->reimpose_parity_every < 0 || o->project_every < 0)
     return fail(FDTD_EINVAL, "evolve: negative option");
   if (o->check_every > 0 && !(o->rel_tol >= 0)) return fail(FDTD_EINVAL, "evolve: rel_tol must be >= 0");
+  if (o->flags & ~FDTD_EVOLVE_ASYNC) return fail(FDTD_EINVAL, "evolve: unknown flag");
+  const bool async = (o->flags & FDTD_EVOLVE_ASYNC) != 0;
+  if (async && o->check_every > 0)
+    return fail(FDTD_EINVAL, "evolve: FDTD_EVOLVE_ASYNC cannot be combined with a convergence check");
   if (steps_done) *steps_done = 0;
   if (converged) *converged = 0;
   ST_TRY(require_ready(h));
   ST_TRY(ensure_memory(h));
   ST_TRY(build_items(h));
   std::vector<MemberState> st;
-  ST_TRY(read_states(h, st));
-  ST_TRY(check_bad(h, st));
-  const long long step0 = st[0].step;
+  long long step0 = 0;
+  if (!async) {
+    ST_TRY(read_states(h, st));
+    ST_TRY(check_bad(h, st));
+    step0 = st[0].step;
+  }
   const int K = o->check_every > 0 ? o->check_every : 64;
   const int P = o->reimpose_parity_every;
   const int PE = o->project_every;
@@ -1047,8 +1079,9 @@ fdtd_status fdtd_evolve(fdtd_t h, const fdtd_evolve_opts* o, int64_t* steps_done
       }
     }
   }
-  ST_TRY(read_states(h, st));
   if (steps_done) *steps_done = done;
+  if (async) return FDTD_OK;  // a non-finite step shows up at the next synchronous call
+  ST_TRY(read_states(h, st));
   if (converged) *converged = conv ? 1 : 0;
   ST_TRY(check_bad(h, st));
   return FDTD_OK;
@@ -1075,7 +1108,8 @@ fdtd_status fdtd_history(fdtd_t h, int32_t member, fdtd_obs* out, int64_t max, i
   std::vector<MemberState> st;
   ST_TRY(read_states(h, st));
   const long long steps = st[member].step;
-  const long long n = std::min<long long>({(long long)max, steps, (long long)h->ring_cap});
+  const long long n = std::min<long long>({(long long)max, steps - h->mem[member].hist_from,
+                                           (long long)h->ring_cap});
   std::vector<double> buf((size_t)h->ring_cap * kRec);
   HIP_TRY(hipMemcpyAsync(buf.data(), h->d_ring() + (size_t)member * h->ring_cap * kRec,
                          sizeof(double) * kRec * h->ring_cap, hipMemcpyDeviceToHost, h->stream));
@@ -1118,7 +1152,7 @@ fdtd_status fdtd_get_psi(fdtd_t h, int32_t member, void* dst, int32_t dtype, int
     HIP_TRY(hipStreamSynchronize(h->stream));
   } else {
     void* tmp = nullptr;
-    hipError_t e = hipMalloc(&tmp, bytes);
+    hipError_t e = dev_malloc(h, &tmp, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(FDTD_ENOMEM, "get_psi: staging allocation failed");
@@ -1144,6 +1178,93 @@ fdtd_status fdtd_get_state(fdtd_t h, int32_t member, void* dst, int32_t on_devic
   std::vector<MemberState> st;
   ST_TRY(read_states(h, st));
   if (step) *step = st[member].step;
+  return FDTD_OK;
+}
+
+// Checkpoint record: this header, then the stored state as held.
+struct CkptHeader {
+  uint64_t magic;     // kCkptMagic
+  int32_t version;    // 1
+  int32_t dtype;      // storage dtype of the state
+  int64_t n;          // lattice side
+  int64_t step;       // steps taken
+  double scale;       // pending scale of the next update
+  uint32_t parity;    // parity word of the member
+  uint32_t pad;
+  double L, dt;       // box and time step (checked on load)
+  uint64_t reserved[2];
+};
+static_assert(sizeof(CkptHeader) == 80, "checkpoint header layout");
+constexpr uint64_t kCkptMagic = 0x314b435044544446ull;  // "FDTDPCK1"
+
+fdtd_status fdtd_checkpoint_size(fdtd_t h, int32_t member, size_t* bytes) {
+  if (!h || !bytes) return fail(FDTD_EINVAL, "checkpoint_size: null argument");
+  ST_TRY(check_member(h, member, false));
+  *bytes = sizeof(CkptHeader) + elem_size(h->dtype) * (size_t)h->mem[member].n3;
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_checkpoint_save(fdtd_t h, int32_t member, void* dst, int32_t on_device) {
+  if (!h || !dst) return fail(FDTD_EINVAL, "checkpoint_save: null argument");
+  ST_TRY(check_member(h, member, false));
+  if (!h->mem[member].init_set) return fail(FDTD_ENOTREADY, "checkpoint_save: no state set");
+  ST_TRY(ensure_memory(h));
+  const MemberHost& m = h->mem[member];
+  std::vector<MemberState> st;
+  ST_TRY(read_states(h, st));
+  ST_TRY(check_bad(h, st));
+  CkptHeader hd;
+  memset(&hd, 0, sizeof hd);
+  hd.magic = kCkptMagic;
+  hd.version = 1;
+  hd.dtype = h->dtype;
+  hd.n = m.N;
+  hd.step = st[member].step;
+  hd.scale = st[member].scale;
+  hd.parity = m.parity;
+  hd.L = m.L;
+  hd.dt = m.dt;
+  char* d = static_cast<char*>(dst);
+  const size_t bytes = elem_size(h->dtype) * (size_t)m.n3;
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(d, &hd, sizeof hd, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(d + sizeof hd, h->psi(member, h->cur), bytes, hipMemcpyDeviceToDevice, h->stream));
+  } else {
+    memcpy(d, &hd, sizeof hd);
+    HIP_TRY(hipMemcpyAsync(d + sizeof hd, h->psi(member, h->cur), bytes, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(h->stream));  // hd is a temporary
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_checkpoint_load(fdtd_t h, int32_t member, const void* src, int32_t on_device) {
+  if (!h || !src) return fail(FDTD_EINVAL, "checkpoint_load: null argument");
+  ST_TRY(check_member(h, member, false));
+  CkptHeader hd;
+  if (on_device) {
+    ST_TRY(ensure_memory(h));
+    HIP_TRY(hipMemcpy(&hd, src, sizeof hd, hipMemcpyDeviceToHost));
+  } else {
+    memcpy(&hd, src, sizeof hd);
+  }
+  const MemberHost& m = h->mem[member];
+  if (hd.magic != kCkptMagic || hd.version != 1) return fail(FDTD_EINVAL, "checkpoint_load: not a checkpoint record");
+  if (hd.dtype != h->dtype || hd.n != m.N)
+    return fail(FDTD_EINVAL, "checkpoint_load: the record's lattice side or dtype differs from the member's");
+  if (hd.L != m.L || hd.dt != m.dt)
+    return fail(FDTD_EINVAL, "checkpoint_load: the record's box length or time step differs from the member's");
+  if (hd.step < 0 || !(hd.scale > 0) || !std::isfinite(hd.scale) || (hd.parity >> 6))
+    return fail(FDTD_EINVAL, "checkpoint_load: corrupt header");
+  ST_TRY(ensure_memory(h));
+  const size_t bytes = elem_size(h->dtype) * (size_t)m.n3;
+  const char* s = static_cast<const char*>(src) + sizeof hd;
+  HIP_TRY(hipMemcpyAsync(h->psi(member, h->cur), s, bytes,
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(launch_set_state(h->d_states(), member, hd.scale, hd.step, 1, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));  // src may be the caller's pageable memory
+  h->mem[member].parity = hd.parity;
+  h->mem[member].init_set = true;
+  h->mem[member].hist_from = hd.step;
   return FDTD_OK;
 }
 
@@ -1190,6 +1311,15 @@ fdtd_status fdtd_synchronize(fdtd_t h) {
   if (!h->ws) return FDTD_OK;
   HIP_TRY(hipSetDevice(h->device));
   HIP_TRY(hipStreamSynchronize(h->stream));
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_get_counters(fdtd_t h, fdtd_counters* out) {
+  if (!h || !out) return fail(FDTD_EINVAL, "get_counters: null argument");
+  out->graph_captures = h->n_captures;
+  out->graph_replays = h->n_replays;
+  out->allocations = h->n_allocs;
+  out->reserved = 0;
   return FDTD_OK;
 }
 
@@ -1243,7 +1373,7 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
   for (auto& m : h->mem) field_bytes += elem_size(h->dtype) * (size_t)m.n3;
   const size_t ring_bytes = sizeof(double) * kRec * (size_t)h->ring_cap * h->count;
   char* save = nullptr;
-  hipError_t e = hipMalloc((void**)&save, field_bytes + sizeof(MemberState) * h->count + ring_bytes);
+  hipError_t e = dev_malloc(h, (void**)&save, field_bytes + sizeof(MemberState) * h->count + ring_bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(FDTD_ENOMEM, "autotune: no memory to save the state");
@@ -1448,7 +1578,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
                        align256(sizeof(double) * (size_t)m.n3) + align256(sizeof(MemberDev) * seg) +
                        align256(sizeof(MemberState) * (size_t)(nck + 1)) + 65536 * sizeof(double);
   char* buf = nullptr;
-  hipError_t e = hipMalloc((void**)&buf, bytes);
+  hipError_t e = dev_malloc(h, (void**)&buf, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(FDTD_ENOMEM, "energy_grad: cannot allocate checkpoint memory");
@@ -1478,14 +1608,18 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
     HIP_TRY(hipMemcpyAsync(cks + j, h->d_states(), sizeof(MemberState), hipMemcpyDeviceToDevice, h->stream));
     ST_TRY(read_states(h, st));
     const long long t0 = st[0].step;
-    ST_TRY(launch_steps(h, len, 1, h->stream));
-    // scales folded into each step, from the history ring
-    for (int i = 0; i < len; ++i) {
-      const long long t = t0 + i;
-      HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)i * kRec, h->d_ring() + (size_t)(t % h->ring_cap) * kRec,
-                             sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+    // scales folded into each step, from the history ring: read back after
+    // at most ring_cap steps, before the ring wraps over them
+    for (int i0 = 0; i0 < len; i0 += h->ring_cap) {
+      const int n = std::min(len - i0, h->ring_cap);
+      ST_TRY(launch_steps(h, n, 1, h->stream));
+      for (int i = i0; i < i0 + n; ++i) {
+        const long long t = t0 + i;
+        HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)i * kRec, h->d_ring() + (size_t)(t % h->ring_cap) * kRec,
+                               sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
+      }
+      HIP_TRY(hipStreamSynchronize(h->stream));
     }
-    HIP_TRY(hipStreamSynchronize(h->stream));
     for (int i = 0; i < len; ++i) scales[(size_t)j * k + i] = rec[(size_t)i * kRec + kScale];
   }
   ST_TRY(read_states(h, st));

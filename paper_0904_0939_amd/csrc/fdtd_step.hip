@@ -22,374 +22,12 @@
 //     finish a member (deterministic run to run);
 //   * the renormalisation scale of step t is computed from the output norm of
 //     step t - 1 and folded into the update (the update is linear), so no
-//     extra pass and no host round trip is needed.
-#include <hip/hip_runtime.h>
-#include <math.h>
-#include <stdint.h>
+#include "fdtd_device.h"
 
-#include <algorithm>
-#include <type_traits>
-
-#include "fdtd_internal.h"
-
-// No implicit fused multiply-adds anywhere in this file: every fma is written
-// out (fma_c), so a site's arithmetic is the same whichever kernel it is
-// inlined into.  The one-step, persistent and two-step kernels then give the
-// same bits for the same step.
 #pragma clang fp contract(off)
 
 namespace fdtd {
 namespace {
-
-// ---------------------------------------------------------------- types ----
-template <int DT>
-struct Types;
-template <>
-struct Types<kF64> {
-  using S = double;  // storage
-  using V = double;  // potential storage
-  using C = double;  // arithmetic
-  static constexpr int kVec = 2;
-};
-template <>
-struct Types<kF32> {
-  using S = float;
-  using V = float;
-  using C = float;
-  static constexpr int kVec = 4;
-};
-template <>
-struct Types<kBF16> {
-  using S = uint16_t;
-  using V = float;
-  using C = float;
-  static constexpr int kVec = 8;
-};
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-// Round to nearest even; NaN stays a (quiet) NaN.  Acts on the magnitude
-// bits only, so it commutes with negation.
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-  const uint32_t u = __float_as_uint(f);
-  const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-  return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? ((u >> 16) | 0x40u) : rne);  // quiet NaN
-}
-
-template <typename S, typename C>
-__device__ __forceinline__ C to_c(S v) {
-  if constexpr (sizeof(S) == 2) {
-    return (C)bf16_to_f32(v);
-  } else {
-    return (C)v;
-  }
-}
-
-template <typename S, typename C>
-__device__ __forceinline__ S from_c(C v) {
-  if constexpr (sizeof(S) == 2) {
-    return f32_to_bf16((float)v);
-  } else {
-    return (S)v;
-  }
-}
-
-template <typename S, int VZ>
-struct alignas(sizeof(S) * VZ) Pack {
-  S v[VZ];
-};
-
-template <typename S, int VZ, typename C>
-__device__ __forceinline__ void load_vec(const S* __restrict__ p, C (&o)[VZ]) {
-  const Pack<S, VZ> t = *reinterpret_cast<const Pack<S, VZ>*>(p);
-#pragma unroll
-  for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
-}
-
-template <typename S, int VZ>
-__device__ __forceinline__ void store_vec(S* __restrict__ p, const Pack<S, VZ>& t) {
-  *reinterpret_cast<Pack<S, VZ>*>(p) = t;
-}
-
-template <typename C, int VZ>
-__device__ __forceinline__ void zero_vec(C (&o)[VZ]) {
-#pragma unroll
-  for (int j = 0; j < VZ; ++j) o[j] = C(0);
-}
-
-__device__ __forceinline__ float rcp_c(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_c(double x) { return 1.0 / x; }
-__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum NV values over the work-group; the result is valid in thread 0.
-// Fixed order: lanes by butterfly, then waves 0..3 left to right.
-template <int NV, int NW = kBlock / 64>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
-  if ((tid & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[tid >> 6][k] = v[k];
-  }
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double t = red[0][k];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) t += red[w][k];
-      v[k] = t;
-    }
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ bool finite_d(double x) { return !(isnan(x) || isinf(x)); }
-
-// Values the work-group shares (work-item fields, member constants) kept in
-// scalar registers: buffer descriptors built from them must be uniform, or
-// every buffer access becomes a per-lane loop.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ unsigned uni(unsigned v) {
-  return (unsigned)__builtin_amdgcn_readfirstlane((int)v);
-}
-template <typename T>
-__device__ __forceinline__ T* uni(T* p) {
-  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
-  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
-}
-
-// ------------------------------------------------------- buffer access ----
-// Raw buffer loads return 0 and raw buffer stores are dropped for offsets at
-// or beyond the resource's size.  Each x-plane gets its own resource, sized
-// to the plane (or to 0 for the ghost planes x = -1 and x = N), so the
-// Dirichlet ghosts around the lattice, the y = -1 / y = N rows and the
-// ragged tail of a work item cost no branches and no HBM traffic.
-constexpr int kRsrcWord3 = 0x00020000;  // gfx9-family raw buffer descriptor
-constexpr unsigned kDeadLane = 1u << 28;  // element offset used by lanes past the plane
-
-// Resource for plane x of a field whose planes are `bytes` long; planes
-// outside [0, N) get an empty resource (every access reads 0 / is dropped).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, int x, int N,
-                                                            unsigned bytes) {
-  const bool in = x >= 0 && x < N;
-  char* p = const_cast<char*>(static_cast<const char*>(base)) + (in ? (long long)x * bytes : 0);
-  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, in ? (int)bytes : 0, kRsrcWord3);
-}
-
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-
-// Cache policy bits of buffer accesses: kNT streams past the caches (data
-// used once: V, and the written state); kKeep leaves the default policy
-// (psi, whose lines are re-read as neighbours by adjacent lanes).
-constexpr int kKeep = 0;
-constexpr int kNT = 2;
-// Stores written through at system scope (sc0 sc1): the written state stays in
-// the last-level cache (MALL) for the next step's reads.  Measured per FP32
-// step: 256^3 51.7 -> 42.5 us, 320^3 101.9 -> 88.5 us, but 384^3 158.6 -> 162.0
-// and 512^3 282.1 -> 283.3 us, where the lattice does not fit.
-constexpr int kWriteThrough = 1 | 16;
-// Build-time choice of the policies of the four streams of the step kernel.
-#ifndef FDTD_AUX_PSI
-#define FDTD_AUX_PSI 0  // own-site psi loads (first touch of each plane)
-#endif
-#ifndef FDTD_AUX_NBR
-#define FDTD_AUX_NBR 0  // y / z neighbour loads (re-reads, meant to hit L2)
-#endif
-#ifndef FDTD_AUX_V
-#define FDTD_AUX_V 2    // V loads (used once): non-temporal
-#endif
-#ifndef FDTD_AUX_OUT
-#define FDTD_AUX_OUT 2  // psi' stores (read back only by the next launch): non-temporal
-#endif
-
-// Load VZ consecutive elements of S at byte offset `off`, converted to C.
-template <typename S, int VZ, typename C, int AUX = kKeep>
-__device__ __forceinline__ void bload(__amdgpu_buffer_rsrc_t r, unsigned off, C (&o)[VZ]) {
-  constexpr int kBytes = (int)sizeof(S) * VZ;
-  if constexpr (kBytes == 16) {
-    const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
-    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
-#pragma unroll
-    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
-  } else if constexpr (kBytes == 32) {
-    const u32x4 w0 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, AUX);
-    const u32x4 w1 = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off + 16, 0, AUX);
-    const Pack<S, VZ / 2> t0 = __builtin_bit_cast(Pack<S, VZ / 2>, w0);
-    const Pack<S, VZ / 2> t1 = __builtin_bit_cast(Pack<S, VZ / 2>, w1);
-#pragma unroll
-    for (int j = 0; j < VZ / 2; ++j) {
-      o[j] = to_c<S, C>(t0.v[j]);
-      o[j + VZ / 2] = to_c<S, C>(t1.v[j]);
-    }
-  } else if constexpr (kBytes == 8) {
-    const u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX);
-    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
-#pragma unroll
-    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
-  } else if constexpr (kBytes == 4) {
-    const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, AUX);
-    const Pack<S, VZ> t = __builtin_bit_cast(Pack<S, VZ>, w);
-#pragma unroll
-    for (int j = 0; j < VZ; ++j) o[j] = to_c<S, C>(t.v[j]);
-  } else {
-    static_assert(kBytes == 2, "unsupported vector width");
-    const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, AUX);
-    o[0] = to_c<S, C>(__builtin_bit_cast(S, w));
-  }
-}
-
-template <typename S, int VZ, int AUX = kKeep>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, const Pack<S, VZ>& t) {
-  constexpr int kBytes = (int)sizeof(S) * VZ;
-  if constexpr (kBytes == 32) {
-    Pack<S, VZ / 2> lo, hi;
-#pragma unroll
-    for (int j = 0; j < VZ / 2; ++j) {
-      lo.v[j] = t.v[j];
-      hi.v[j] = t.v[j + VZ / 2];
-    }
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, lo), r, (int)off, 0, AUX);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, hi), r, (int)off + 16, 0, AUX);
-  } else if constexpr (kBytes == 16) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, (int)off, 0, AUX);
-  } else if constexpr (kBytes == 8) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, t), r, (int)off, 0, AUX);
-  } else if constexpr (kBytes == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, t), r, (int)off, 0, AUX);
-  } else {
-    static_assert(kBytes == 2, "unsupported vector width");
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, t), r, (int)off, 0, AUX);
-  }
-}
-
-// Stochastic rounding to BF16 (used for the stored state of BF16 lattices):
-// add 16 random bits to the magnitude and truncate.  The result is unbiased,
-// E[round(v)] = v, so increments far below one BF16 ulp still move the state
-// on average instead of being rounded away.  Acts on the magnitude only, so
-// mirror sites given the same random bits round to exactly opposite values.
-// Branch-free: Inf keeps its all-zero low half, so adding r16 < 2^16 leaves
-// it Inf; a NaN magnitude is first replaced by the quiet NaN 0x7fc00000,
-// which the addition cannot carry out of the NaN range.
-__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16) {
-  const uint32_t u = __float_as_uint(f);
-  const uint32_t mag = min(u & 0x7fffffffu, 0x7fc00000u);
-  return (uint16_t)(((u & 0x80000000u) | (mag + r16)) >> 16);
-}
-
-// 32-bit integer hash (lowbias32, C. Wellons): random bits of the rounding.
-// The 32 bits of a site are hash32(q ^ kSaltYZ) ^ hash32(cx + hash32(step)),
-// with cx = min(x, N - 1 - x) and q its mirror-canonical (y, z) index k
-// (odd N) or k >> 1 (even N).  The first factor is fixed per lane for a whole
-// work item, the second is uniform over the work-group (scalar unit), so a
-// site costs one XOR.  On even N one 32-bit draw serves two sites: the site
-// takes half k & 1; the z-pair {2i, 2i+1} always shares k >> 1 (on one side
-// of the centre the two indices differ in the last bit only; a pair across
-// the centre is one canonical site).  The bits depend on the canonical
-// (x, y, z) and the step only, never on the launch shape, and mirror sites
-// share them.
-__device__ __forceinline__ uint32_t hash32(uint32_t x) {
-  x ^= x >> 16;
-  x *= 0x7feb352du;
-  x ^= x >> 15;
-  x *= 0x846ca68bu;
-  x ^= x >> 16;
-  return x;
-}
-constexpr uint32_t kSaltYZ = 0x68e31da4u;
-
-// Device-scope relaxed load of member state that other work-groups of the
-// same launch may have written (a vector load, never the scalar cache).
-template <typename T>
-__device__ __forceinline__ T ld_agent(const T& x) {
-  return __hip_atomic_load(const_cast<T*>(&x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// A work item hands its partial sums to the member's last work-group within
-// one launch.  Only the partials cross work-groups inside a launch (the
-// updated state is read by the next launch), so instead of a release fence,
-// which writes back the whole L2 of this XCD, the partials are stored as
-// agent-scope atomic stores (written through to the coherence point), the
-// wave waits until they have completed (vmcnt(0)), and only then counts the
-// item on the member's counter; the last work-group reads them with
-// agent-scope atomic loads.  Returns the counter's previous value.
-template <int NV>
-__device__ __forceinline__ unsigned publish_partials(double* const (&dst)[NV], const double (&v)[NV][5],
-                                                     unsigned* counter) {
-#pragma unroll
-  for (int i = 0; i < NV; ++i)
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-      __hip_atomic_store(&dst[i][q], v[i][q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt, lgkmcnt unconstrained
-  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Last work-group of member m: record the step's sums, set the scale of the
-// next update, advance the step counter, flag non-finite sums, re-arm the
-// completion counter and, last, publish the step as finalised (release).
-// rn: -1 the renorm_every rule (rescale when the new step count is a
-// multiple of renorm_every); 0 no rescale; 1 the rule applied to this step or
-// the one before (the second step of a temporally blocked pass: a rescale due
-// after the first is deferred to it).
-__device__ __forceinline__ void finalize(const StepArgs& A, const MemberDev& M, int m,
-                                      const double (&tot)[5], bool upd, int rn = -1) {
-  MemberState& st = A.states[m];
-  const double kin = -M.kin_scale * tot[1];
-  const long long t = ld_agent(st.step);
-  double rec[kRec] = {tot[0], kin, tot[2], tot[3], tot[4], (double)t, ld_agent(st.scale), 0.0};
-  if (upd) {
-    double* dst = A.ring + ((long long)m * A.ring_cap + (t % A.ring_cap)) * kRec;
-#pragma unroll
-    for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
-    const long long nt = t + 1;
-    const bool renorm = A.renorm_every > 0 && rn != 0 &&
-                        ((nt % A.renorm_every) == 0 || (rn == 1 && ((nt - 1) % A.renorm_every) == 0));
-    st.scale = renorm ? 1.0 / sqrt(M.a3 * tot[4]) : 1.0;
-    st.step = nt;
-    if (!(finite_d(tot[0]) && finite_d(tot[4]) && finite_d(kin) && finite_d(tot[2])) &&
-        !ld_agent(st.bad)) {
-      st.bad = 1;
-      st.bad_step = t;
-    }
-  } else {
-    // reduction-only pass: the host inspects the sums itself
-    double* dst = A.obs_out + (long long)m * kRec;
-#pragma unroll
-    for (int k = 0; k < kRec; ++k) dst[k] = rec[k];
-    if (A.set_scale) st.scale = 1.0 / sqrt(M.a3 * tot[0]);
-  }
-  st.counter = 0u;
-  if (upd) __hip_atomic_fetch_add(&st.fin, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Cross-lane read within the wave (ds_bpermute through the LDS crossbar,
-// no memory traffic); src must be in [0, 64) for the lanes whose result is used.
-__device__ __forceinline__ float shfl_c(float v, int src) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute((src & 63) << 2, __float_as_int(v)));
-}
-__device__ __forceinline__ double shfl_c(double v, int src) {
-  const long long u = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)u);
-  const int hi = __builtin_amdgcn_ds_bpermute((src & 63) << 2, (int)(u >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-#ifndef FDTD_SHUFFLE_Z
-#define FDTD_SHUFFLE_Z 1
-#endif
-constexpr bool kShuffleZ = FDTD_SHUFFLE_Z != 0;
 
 // ------------------------------------------------------- fused step kernel --
 // Per-lane state of one work item: RY vectors of VZ sites at fixed (y, z).
@@ -1426,725 +1064,6 @@ __global__ __launch_bounds__(TileShape<DT>::kTB) void k_step_tile(StepArgs A) {
     __syncthreads();
   }
 }
-
-// ----------------------------------------------------------- potentials ----
-// Regular dodecahedron of Sec. VII.E in lattice units u = x / ((N - 1) a / 2)
-// (the first and last sites of each axis at u = -1 and 1): vertices
-// (+-1, +-1, +-1)/phi, (0, +-1/phi^2, +-1), (+-1/phi^2, +-1, 0),
-// (+-1, 0, +-1/phi^2); faces perpendicular to (0, +-phi, +-1), (+-1, 0, +-phi),
-// (+-phi, +-1, 0), each at the largest projection of the vertices on its unit
-// normal.  Closed, with a relative slack of 1e-12 so that sites exactly on a
-// face are inside whatever the last bit; FP64 without fused multiply-adds.
-__device__ bool dodeca_inside(double ux, double uy, double uz) {
-#pragma clang fp contract(off)
-  const double phi = 0.5 * (1.0 + sqrt(5.0));
-  const double ip = 1.0 / phi, ip2 = 1.0 / (phi * phi);
-  double vtx[20][3];
-  int nv = 0;
-  for (int sx = -1; sx <= 1; sx += 2)
-    for (int sy = -1; sy <= 1; sy += 2)
-      for (int sz = -1; sz <= 1; sz += 2) {
-        vtx[nv][0] = sx * ip;
-        vtx[nv][1] = sy * ip;
-        vtx[nv][2] = sz * ip;
-        ++nv;
-      }
-  for (int s1 = -1; s1 <= 1; s1 += 2)
-    for (int s2 = -1; s2 <= 1; s2 += 2) {
-      vtx[nv][0] = 0.0; vtx[nv][1] = s1 * ip2; vtx[nv][2] = s2 * 1.0; ++nv;
-      vtx[nv][0] = s1 * ip2; vtx[nv][1] = s2 * 1.0; vtx[nv][2] = 0.0; ++nv;
-      vtx[nv][0] = s1 * 1.0; vtx[nv][1] = 0.0; vtx[nv][2] = s2 * ip2; ++nv;
-    }
-  const double nrm[6][3] = {{0, phi, 1}, {0, phi, -1}, {1, 0, phi},
-                            {-1, 0, phi}, {phi, 1, 0}, {phi, -1, 0}};
-  for (int f = 0; f < 6; ++f) {
-    const double len = sqrt(nrm[f][0] * nrm[f][0] + nrm[f][1] * nrm[f][1] + nrm[f][2] * nrm[f][2]);
-    double d = 0.0;
-    for (int v = 0; v < 20; ++v) {
-      const double pr = (vtx[v][0] * nrm[f][0] + vtx[v][1] * nrm[f][1] + vtx[v][2] * nrm[f][2]) / len;
-      d = pr > d ? pr : d;
-    }
-    const double q = (ux * nrm[f][0] + uy * nrm[f][1] + uz * nrm[f][2]) / len;
-    if (fabs(q) > d * (1.0 + 1e-12)) return false;
-  }
-  return true;
-}
-
-template <typename TV>
-__global__ __launch_bounds__(kBlock) void k_potential(TV* __restrict__ V, int N, double ha,
-                                                      double a, int kind,
-                                                      const double* __restrict__ p, int np) {
-  const long long n3 = (long long)N * N * N;
-  const double cN = (double)(N - 1);
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (long long)gridDim.x * blockDim.x) {
-    const int iz = (int)(s % N);
-    const long long q = s / N;
-    const int iy = (int)(q % N);
-    const int ix = (int)(q / N);
-    const double x = (2.0 * ix - cN) * ha, y = (2.0 * iy - cN) * ha, z = (2.0 * iz - cN) * ha;
-    const double r = sqrt(x * x + y * y + z * z);
-    double v = 0.0;
-    switch (kind) {
-      case 0: v = p[0]; break;
-      case 1: v = 0.5 * (p[0] * p[0] * x * x + p[1] * p[1] * y * y + p[2] * p[2] * z * z); break;
-      case 2: v = -p[0] / r; break;
-      case 3: v = (r < a) ? 0.0 : (-p[0] / r + p[0] / a); break;
-      case 4: v = -p[0] / r + p[1] * r + p[2] * z * z; break;
-      case 5: {
-        v = 0.5 * (p[0] * p[0] * x * x + p[1] * p[1] * y * y + p[2] * p[2] * z * z);
-        for (int k = 3; k + 4 < np; k += 5) {
-          const double dx = x - p[k + 1], dy = y - p[k + 2], dz = z - p[k + 3];
-          const double d2 = dx * dx + dy * dy + dz * dz;
-          v -= p[k] * exp(-d2 / (2.0 * p[k + 4] * p[k + 4]));
-        }
-        break;
-      }
-      case 6: {
-        const double half = 0.5 * (double)(N - 1) * a;
-        v = (N > 1 && dodeca_inside(x / half, y / half, z / half)) ? p[0] : 0.0;
-        break;
-      }
-      default: v = 0.0;
-    }
-    V[s] = (TV)v;
-  }
-}
-
-// -------------------------------------------------------- initial state ----
-__device__ __forceinline__ uint64_t splitmix(uint64_t seed, uint64_t counter) {
-  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ double unit53(uint64_t r) {
-  return (double)(r >> 11) * (1.0 / 9007199254740992.0);
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_initial(S* __restrict__ psi, int N, uint64_t seed,
-                                                    uint32_t member, int kind, uint32_t parity) {
-  const long long n3 = (long long)N * N * N;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (long long)gridDim.x * blockDim.x) {
-    int c[3];
-    c[2] = (int)(s % N);
-    const long long q = s / N;
-    c[1] = (int)(q % N);
-    c[0] = (int)(q / N);
-    double sign = 1.0;
-    bool zero = false;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const uint32_t mode = (parity >> (2 * ax)) & 3u;
-      if (mode == 0u) continue;
-      const int mir = N - 1 - c[ax];
-      if (c[ax] > mir) {  // upper half takes the value of its mirror site
-        c[ax] = mir;
-        if (mode == 2u) sign = -sign;
-      } else if (c[ax] == mir && mode == 2u) {
-        zero = true;
-      }
-    }
-    const long long src = ((long long)c[0] * N + c[1]) * N + c[2];
-    const uint64_t ctr = ((uint64_t)member << 36) + 2ull * (uint64_t)src;
-    double val;
-    if (kind == 0) {
-      val = 2.0 * unit53(splitmix(seed, ctr)) - 1.0;
-    } else {
-      const double u1 = unit53(splitmix(seed, ctr)) + 1.0 / 9007199254740992.0;
-      const double u2 = unit53(splitmix(seed, ctr + 1ull));
-      val = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-    }
-    val = zero ? 0.0 : sign * val;
-    if constexpr (sizeof(S) == 2) psi[s] = f32_to_bf16((float)val);
-    else psi[s] = (S)val;
-  }
-}
-
-// ----------------------------------------------------------- conversion ----
-template <typename SS, typename DS>
-__global__ __launch_bounds__(kBlock) void k_convert(const SS* __restrict__ src,
-                                                    DS* __restrict__ dst, long long n,
-                                                    double scale) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    double v;
-    if constexpr (sizeof(SS) == 2) v = (double)bf16_to_f32(src[i]);
-    else v = (double)src[i];
-    v *= scale;
-    if constexpr (sizeof(DS) == 2) dst[i] = f32_to_bf16((float)v);
-    else dst[i] = (DS)v;
-  }
-}
-
-// ------------------------------------------------------------- upsample ----
-template <typename CS>
-__device__ __forceinline__ double fetch_c(const CS* __restrict__ pc, int N, int x, int y, int z) {
-  if (x < 0 || y < 0 || z < 0 || x >= N || y >= N || z >= N) return 0.0;  // ghost
-  const CS v = pc[((long long)x * N + y) * N + z];
-  if constexpr (sizeof(CS) == 2) return (double)bf16_to_f32(v);
-  else return (double)v;
-}
-
-// Trilinear spread of a coarse state onto a finer lattice of the same box
-// (Sec. VI).  Interpolates along z, then y, then x; each 1-d step adds the
-// two weighted ends, so mirrored fine sites see the same sums.
-// A thread owns kUpVZ consecutive fine z sites of one fine row y and streams
-// kUpXC fine planes.  The (z, y) interpolation of a coarse plane at the
-// thread's sites does not depend on the fine x, so it is formed once per
-// coarse plane and serves every fine plane between that coarse plane and the
-// next: a fine site then costs one lerp along x (and, at a 2x ratio, half of
-// a plane's two z lerps and one y lerp).  The fine coordinate of an axis maps
-// into coarse index space as ((2 j - (Nf - 1)) haf) / ac + (Nc - 1) / 2; the
-// plane weights of the block's x-range are formed once, in LDS.
-constexpr int kUpVZ = 4;   // fine z sites per thread
-constexpr int kUpXC = 32;  // fine planes per thread
-
-// Fine index j of an axis -> lower coarse index i0 and the weights of coarse
-// sites i0 (wlo) and i0 + 1 (whi).  The map is evaluated at the
-// mirror-canonical index min(j, Nf - 1 - j); the mirrored half takes the
-// mirrored coarse pair with the two weights swapped, so sites j and
-// Nf - 1 - j add the same two products: the interpolation maps a mirror-odd
-// (even) state to a mirror-odd (even) one bit for bit, whatever the spacings
-// (the sums (Nc - 1) / 2 + u and (Nc - 1) / 2 - u need not round alike).
-__device__ __forceinline__ void up_weight(int j, int Nf, int Nc, double cNf, double haf, double ac,
-                                          double halfc, int& i0, double& wlo, double& whi) {
-  const int jm = min(j, Nf - 1 - j);
-  const double t = ((2.0 * jm - cNf) * haf) / ac + halfc;
-  const double fl = floor(t);
-  const double w = t - fl;
-  if (j == jm) {
-    i0 = (int)fl;
-    wlo = 1.0 - w;
-    whi = w;
-  } else {
-    i0 = Nc - 2 - (int)fl;
-    wlo = w;
-    whi = 1.0 - w;
-  }
-}
-
-// Coarse planes whose loads a thread issues together (FP64 coarse states:
-// half as many, for registers).
-#ifndef FDTD_UP_GROUP
-#define FDTD_UP_GROUP 4
-#endif
-
-// PAIR: a BF16 coarse lattice of even side under a fine side at least twice
-// as large.  A thread's coarse z indices then lie within six consecutive
-// values from an even start, read as three dwords per coarse row (a dword
-// holds an aligned pair of sites and never straddles a row), 6 loads per
-// coarse plane instead of 16 single-site loads.  Single-site loads are what
-// bound the kernel: they keep the texture addresser busy.
-template <typename CS, typename FS, bool PAIR>
-__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc, double ac,
-                                                     FS* __restrict__ pf, int Nf, double haf) {
-  static_assert(!PAIR || sizeof(CS) == 2, "pair loads are for BF16 coarse states");
-  __shared__ int s_i0[kUpXC];
-  __shared__ double s_w[kUpXC], s_w1[kUpXC];  // weights of coarse planes i0 + 1, i0
-  const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
-  const int x0 = blockIdx.y * kUpXC;
-  const int nx = min(kUpXC, Nf - x0);
-  if ((int)threadIdx.x < nx) {
-    int i0;
-    double wlo, whi;
-    up_weight(x0 + threadIdx.x, Nf, Nc, cNf, haf, ac, halfc, i0, wlo, whi);
-    s_i0[threadIdx.x] = i0;
-    s_w[threadIdx.x] = whi;
-    s_w1[threadIdx.x] = wlo;
-  }
-  __syncthreads();
-  const int nzv = (Nf + kUpVZ - 1) / kUpVZ;
-  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (long long)Nf * nzv) return;
-  const int y = (int)(col / nzv);
-  const int z0 = (int)(col - (long long)y * nzv) * kUpVZ;
-  int iy, iz[kUpVZ];
-  double wy, wy1, wz[kUpVZ], wz1[kUpVZ];
-  up_weight(y, Nf, Nc, cNf, haf, ac, halfc, iy, wy1, wy);
-#pragma unroll
-  for (int j = 0; j < kUpVZ; ++j)
-    up_weight(min(z0 + j, Nf - 1), Nf, Nc, cNf, haf, ac, halfc, iz[j], wz1[j], wz[j]);
-  // (z, y) interpolation of coarse plane c at the thread's sites.  Plane c
-  // is one buffer resource (empty outside the lattice); a coarse site whose
-  // row or column lies outside the lattice gets an offset past the plane.
-  // Both read 0: the zero ghosts cost no branches and no traffic.
-  const unsigned dead = kDeadLane * (unsigned)sizeof(CS);
-  unsigned off[2][kUpVZ][2];
-#pragma unroll
-  for (int cy = 0; cy < 2; ++cy) {
-    const int yy = iy + cy;
-#pragma unroll
-    for (int j = 0; j < kUpVZ; ++j)
-#pragma unroll
-      for (int cz = 0; cz < 2; ++cz) {
-        const int zz = iz[j] + cz;
-        const bool ok = yy >= 0 && yy < Nc && zz >= 0 && zz < Nc;
-        off[cy][j][cz] = ok ? (unsigned)(yy * Nc + zz) * (unsigned)sizeof(CS) : dead;
-      }
-  }
-  const unsigned pbytes = (unsigned)Nc * (unsigned)Nc * (unsigned)sizeof(CS);
-  // PAIR: dword m of row cy holds coarse sites zs + 2m, zs + 2m + 1; site j
-  // takes its two coarse values at dz[j], dz[j] + 1 of those six (<= 4 + 1:
-  // the fine sites of a thread span at most 1.5 coarse spacings)
-  unsigned poff[2][3];
-  int dz[kUpVZ];
-  if constexpr (PAIR) {
-    const int zs = iz[0] - (iz[0] & 1);  // down to even (iz[0] >= -1)
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy) {
-      const int yy = iy + cy;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const int zz = zs + 2 * m;  // even: the pair lies wholly inside or outside [0, Nc)
-        const bool ok = yy >= 0 && yy < Nc && zz >= 0 && zz < Nc;
-        poff[cy][m] = ok ? (unsigned)(yy * Nc + zz) * 2u : dead;
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kUpVZ; ++j) dz[j] = iz[j] - zs;
-  }
-  // coarse values as loaded (FP64 coarse states stay FP64)
-  using CE = typename std::conditional<sizeof(CS) == 8, double, float>::type;
-  // loads of coarse plane c at the thread's sites, and their (z, y) lerps
-  auto load_plane = [&](int c, CE (&e)[2][kUpVZ][2]) {
-    const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, c, Nc, pbytes);
-    if constexpr (PAIR) {
-#pragma unroll
-      for (int cy = 0; cy < 2; ++cy) {
-        float v[6];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          const unsigned wd = __builtin_amdgcn_raw_buffer_load_b32(rp, (int)poff[cy][m], 0, 0);
-          v[2 * m] = __uint_as_float(wd << 16);
-          v[2 * m + 1] = __uint_as_float(wd & 0xffff0000u);
-        }
-#pragma unroll
-        for (int j = 0; j < kUpVZ; ++j)
-#pragma unroll
-          for (int cz = 0; cz < 2; ++cz) {
-            const int k = dz[j] + cz;
-            float r = v[0];
-#pragma unroll
-            for (int q = 1; q < 6; ++q) r = k == q ? v[q] : r;
-            e[cy][j][cz] = r;
-          }
-      }
-    } else {
-#pragma unroll
-      for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-        for (int j = 0; j < kUpVZ; ++j)
-#pragma unroll
-          for (int cz = 0; cz < 2; ++cz) {
-            CE q[1];
-            bload<CS, 1, CE>(rp, off[cy][j][cz], q);
-            e[cy][j][cz] = q[0];
-          }
-    }
-  };
-  auto interp = [&](const CE (&e)[2][kUpVZ][2], double (&o)[kUpVZ]) {
-    double v[2][kUpVZ];
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int j = 0; j < kUpVZ; ++j)
-        v[cy][j] = wz1[j] * (double)e[cy][j][0] + wz[j] * (double)e[cy][j][1];
-#pragma unroll
-    for (int j = 0; j < kUpVZ; ++j) o[j] = wy1 * v[0][j] + wy * v[1][j];
-  };
-  // A window of G + 1 consecutive coarse planes, base .. base + G (w[k] is
-  // plane base + k), advanced G planes at a time: the loads of the G new
-  // planes are issued together, one memory round trip per G coarse planes.
-  // Fine planes are emitted in order; fine plane i lies between coarse
-  // planes s_i0[i] and s_i0[i] + 1 (non-decreasing in i; uniform).
-  constexpr int G = sizeof(CE) == 8 ? (FDTD_UP_GROUP + 1) / 2 : FDTD_UP_GROUP;
-  const bool full = z0 + kUpVZ <= Nf && (Nf % kUpVZ) == 0;
-  auto emit = [&](int i, const double (&lo)[kUpVZ], const double (&hi)[kUpVZ]) {
-    const double wx = s_w[i], wx1 = s_w1[i];
-    Pack<FS, kUpVZ> o;
-#pragma unroll
-    for (int j = 0; j < kUpVZ; ++j) {
-      const double v = wx1 * lo[j] + wx * hi[j];
-      if constexpr (sizeof(FS) == 2) o.v[j] = f32_to_bf16((float)v);
-      else o.v[j] = (FS)v;
-    }
-    FS* dst = pf + ((long long)(x0 + i) * Nf + y) * Nf + z0;
-    if (full) {
-      *reinterpret_cast<Pack<FS, kUpVZ>*>(dst) = o;
-    } else {
-#pragma unroll
-      for (int j = 0; j < kUpVZ; ++j)
-        if (z0 + j < Nf) dst[j] = o.v[j];
-    }
-  };
-  double w[G + 1][kUpVZ];
-  int base = uni(s_i0[0]);  // the block's planes: uniform
-  {
-    CE e[G + 1][2][kUpVZ][2];
-#pragma unroll
-    for (int k = 0; k <= G; ++k) load_plane(base + k, e[k]);
-#pragma unroll
-    for (int k = 0; k <= G; ++k) interp(e[k], w[k]);
-  }
-  int i = 0;
-  while (true) {
-#pragma unroll
-    for (int k = 0; k < G; ++k)
-      while (i < nx && uni(s_i0[i]) == base + k) {
-        emit(i, w[k], w[k + 1]);
-        ++i;
-      }
-    if (i >= nx) break;
-    base += G;
-#pragma unroll
-    for (int j = 0; j < kUpVZ; ++j) w[0][j] = w[G][j];
-    CE e[G][2][kUpVZ][2];
-#pragma unroll
-    for (int k = 0; k < G; ++k) load_plane(base + 1 + k, e[k]);
-#pragma unroll
-    for (int k = 0; k < G; ++k) interp(e[k], w[k + 1]);
-  }
-}
-
-// ----------------------------------------------------- parity reimposed ----
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_reimpose(S* __restrict__ psi, int N, uint32_t parity) {
-  const long long n3 = (long long)N * N * N;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (long long)gridDim.x * blockDim.x) {
-    int c[3];
-    c[2] = (int)(s % N);
-    const long long q = s / N;
-    c[1] = (int)(q % N);
-    c[0] = (int)(q / N);
-    bool neg = false, zero = false, moved = false;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const uint32_t mode = (parity >> (2 * ax)) & 3u;
-      if (mode == 0u) continue;
-      const int mir = N - 1 - c[ax];
-      if (c[ax] > mir) {
-        c[ax] = mir;
-        moved = true;
-        if (mode == 2u) neg = !neg;
-      } else if (c[ax] == mir && mode == 2u) {
-        zero = true;
-      }
-    }
-    if (zero) {
-      psi[s] = S(0);
-    } else if (moved) {
-      // the source lies in the lower half of every masked axis: never written here
-      const S v = psi[((long long)c[0] * N + c[1]) * N + c[2]];
-      if constexpr (sizeof(S) == 2) psi[s] = neg ? (uint16_t)(v ^ 0x8000u) : v;
-      else psi[s] = neg ? -v : v;
-    }
-  }
-}
-
-__global__ void k_set_state(MemberState* st, int member, double scale, long long step,
-                            int reset_bad) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    MemberState& s = st[member];
-    s.scale = scale;
-    s.step = step;
-    s.counter = 0u;
-    if (reset_bad) {
-      s.bad = 0;
-      s.bad_step = -1;
-    }
-  }
-}
-
-// -------------------------------------------------------------- adjoint ----
-// One step of the adjoint recurrence of the renormalised update
-// psi_{t+1} = s_t M psi_t,  M = I + diag(B) (c Lap - dt diag(V)):
-//   lambda_t = s_t M^T lambda_{t+1},
-//   (M^T l)_j = l_j + c (Lap w)_j - dt V_j w_j,   w = B l,
-//   G_j += lambda_{t+1,j} (-(dt/2) B_j) (s_t psi_{t,j} + psi_{t+1,j}),
-// the last line being d psi_{t+1,j} / dV_j (through A_j and B_j) times the
-// adjoint.  Streamed along x like the forward step: a work item is a chunk of
-// 256 x VZ consecutive sites of the flattened (y, z) plane and an x-range;
-// each lane keeps w of its sites for planes x - 1, x, x + 1 in registers (so
-// lambda and V come from HBM once), and forms the y / z neighbours' w from
-// loads the adjacent rows and lanes also make (served by L1 / L2).  Out-of-
-// range loads read 0 (zero ghosts).  Per site: lambda, V, psi_t, psi_{t+1}
-// and G read, lambda_t and G written.
-template <typename S, int VZ, int BT>
-__global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
-  using C = typename std::conditional<sizeof(S) == 8, double, float>::type;
-  constexpr unsigned kES = sizeof(S);
-  const int N = a.N;
-  const unsigned P = (unsigned)N * (unsigned)N, pb = P * kES;
-  const unsigned F = (unsigned)BT * VZ;
-  const int nchunk = (int)((P + F - 1) / F), nx = a.nx;
-  const C c = (C)a.c, dt = (C)a.dt, eps = (C)(0.5 * a.dt), st = (C)a.s_t;
-  const double hdt = -0.5 * a.dt, std_ = (double)st;
-  const int tid = threadIdx.x;
-  auto wof = [&](C l, C v) -> C { return l * rcp_c(C(1) + eps * v); };
-  for (int it = blockIdx.x; it < nchunk * nx; it += gridDim.x) {
-    const int ch = it % nchunk, xr = it / nchunk;
-    const int xb = (int)(((long long)xr * N) / nx), xe = (int)(((long long)(xr + 1) * N) / nx);
-    const unsigned f = (unsigned)ch * F + (unsigned)tid * VZ;
-    const bool ok = f < P;
-    const unsigned fe = ok ? f : kDeadLane;
-    const int y = ok ? (int)(f / (unsigned)N) : 0;
-    const int z0 = ok ? (int)(f - (unsigned)y * N) : 0;
-    const bool zlo = ok && z0 > 0, zhi = ok && z0 + VZ < N;
-    const unsigned off = fe * kES, offm = (fe - (unsigned)N) * kES, offp = (fe + (unsigned)N) * kES;
-    const unsigned offzm = fe * kES - kES, offzp = fe * kES + VZ * kES;
-    // w of the lane's sites on planes x - 1 (wm) and x (wc); lambda, V on x
-    C wm[VZ], wc[VZ], lc[VZ], vc[VZ];
-    {
-      C l0[VZ], v0[VZ];
-      bload<S, VZ, C>(plane_rsrc(a.lam_in, xb - 1, N, pb), off, l0);
-      bload<S, VZ, C>(plane_rsrc(a.V, xb - 1, N, pb), off, v0);
-      bload<S, VZ, C>(plane_rsrc(a.lam_in, xb, N, pb), off, lc);
-      bload<S, VZ, C>(plane_rsrc(a.V, xb, N, pb), off, vc);
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) {
-        wm[j] = wof(l0[j], v0[j]);
-        wc[j] = wof(lc[j], vc[j]);
-      }
-    }
-    for (int x = xb; x < xe; ++x) {
-      C lp[VZ], vp[VZ], lym[VZ], vym[VZ], lyp[VZ], vyp[VZ], pt[VZ], pt1[VZ];
-      C lzm[1], vzm[1], lzp[1], vzp[1];
-      const __amdgpu_buffer_rsrc_t rl1 = plane_rsrc(a.lam_in, x + 1, N, pb);
-      const __amdgpu_buffer_rsrc_t rv1 = plane_rsrc(a.V, x + 1, N, pb);
-      const __amdgpu_buffer_rsrc_t rl = plane_rsrc(a.lam_in, x, N, pb);
-      const __amdgpu_buffer_rsrc_t rv = plane_rsrc(a.V, x, N, pb);
-      bload<S, VZ, C>(rl1, off, lp);
-      bload<S, VZ, C>(rv1, off, vp);
-      bload<S, VZ, C>(rl, offm, lym);
-      bload<S, VZ, C>(rv, offm, vym);
-      bload<S, VZ, C>(rl, offp, lyp);
-      bload<S, VZ, C>(rv, offp, vyp);
-      bload<S, 1, C>(rl, offzm, lzm);
-      bload<S, 1, C>(rv, offzm, vzm);
-      bload<S, 1, C>(rl, offzp, lzp);
-      bload<S, 1, C>(rv, offzp, vzp);
-      // read once and written once: past the caches, which keep lambda and V
-      // for the neighbour re-reads
-      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t, x, N, pb), off, pt);
-      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t1, x, N, pb), off, pt1);
-      const __amdgpu_buffer_rsrc_t rg = plane_rsrc(a.G, x, N, P * 8u);
-      double gv[VZ];
-      bload<double, VZ, double, kNT>(rg, fe * 8u, gv);
-      C wp[VZ];
-      Pack<S, VZ> o;
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) wp[j] = wof(lp[j], vp[j]);
-      const C wzl = zlo ? wof(lzm[0], vzm[0]) : C(0), wzr = zhi ? wof(lzp[0], vzp[0]) : C(0);
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) {
-        const C w = wc[j];
-        const C wym = wof(lym[j], vym[j]), wyp = wof(lyp[j], vyp[j]);
-        const C wzm = j > 0 ? wc[j - 1] : wzl, wzp = j < VZ - 1 ? wc[j + 1] : wzr;
-        const C lapw = (((wm[j] - w) + (wp[j] - w)) + ((wym - w) + (wyp - w))) + ((wzm - w) + (wzp - w));
-        o.v[j] = (S)(st * (lc[j] + c * lapw - dt * vc[j] * w));
-        const C B = rcp_c(C(1) + eps * vc[j]);
-        gv[j] += (double)lc[j] * (hdt * (double)B) * (std_ * (double)pt[j] + (double)pt1[j]);
-      }
-      bstore<S, VZ, kNT>(plane_rsrc(a.lam_out, x, N, pb), off, o);
-      Pack<double, VZ> go;
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) go.v[j] = gv[j];
-      bstore<double, VZ, kNT>(rg, fe * 8u, go);
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) {
-        wm[j] = wc[j];
-        wc[j] = wp[j];
-        lc[j] = lp[j];
-        vc[j] = vp[j];
-      }
-    }
-  }
-}
-
-template <typename S>
-__global__ __launch_bounds__(kBlock) void k_adjoint_init(AdjInitArgs a) {
-  const S* __restrict__ V = static_cast<const S*>(a.V);
-  const S* __restrict__ p = static_cast<const S*>(a.psi);
-  S* __restrict__ lam = static_cast<S*>(a.lam);
-  const int N = a.N;
-  const long long P = (long long)N * N, n3 = P * N;
-  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-       s += (long long)gridDim.x * blockDim.x) {
-    const int iz = (int)(s % N);
-    const long long q = s / N;
-    const int iy = (int)(q % N);
-    const int ix = (int)(q / N);
-    const double c0 = (double)p[s];
-    auto at = [&](bool okk, long long k) -> double { return okk ? (double)p[k] : 0.0; };
-    const double lap = (((at(ix > 0, s - P) - c0) + (at(ix < N - 1, s + P) - c0)) +
-                        ((at(iy > 0, s - N) - c0) + (at(iy < N - 1, s + N) - c0))) +
-                       ((at(iz > 0, s - 1) - c0) + (at(iz < N - 1, s + 1) - c0));
-    const double hp = -a.kin_scale * lap + (double)V[s] * c0;
-    lam[s] = (S)(2.0 * (hp - a.E * c0) / a.S0);
-    a.G[s] = c0 * c0 / a.S0;
-  }
-}
-
-// Contraction of dE/dV with the analytic derivatives of the potential's
-// parameters (kinds numbered as in k_potential, which defines each V):
-//   CONST 1; HO p_d x_d^2; COULOMB -1/r; COULOMB_REG 1/a - 1/r (0 for r < a);
-//   CORNELL -1/r, r, z^2; WELLS p_d x_d^2 for the oscillator (j < 3), and for
-//   well k with e = exp(-d^2 / 2 s^2): A -e, centre c_d -A e (x_d - c_d) / s^2,
-//   width s -A e d^2 / s^3; DODECA 1 inside the solid.
-constexpr int kMaxWrt = 64;
-
-__device__ __forceinline__ double param_dv(int kind, const double* __restrict__ p, int j,
-                                           const double (&xs)[3], double r, double a, int N,
-                                           double half) {
-  switch (kind) {
-    case 0: return 1.0;
-    case 1: return p[j] * xs[j] * xs[j];
-    case 2: return -1.0 / r;
-    case 3: return (r < a) ? 0.0 : (1.0 / a - 1.0 / r);
-    case 4: return j == 0 ? -1.0 / r : (j == 1 ? r : xs[2] * xs[2]);
-    case 5: {
-      if (j < 3) return p[j] * xs[j] * xs[j];
-      const double* w = p + 3 + 5 * ((j - 3) / 5);
-      const int q = (j - 3) % 5;
-      const double dx = xs[0] - w[1], dy = xs[1] - w[2], dz = xs[2] - w[3];
-      const double d2 = dx * dx + dy * dy + dz * dz;
-      const double e = exp(-d2 / (2.0 * w[4] * w[4]));
-      if (q == 0) return -e;
-      if (q == 4) return -w[0] * e * d2 / (w[4] * w[4] * w[4]);
-      return -w[0] * e * (xs[q - 1] - w[q]) / (w[4] * w[4]);
-    }
-    case 6: return (N > 1 && dodeca_inside(xs[0] / half, xs[1] / half, xs[2] / half)) ? 1.0 : 0.0;
-    default: return 0.0;
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_param_contract(const double* __restrict__ G, int N,
-                                                           double ha, double a, int kind,
-                                                           const double* __restrict__ p,
-                                                           const int* __restrict__ wrt, int nwrt,
-                                                           double* __restrict__ partials) {
-  __shared__ double red[kBlock / 64][8];
-  const long long n3 = (long long)N * N * N;
-  const double cN = (double)(N - 1), half = 0.5 * (double)(N - 1) * a;
-  for (int k0 = 0; k0 < nwrt; k0 += 8) {
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n3;
-         s += (long long)gridDim.x * blockDim.x) {
-      const int iz = (int)(s % N);
-      const long long q = s / N;
-      const int iy = (int)(q % N);
-      const int ix = (int)(q / N);
-      const double xs[3] = {(2.0 * ix - cN) * ha, (2.0 * iy - cN) * ha, (2.0 * iz - cN) * ha};
-      const double r = sqrt(xs[0] * xs[0] + xs[1] * xs[1] + xs[2] * xs[2]);
-      const double g = G[s];
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const int k = k0 + kk;
-        if (k >= nwrt) break;
-        acc[kk] += g * param_dv(kind, p, wrt[k], xs, r, a, N, half);
-      }
-    }
-    block_sum<8>(acc, red);
-    if (threadIdx.x == 0) {
-      for (int kk = 0; kk < 8 && k0 + kk < nwrt; ++kk)
-        partials[(long long)blockIdx.x * kMaxWrt + k0 + kk] = acc[kk];
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials,
-                                                         int nblocks, int nwrt,
-                                                         double* __restrict__ out) {
-  const int k = threadIdx.x;
-  if (k < nwrt) {
-    double t = 0.0;
-    for (int b = 0; b < nblocks; ++b) t += partials[(long long)b * kMaxWrt + k];
-    out[k] = t;
-  }
-}
-
-// ----------------------------------------------------------- projection ----
-// Excited states by projection (Sec. III): psi <- psi - phi <phi|psi> /
-// <phi|phi>.  Three launches per state, no host round trip: FP64 partial sums
-// of <phi|phi> and <phi|psi> per work-group (grid-stride, fixed grid), one
-// work-group summing them in a fixed order into the coefficient (device
-// memory), then the update reading it.
-constexpr int kProjGrid = 1024;
-
-template <typename S, typename B>
-__global__ __launch_bounds__(kBlock) void k_proj_partials(const S* __restrict__ psi,
-                                                          const B* __restrict__ phi,
-                                                          long long n3, double* partials) {
-  __shared__ double red[kBlock / 64][2];
-  double pp = 0.0, pq = 0.0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3;
-       i += (long long)gridDim.x * kBlock) {
-    const double f = (double)phi[i];
-    pp += f * f;
-    pq += f * to_c<S, double>(psi[i]);
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    pp += __shfl_down(pp, o);
-    pq += __shfl_down(pq, o);
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    red[w][0] = pp;
-    red[w][1] = pq;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int k = 0; k < kBlock / 64; ++k) {
-      a += red[k][0];
-      b += red[k][1];
-    }
-    partials[2 * blockIdx.x] = a;
-    partials[2 * blockIdx.x + 1] = b;
-  }
-}
-
-__global__ void k_proj_coef(const double* __restrict__ partials, int nblocks, double* coef) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double pp = 0.0, pq = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-      pp += partials[2 * b];
-      pq += partials[2 * b + 1];
-    }
-    coef[0] = pp > 0.0 ? pq / pp : 0.0;
-  }
-}
-
-template <typename S, typename B>
-__global__ __launch_bounds__(kBlock) void k_proj_update(S* __restrict__ psi,
-                                                        const B* __restrict__ phi, long long n3,
-                                                        const double* __restrict__ coef) {
-  const double c = coef[0];
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n3;
-       i += (long long)gridDim.x * kBlock) {
-    if constexpr (sizeof(S) == 8) {
-      psi[i] = psi[i] - c * (double)phi[i];
-    } else {
-      const float v = to_c<S, float>(psi[i]) - (float)c * (float)phi[i];
-      psi[i] = from_c<S, float>(v);
-    }
-  }
-}
-
-// ------------------------------------------------------------- dispatch ----
-int grid_for(long long n) {
-  long long g = (n + kBlock - 1) / kBlock;
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  return (int)g;
-}
-
 // Launch shapes holding more than 32 bytes of arithmetic-type state per
 // lane and plane (8 FP32 or 4 FP64 sites) spill registers and are not
 // instantiated; the scalar-lane fallback (VZ = 1) and the reduction-only
@@ -2391,191 +1310,6 @@ hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int gr
     case kBF16: return step_dt<kBF16>(vz, depth, ry, update, grid, bt, fv, wt, a, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-hipError_t launch_potential(int vdtype, void* V, int N, double ha, double a, int kind,
-                            const double* p_dev, int np, hipStream_t s) {
-  const int g = grid_for((long long)N * N * N);
-  if (vdtype == kF64)
-    hipLaunchKernelGGL(k_potential<double>, dim3(g), dim3(kBlock), 0, s, (double*)V, N, ha, a,
-                       kind, p_dev, np);
-  else
-    hipLaunchKernelGGL(k_potential<float>, dim3(g), dim3(kBlock), 0, s, (float*)V, N, ha, a, kind,
-                       p_dev, np);
-  return hipGetLastError();
-}
-
-hipError_t launch_initial(int dtype, void* psi, int N, uint64_t seed, uint32_t member, int kind,
-                          uint32_t parity, hipStream_t s) {
-  const int g = grid_for((long long)N * N * N);
-  switch (dtype) {
-    case kF64: hipLaunchKernelGGL(k_initial<double>, dim3(g), dim3(kBlock), 0, s, (double*)psi, N, seed, member, kind, parity); break;
-    case kF32: hipLaunchKernelGGL(k_initial<float>, dim3(g), dim3(kBlock), 0, s, (float*)psi, N, seed, member, kind, parity); break;
-    case kBF16: hipLaunchKernelGGL(k_initial<uint16_t>, dim3(g), dim3(kBlock), 0, s, (uint16_t*)psi, N, seed, member, kind, parity); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-namespace {
-template <typename SS>
-hipError_t convert_to(const SS* src, int ddtype, void* dst, long long n, double scale,
-                      hipStream_t s) {
-  const int g = grid_for(n);
-  switch (ddtype) {
-    case kF64: hipLaunchKernelGGL((k_convert<SS, double>), dim3(g), dim3(kBlock), 0, s, src, (double*)dst, n, scale); break;
-    case kF32: hipLaunchKernelGGL((k_convert<SS, float>), dim3(g), dim3(kBlock), 0, s, src, (float*)dst, n, scale); break;
-    case kBF16: hipLaunchKernelGGL((k_convert<SS, uint16_t>), dim3(g), dim3(kBlock), 0, s, src, (uint16_t*)dst, n, scale); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-template <typename CS>
-hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, void* pf, int Nf,
-                       double haf, hipStream_t s) {
-  (void)hac;
-  // (y, z-vector) columns of the fine lattice x fine x-ranges of kUpXC planes
-  const long long cols = (long long)Nf * ((Nf + kUpVZ - 1) / kUpVZ);
-  const dim3 g((unsigned)((cols + kBlock - 1) / kBlock), (unsigned)((Nf + kUpXC - 1) / kUpXC));
-  if constexpr (sizeof(CS) == 2) {
-    if (Nc % 2 == 0 && Nf >= 2 * Nc) {
-      switch (fdtype) {
-        case kF64: hipLaunchKernelGGL((k_upsample<CS, double, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
-        case kF32: hipLaunchKernelGGL((k_upsample<CS, float, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
-        case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
-        default: return hipErrorInvalidValue;
-      }
-      return hipGetLastError();
-    }
-  }
-  switch (fdtype) {
-    case kF64: hipLaunchKernelGGL((k_upsample<CS, double, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
-    case kF32: hipLaunchKernelGGL((k_upsample<CS, float, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
-    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-}  // namespace
-
-hipError_t launch_convert(int sdtype, const void* src, int ddtype, void* dst, long long n,
-                          double scale, hipStream_t s) {
-  switch (sdtype) {
-    case kF64: return convert_to((const double*)src, ddtype, dst, n, scale, s);
-    case kF32: return convert_to((const float*)src, ddtype, dst, n, scale, s);
-    case kBF16: return convert_to((const uint16_t*)src, ddtype, dst, n, scale, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, double ac, int fdtype,
-                           void* pf, int Nf, double haf, hipStream_t s) {
-  switch (cdtype) {
-    case kF64: return upsample_to((const double*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
-    case kF32: return upsample_to((const float*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
-    case kBF16: return upsample_to((const uint16_t*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_project(int dtype, void* psi, const void* phi, long long n3, double* partials,
-                          double* coef, hipStream_t s) {
-  const int g = kProjGrid;
-  switch (dtype) {
-    case kF64:
-      hipLaunchKernelGGL((k_proj_partials<double, double>), dim3(g), dim3(kBlock), 0, s,
-                         (const double*)psi, (const double*)phi, n3, partials);
-      break;
-    case kF32:
-      hipLaunchKernelGGL((k_proj_partials<float, float>), dim3(g), dim3(kBlock), 0, s,
-                         (const float*)psi, (const float*)phi, n3, partials);
-      break;
-    case kBF16:
-      hipLaunchKernelGGL((k_proj_partials<uint16_t, float>), dim3(g), dim3(kBlock), 0, s,
-                         (const uint16_t*)psi, (const float*)phi, n3, partials);
-      break;
-    default: return hipErrorInvalidValue;
-  }
-  hipLaunchKernelGGL(k_proj_coef, dim3(1), dim3(64), 0, s, (const double*)partials, g, coef);
-  switch (dtype) {
-    case kF64:
-      hipLaunchKernelGGL((k_proj_update<double, double>), dim3(g), dim3(kBlock), 0, s,
-                         (double*)psi, (const double*)phi, n3, (const double*)coef);
-      break;
-    case kF32:
-      hipLaunchKernelGGL((k_proj_update<float, float>), dim3(g), dim3(kBlock), 0, s,
-                         (float*)psi, (const float*)phi, n3, (const double*)coef);
-      break;
-    default:
-      hipLaunchKernelGGL((k_proj_update<uint16_t, float>), dim3(g), dim3(kBlock), 0, s,
-                         (uint16_t*)psi, (const float*)phi, n3, (const double*)coef);
-  }
-  return hipGetLastError();
-}
-
-int project_partials_doubles() { return 2 * kProjGrid; }
-
-hipError_t launch_reimpose(int dtype, void* psi, int N, uint32_t parity, hipStream_t s) {
-  const int g = grid_for((long long)N * N * N);
-  switch (dtype) {
-    case kF64: hipLaunchKernelGGL(k_reimpose<double>, dim3(g), dim3(kBlock), 0, s, (double*)psi, N, parity); break;
-    case kF32: hipLaunchKernelGGL(k_reimpose<float>, dim3(g), dim3(kBlock), 0, s, (float*)psi, N, parity); break;
-    case kBF16: hipLaunchKernelGGL(k_reimpose<uint16_t>, dim3(g), dim3(kBlock), 0, s, (uint16_t*)psi, N, parity); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_set_state(MemberState* st, int member, double scale, long long step,
-                            int reset_bad, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(64), 0, s, st, member, scale, step, reset_bad);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s) {
-  if (a.N < 1 || (dtype != kF64 && dtype != kF32)) return hipErrorInvalidValue;
-  // VZ sites per lane when N allows (a lane's vector stays within a z-row),
-  // else one
-  const int vz = dtype == kF64 ? 2 : 4;
-  const bool vec = a.N % vz == 0;
-  const long long P = (long long)a.N * a.N, F = (long long)kBlock * (vec ? vz : 1);
-  const long long nchunk = (P + F - 1) / F;
-  AdjArgs b = a;
-  // x split into ranges for about 2048 work items (measured at 256^3 FP32:
-  // 256 to 4096 items and 256 to 1024 lanes per work-group within 3%)
-  b.nx = (int)std::min<long long>(a.N, std::max<long long>(1, (2048 + nchunk - 1) / nchunk));
-  const int g = (int)std::min<long long>(nchunk * b.nx, 1 << 20);
-  if (dtype == kF64) {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, 2, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<double, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-  } else {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, 4, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<float, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_init(int dtype, const AdjInitArgs& a, hipStream_t s) {
-  const int g = grid_for((long long)a.N * a.N * a.N);
-  if (dtype == kF64) hipLaunchKernelGGL(k_adjoint_init<double>, dim3(g), dim3(kBlock), 0, s, a);
-  else if (dtype == kF32) hipLaunchKernelGGL(k_adjoint_init<float>, dim3(g), dim3(kBlock), 0, s, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
-
-hipError_t launch_param_contract(const double* G, int N, double ha, double a, int kind,
-                                 const double* p_dev, int np, const int* wrt_dev, int nwrt,
-                                 double* partials, int nblocks, double* out_dev, hipStream_t s) {
-  if (nwrt < 1 || nwrt > kMaxWrt || nblocks < 1 || kind < 0 || kind > 6 || np < 1)
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_param_contract, dim3(nblocks), dim3(kBlock), 0, s, G, N, ha, a, kind, p_dev,
-                     wrt_dev, nwrt, partials);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kMaxWrt), 0, s, partials, nblocks, nwrt,
-                     out_dev);
-  return hipGetLastError();
 }
 
 }  // namespace fdtd

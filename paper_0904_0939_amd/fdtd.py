@@ -25,6 +25,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENOTREADY, ENONFINITE = range(7)
 F64, F32, BF16 = 0, 1, 2
 POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS, POT_DODECA = range(7)
 INIT_UNIFORM, INIT_GAUSS, INIT_USER = 0, 1, 2
+EVOLVE_ASYNC = 1
 
 
 def parity(px: int = 0, py: int = 0, pz: int = 0) -> int:
@@ -51,7 +52,7 @@ class fdtd_evolve_opts(C.Structure):
     _fields_ = [("max_steps", C.c_int64), ("renorm_every", C.c_int32),
                 ("check_every", C.c_int32), ("reimpose_parity_every", C.c_int32),
                 ("use_graph", C.c_int32), ("rel_tol", C.c_double),
-                ("project_every", C.c_int32), ("reserved", C.c_int32)]
+                ("project_every", C.c_int32), ("flags", C.c_int32)]
 
 
 class fdtd_tuning(C.Structure):
@@ -62,6 +63,14 @@ class fdtd_tuning(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class fdtd_counters(C.Structure):
+    _fields_ = [("graph_captures", C.c_int64), ("graph_replays", C.c_int64),
+                ("allocations", C.c_int64), ("reserved", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 class FdtdError(RuntimeError):
@@ -88,6 +97,9 @@ _SIGS = {
     "fdtd_history": [_P, C.c_int32, C.POINTER(fdtd_obs), C.c_int64, C.POINTER(C.c_int64)],
     "fdtd_get_psi": [_P, C.c_int32, _P, C.c_int32, C.c_int32],
     "fdtd_get_state": [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_int64)],
+    "fdtd_checkpoint_size": [_P, C.c_int32, C.POINTER(C.c_size_t)],
+    "fdtd_checkpoint_save": [_P, C.c_int32, _P, C.c_int32],
+    "fdtd_checkpoint_load": [_P, C.c_int32, _P, C.c_int32],
     "fdtd_upsample": [_P, C.c_int32, _P, C.c_int32],
     "fdtd_energy_grad": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
                          C.POINTER(C.c_int32), C.c_int32, _P, C.POINTER(C.c_double),
@@ -99,6 +111,7 @@ _SIGS = {
     "fdtd_tune_cache_load": [C.c_char_p],
     "fdtd_synchronize": [_P],
     "fdtd_info": [_P, C.POINTER(C.c_int32), C.POINTER(_P)],
+    "fdtd_get_counters": [_P, C.POINTER(fdtd_counters)],
 }
 
 _lib = None
@@ -218,6 +231,20 @@ def fdtd_get_state(h, member: int, ptr: int, on_device: int) -> int:
     return st.value
 
 
+def fdtd_checkpoint_size(h, member: int) -> int:
+    n = C.c_size_t()
+    _call("fdtd_checkpoint_size", h, member, C.byref(n))
+    return n.value
+
+
+def fdtd_checkpoint_save(h, member: int, ptr: int, on_device: int):
+    _call("fdtd_checkpoint_save", h, member, ptr, on_device)
+
+
+def fdtd_checkpoint_load(h, member: int, ptr: int, on_device: int):
+    _call("fdtd_checkpoint_load", h, member, ptr, on_device)
+
+
 def fdtd_upsample(coarse, cm: int, fine, fm: int):
     _call("fdtd_upsample", coarse, cm, fine, fm)
 
@@ -260,6 +287,12 @@ def fdtd_tune_cache_load(path: str):
 
 def fdtd_synchronize(h):
     _call("fdtd_synchronize", h)
+
+
+def fdtd_get_counters(h) -> dict:
+    c = fdtd_counters()
+    _call("fdtd_get_counters", h, C.byref(c))
+    return c.as_dict()
 
 
 def fdtd_info(h):

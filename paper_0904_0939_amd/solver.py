@@ -55,11 +55,15 @@ class _Handle:
             pass
 
     def evolve(self, steps: int, renorm_every: int = 1, check_every: int = 0, rel_tol: float = 0.0,
-               use_graph: bool = True, reimpose_parity_every: int = 0, project_every: int = 0):
+               use_graph: bool = True, reimpose_parity_every: int = 0, project_every: int = 0,
+               async_launch: bool = False):
         o = F.fdtd_evolve_opts(int(steps), int(renorm_every), int(check_every),
                                int(reimpose_parity_every), 1 if use_graph else 0, float(rel_tol),
-                               int(project_every), 0)
+                               int(project_every), F.EVOLVE_ASYNC if async_launch else 0)
         return F.fdtd_evolve(self.h, o)
+
+    def counters(self) -> Dict:
+        return F.fdtd_get_counters(self.h)
 
     def set_projection_states(self, states, member: int = 0):
         """Keep `states` (a sequence of N^3 arrays or tensors, or one stacked
@@ -126,6 +130,17 @@ class _Handle:
         out = np.empty((N, N, N), dtype={F.F64: np.float64, F.F32: np.float32, F.BF16: np.uint16}[code])
         F.fdtd_get_state(self.h, member, out.ctypes.data, 0)
         return out
+
+    def checkpoint(self, member: int = 0) -> np.ndarray:
+        """A checkpoint record of the member (header + stored state) in host memory."""
+        buf = np.empty(F.fdtd_checkpoint_size(self.h, member), dtype=np.uint8)
+        F.fdtd_checkpoint_save(self.h, member, buf.ctypes.data, 0)
+        return buf
+
+    def restore(self, record: np.ndarray, member: int = 0):
+        """Continue from a record written by checkpoint() (same N, dtype, L, dt)."""
+        a = np.ascontiguousarray(record, dtype=np.uint8)
+        F.fdtd_checkpoint_load(self.h, member, a.ctypes.data, 0)
 
     def psi_tensor(self, member: int = 0, dtype=torch.float32) -> torch.Tensor:
         N = self.cfgs[member].n
@@ -249,7 +264,8 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
 
 class EnergyOfPotential(torch.autograd.Function):
     """E[psi_T](V) for a Solver whose state is the fixed start psi_0: forward
-    sets V, runs the adjoint driver once and keeps dE/dV; backward returns
+    sets V and, when V needs a gradient, runs the adjoint driver once and
+    keeps dE/dV (otherwise it only relaxes and reads E); backward returns
     grad_output * dE/dV, so torch's autograd can chain through any V(theta)."""
 
     @staticmethod
@@ -257,6 +273,11 @@ class EnergyOfPotential(torch.autograd.Function):
                 checkpoint_every: int):
         solver.set_potential_array(V.detach())
         solver.set_initial_array(psi0)
+        if not ctx.needs_input_grad[0]:
+            solver.evolve(steps, renorm_every=1, use_graph=False)
+            E = solver.observables()[0]["energy"]
+            ctx.save_for_backward(None)
+            return torch.tensor(E, dtype=torch.float64, device=V.device)
         E, _, G = solver.energy_grad(steps, checkpoint_every, want_field=True)
         ctx.save_for_backward(G)
         return torch.tensor(E, dtype=torch.float64, device=V.device)

@@ -286,3 +286,58 @@ def test_tune_cache_file_round_trip_and_errors(tmp_path):
     empty.write_text("")
     F.fdtd_tune_cache_load(str(empty))
     assert saved() == []
+
+
+def test_evolve_flags_are_validated_before_any_device_work():
+    h = F.fdtd_create(cfg())
+    try:
+        bad = F.fdtd_evolve_opts(10, 1, 0, 0, 0, 0.0, 0, 2)  # unknown flag
+        assert status_of("fdtd_evolve", h, C.byref(bad), None, None) == F.EINVAL
+        bad = F.fdtd_evolve_opts(10, 1, 5, 0, 0, 0.0, 0, F.EVOLVE_ASYNC)  # async + check
+        assert status_of("fdtd_evolve", h, C.byref(bad), None, None) == F.EINVAL
+        assert "ASYNC" in F.fdtd_last_error()
+        ok = F.fdtd_evolve_opts(10, 1, 0, 0, 1, 0.0, 0, F.EVOLVE_ASYNC)
+        assert status_of("fdtd_evolve", h, C.byref(ok), None, None) == F.ENOTREADY
+    finally:
+        F.fdtd_destroy(h)
+
+
+def test_counters_start_at_zero():
+    h = F.fdtd_create(cfg())
+    try:
+        assert F.fdtd_get_counters(h) == {"graph_captures": 0, "graph_replays": 0, "allocations": 0}
+        assert status_of("fdtd_get_counters", h, None) == F.EINVAL
+        assert status_of("fdtd_get_counters", None, C.byref(F.fdtd_counters())) == F.EINVAL
+    finally:
+        F.fdtd_destroy(h)
+
+
+def _header(magic=0x314B435044544446, version=1, dtype=F.F32, n=16, step=5, scale=0.5,
+            parity=0, L=8.0, dt=None):
+    import struct
+
+    a = L / n
+    dt = 0.125 * a * a if dt is None else dt
+    return struct.pack("<QiiqqdIIdd16x", magic, version, dtype, n, step, scale, parity, 0, L, dt)
+
+
+def test_checkpoint_record_size_and_header_checks_without_device():
+    """Record = 80-byte header + the stored state; a load checks the header
+    (magic, version, dtype, N, L, dt, step, scale, parity) before it touches
+    the device."""
+    h = F.fdtd_create(cfg(N=16, dtype=F.F32))
+    try:
+        assert F.fdtd_checkpoint_size(h, 0) == 80 + 4 * 16**3
+        assert status_of("fdtd_checkpoint_size", h, 1, C.byref(C.c_size_t())) == F.EINVAL
+        assert status_of("fdtd_checkpoint_save", h, 0, C.c_void_p(64), 0) == F.ENOTREADY
+        for hd in (_header(magic=1), _header(version=2), _header(dtype=F.F64), _header(n=15),
+                   _header(L=8.5), _header(dt=1e-5), _header(step=-1), _header(scale=0.0),
+                   _header(scale=float("inf")), _header(parity=1 << 6)):
+            buf = C.create_string_buffer(hd + bytes(4 * 16**3))
+            assert status_of("fdtd_checkpoint_load", h, 0, buf, 0) == F.EINVAL
+        good = C.create_string_buffer(_header() + bytes(4 * 16**3))
+        # a valid record gets as far as the device
+        assert status_of("fdtd_checkpoint_load", h, 0, good, 0) == F.EHIP
+        assert status_of("fdtd_checkpoint_load", h, 0, None, 0) == F.EINVAL
+    finally:
+        F.fdtd_destroy(h)

@@ -191,7 +191,11 @@ def test_gradient_256_adjoint_vs_fd_and_hellmann_feynman():
     scale = np.abs(fd).max()
     say("adjoint", grad)
     say("fd     ", fd)
-    assert np.abs(grad - fd).max() < 1e-4 * scale
+    rel = np.abs(grad - fd) / np.abs(fd)
+    say("rel    ", rel)
+    # 1e-4 relative per component; a component below 1e-3 of the largest is
+    # held to 1e-4 of that floor (1e-7 of the largest)
+    assert np.all(np.abs(grad - fd) <= 1e-4 * np.maximum(np.abs(fd), 1e-3 * scale))
     # Hellmann-Feynman: sum psi^2 dV/dtheta / sum psi^2 on the final state
     hf = np.array([float(np.sum(psiT * psiT * orc.wells_dv(p, 256, lat.L, j)) / np.sum(psiT * psiT))
                    for j in wrt])

@@ -11,9 +11,16 @@ lattice must give instead (the exact level it approximates) and says so:
     odd level converges to -0.055451 (0.19% from -1/18), the paper prints
     -0.055360;
   * dodecahedron (regular solid; the printed vertex list has one family with
-    two coordinates exchanged): every printed level lies above the converged
-    lattice level (-99.78 vs -99.857, -99.55 vs -99.710 on 128^3; -99.97
-    vs -99.991 on 512^3), as unconverged energies do; see the test."""
+    two coordinates exchanged): NOT reproduced.  The lattice levels are
+    -99.857 / -99.710 on 128^3 and -99.991 on 512^3; the paper prints
+    -99.78 / -99.55 / -99.97.  A run from noise stopped by the paper's own
+    rule (binding energy changing by less than a part in 10^6 per 100
+    steps) ends within a few thousandths of the converged level, so the
+    stop rule does not account for the gap at 128^3.  The tests check what
+    the lattice must satisfy instead: the stop rule's energy against the
+    converged level, and the inverse-square scaling of the level above the
+    well bottom between the 128^3 and 512^3 solids (same spacing, sides
+    127 a and 511 a)."""
 import json
 import os
 import sys
@@ -96,27 +103,62 @@ def test_coulomb_multires_to_1024():
     assert abs(e - g["E0"]) < 1e-4
 
 
-@pytest.mark.parametrize("key,levels", [("dodecahedron_128", (32, 64, 128)),
-                                        ("dodecahedron_512", (128, 256, 512))])
-def test_dodecahedron_levels_lie_below_the_printed_ones(key, levels):
-    """The energy of any state is an upper bound of the lattice ground state
-    (and, odd in z, of the first odd level), and relaxation approaches it
-    from above.  With V = -100 inside, a convergence test relative to |E|
-    ~ 100 stops long before the ~0.2 binding above the well bottom has
-    settled, which is how the printed values read: each lies above the
-    converged lattice level, by less than 0.25."""
-    g = GOLD[key]
-    L = g["N"] * g["a"]
-    args = dict(dt_over_a2=g["dt"] / g["a"] ** 2, rel_tol=(1e-9,), max_steps=(60000,))
-    s, log = multires(levels, L, F.POT_DODECA, [-100.0], ["f32"] * 3, seed=14, **args)
-    e0 = s.observables()[0]["energy"]
+def _stop_rule_run(g, parity, seed=14):
+    """128^3 from noise, no multi-resolution, FP32 with FP64 reductions:
+    stopped by the paper's rule (check every 100 steps, binding energy
+    changed by at most 1e-6 of itself), then carried on to a change below
+    1e-9 of itself (the converged level, to about 1e-5)."""
+    from paper_0904_0939_amd.solver import Solver
+
+    s = Solver(g["N"], g["N"] * g["a"], dt=g["dt"], dtype="f32")
+    s.set_potential(F.POT_DODECA, [-100.0])
+    s.set_initial(seed, parity=parity)
+    done, conv = s.evolve(400000, check_every=100, rel_tol=1e-6)
+    e_stop = s.observables()[0]["binding"]
+    more, conv2 = s.evolve(400000, check_every=100, rel_tol=1e-9)
+    e_conv = s.observables()[0]["binding"]
     s.close()
-    say(f"{key}: E0 = {e0:.5f} (paper {g['E0']}) {log}")
-    assert -100.0 < e0 < g["E0"] and g["E0"] - e0 < 0.25
-    if "E1" in g:
-        s1, log1 = multires(levels, L, F.POT_DODECA, [-100.0], ["f32"] * 3, seed=14,
-                            parity=W.parity_word(z=2), **args)
-        e1 = s1.observables()[0]["energy"]
-        s1.close()
-        say(f"  E1 = {e1:.5f} (A_z start; paper {g['E1']})")
-        assert e0 < e1 < g["E1"] and g["E1"] - e1 < 0.25
+    return done, conv, e_stop, done + more, conv2, e_conv
+
+
+def test_dodecahedron_128_with_the_papers_stop_rule():
+    """The paper's 128^3 run (a = 0.1, dt = 0.001) stopped by its own
+    criterion.  Relaxation approaches a level from above, and the stop rule
+    leaves E - E_level of about 1e-4 / (2 gap x 0.1) ~ 3e-3 for a gap of
+    0.15: the stop energy lies above the converged level by less than 0.01.
+    The printed -99.78 / -99.55 are not reproduced (logged)."""
+    g = GOLD["dodecahedron_128"]
+    conv = {}
+    for name, par, printed in (("E0", 0, g["E0"]), ("E1", W.parity_word(z=2), g["E1"])):
+        n1, c1, e_stop, n2, c2, e_conv = _stop_rule_run(g, par)
+        say(f"dodecahedron 128^3 {name}: stop rule at step {n1}: {e_stop:.6f}; converged at "
+            f"step {n2}: {e_conv:.6f}; paper {printed} (not reproduced)")
+        assert c1 and c2
+        assert -100.0 < e_conv <= e_stop + 1e-5
+        assert e_stop - e_conv < 0.01
+        conv[name] = e_conv
+    # the odd start converges to a level above the ground state
+    assert conv["E0"] < conv["E1"]
+
+
+def test_dodecahedron_level_scales_with_the_inverse_square_of_the_size():
+    """The solid spans the lattice (u = -1 at the first site, 1 at the last),
+    so at one spacing a the 512^3 solid is (511/127) times the 128^3 one.
+    For a well this deep (penetration 1/sqrt(200) ~ 0.07 against inradii of
+    5.4 and 21.7) the level above the bottom, E + 100, scales as the inverse
+    square of the size to within a few per cent.  Both lattices: FP32
+    multi-resolution chains converged to 1e-9 per 100 steps."""
+    out = {}
+    for key, levels in (("dodecahedron_128", (32, 64, 128)), ("dodecahedron_512", (128, 256, 512))):
+        g = GOLD[key]
+        L = g["N"] * g["a"]
+        s, log = multires(levels, L, F.POT_DODECA, [-100.0], ["f32"] * 3, seed=14,
+                          dt_over_a2=g["dt"] / g["a"] ** 2, rel_tol=(1e-9,),
+                          max_steps=(60000,))
+        out[key] = s.observables()[0]["energy"]
+        s.close()
+        say(f"{key}: E0 = {out[key]:.6f} (paper {g['E0']}, not reproduced) {log}")
+    ratio = (out["dodecahedron_512"] + 100.0) / (out["dodecahedron_128"] + 100.0)
+    expect = (127.0 / 511.0) ** 2
+    say(f"(E + 100) ratio 512 / 128: {ratio:.5f}; inverse square of the size {expect:.5f}")
+    assert abs(ratio / expect - 1.0) < 0.05
