@@ -343,10 +343,29 @@ fdtd_status fdtd_upsample(fdtd_t coarse, int32_t coarse_member, fdtd_t fine, int
  *             entry: oscillator frequencies, well amplitudes, centres and
  *             widths);
  *   energy    E after `steps` steps.
- * The handle's state is advanced by `steps` steps, as fdtd_evolve would. */
+ * The handle's state is advanced by `steps` steps, as fdtd_evolve would.
+ * Device memory: the workspace bound by fdtd_bind_grad_workspace (FDTD_ENOMEM
+ * if it is smaller than fdtd_grad_workspace_size), else a buffer the library
+ * allocates on the first call and keeps for later calls (re-allocated only
+ * when a call needs more).  On F32 lattices dE/dV accumulates in FP32 within
+ * each checkpoint segment and in FP64 across segments. */
 fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,
                              const double* theta, int32_t ntheta, const int32_t* wrt,
                              int32_t nwrt, void* dE_dV, double* dE_dtheta, double* energy);
+
+/* Device bytes fdtd_energy_grad needs on this single-lattice handle for
+ * `steps` steps with checkpoints every `checkpoint_every`: ceil(steps / k)
+ * checkpoints and min(k, steps) + 1 recomputed states of N^3 storage values,
+ * two adjoint fields, the FP64 dE/dV accumulator (and, on F32 lattices, its
+ * FP32 segment accumulator), plus descriptors and 512 KiB of scratch. */
+fdtd_status fdtd_grad_workspace_size(fdtd_t h, int32_t steps, int32_t checkpoint_every,
+                                     size_t* bytes);
+
+/* Use caller-owned device memory (e.g. a torch tensor; 256-byte aligned, kept
+ * alive until fdtd_destroy or the next bind) for fdtd_energy_grad instead of a
+ * library allocation; a buffer the library had allocated is freed.  dev_ptr
+ * NULL unbinds (later calls allocate again). */
+fdtd_status fdtd_bind_grad_workspace(fdtd_t h, void* dev_ptr, size_t bytes);
 
 /* ---- launch shape -----------------------------------------------------------*/
 

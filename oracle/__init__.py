@@ -19,7 +19,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FDTD_ORACLE_LIB: load another build of the same source (the sanitizer build)
+_LIB_PATH = os.environ.get("FDTD_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 POT_CONST, POT_HO, POT_COULOMB, POT_COULOMB_REG, POT_CORNELL, POT_WELLS, POT_DODECA = range(7)
@@ -37,9 +38,9 @@ def parity_word(x: int = 0, y: int = 0, z: int = 0) -> int:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or (
+        if not os.environ.get("FDTD_ORACLE_LIB") and (not os.path.exists(_LIB_PATH) or (
             os.path.getmtime(_LIB_PATH) < os.path.getmtime(os.path.join(_HERE, "fdtd_oracle.c"))
-        ):
+        )):
             from . import build as _b
 
             _b.build()

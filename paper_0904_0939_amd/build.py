@@ -61,5 +61,45 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     return LIB
 
 
+SANITIZE_LIB = os.path.join(HERE, "_build", "sanitize", "libfdtd.so")
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime a sanitizer build needs preloaded."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    out = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], check=True,
+                         capture_output=True, text=True).stdout.strip()
+    return out
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The host runtime built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host pass only), linked with the regular kernel objects into
+    _build/sanitize/libfdtd.so.  For CPU checks of the host code: load it
+    with FDTD_LIB_PATH and asan_runtime() preloaded."""
+    objdir = os.path.join(HERE, "_build")
+    if not all(os.path.exists(os.path.join(objdir, s + ".o")) for s in SOURCES[:-1]):
+        build(verbose)
+    sdir = os.path.dirname(SANITIZE_LIB)
+    os.makedirs(sdir, exist_ok=True)
+    obj = os.path.join(sdir, "fdtd_runtime.cpp.o")
+    cmd = [hipcc(), "-O1", "-g", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
+           "-I", os.path.join(ROOT, "include"), "-x", "hip", "-c",
+           os.path.join(CSRC, "fdtd_runtime.cpp"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    objs = [os.path.join(objdir, s + ".o") for s in SOURCES[:-1]] + [obj]
+    subprocess.run([hipcc(), "-shared", f"--offload-arch={ARCH}", *objs, "-o", SANITIZE_LIB + ".tmp"],
+                   check=True)
+    os.replace(SANITIZE_LIB + ".tmp", SANITIZE_LIB)
+    return SANITIZE_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

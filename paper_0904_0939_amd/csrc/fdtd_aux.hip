@@ -163,8 +163,8 @@ __device__ __forceinline__ double fetch_c(const CS* __restrict__ pc, int N, int 
 // a plane's two z lerps and one y lerp).  The fine coordinate of an axis maps
 // into coarse index space as ((2 j - (Nf - 1)) haf) / ac + (Nc - 1) / 2; the
 // plane weights of the block's x-range are formed once, in LDS.
-constexpr int kUpVZ = 4;   // fine z sites per thread
-constexpr int kUpXC = 32;  // fine planes per thread
+constexpr int kUpVZ = kUpSitesZ;  // fine z sites per thread
+constexpr int kUpXC = kUpPlanes;  // fine planes per thread (and per work-group)
 
 // Fine index j of an axis -> lower coarse index i0 and the weights of coarse
 // sites i0 (wlo) and i0 + 1 (whi).  The map is evaluated at the
@@ -190,6 +190,12 @@ __device__ __forceinline__ void up_weight(int j, int Nf, int Nc, double cNf, dou
   }
 }
 
+// Cache policy of the fine stores (kNT: past the caches; the state is read
+// back only by the next launch).
+#ifndef FDTD_UP_OUT
+#define FDTD_UP_OUT 2
+#endif
+
 // Coarse planes whose loads a thread issues together (FP64 coarse states:
 // half as many, for registers).
 #ifndef FDTD_UP_GROUP
@@ -202,27 +208,15 @@ __device__ __forceinline__ void up_weight(int j, int Nf, int Nc, double cNf, dou
 // holds an aligned pair of sites and never straddles a row), 6 loads per
 // coarse plane instead of 16 single-site loads.  Single-site loads are what
 // bound the kernel: they keep the texture addresser busy.
+// The interpolation of one thread's column (kUpVZ fine z sites of one fine
+// row, the work-group's fine planes); adds the squares of the stored values
+// to `norm`.
 template <typename CS, typename FS, bool PAIR>
-__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc, double ac,
-                                                     FS* __restrict__ pf, int Nf, double haf) {
-  static_assert(!PAIR || sizeof(CS) == 2, "pair loads are for BF16 coarse states");
-  __shared__ int s_i0[kUpXC];
-  __shared__ double s_w[kUpXC], s_w1[kUpXC];  // weights of coarse planes i0 + 1, i0
+__device__ __forceinline__ void up_columns(const CS* __restrict__ pc, int Nc, double ac,
+                                           FS* __restrict__ pf, int Nf, double haf, long long col,
+                                           int nzv, int x0, int nx, const int* s_i0,
+                                           const double* s_w, const double* s_w1, double& norm) {
   const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
-  const int x0 = blockIdx.y * kUpXC;
-  const int nx = min(kUpXC, Nf - x0);
-  if ((int)threadIdx.x < nx) {
-    int i0;
-    double wlo, whi;
-    up_weight(x0 + threadIdx.x, Nf, Nc, cNf, haf, ac, halfc, i0, wlo, whi);
-    s_i0[threadIdx.x] = i0;
-    s_w[threadIdx.x] = whi;
-    s_w1[threadIdx.x] = wlo;
-  }
-  __syncthreads();
-  const int nzv = (Nf + kUpVZ - 1) / kUpVZ;
-  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= (long long)Nf * nzv) return;
   const int y = (int)(col / nzv);
   const int z0 = (int)(col - (long long)y * nzv) * kUpVZ;
   int iy, iz[kUpVZ];
@@ -326,6 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
   // planes s_i0[i] and s_i0[i] + 1 (non-decreasing in i; uniform).
   constexpr int G = sizeof(CE) == 8 ? (FDTD_UP_GROUP + 1) / 2 : FDTD_UP_GROUP;
   const bool full = z0 + kUpVZ <= Nf && (Nf % kUpVZ) == 0;
+  const unsigned fbytes = (unsigned)Nf * (unsigned)Nf * (unsigned)sizeof(FS);
   auto emit = [&](int i, const double (&lo)[kUpVZ], const double (&hi)[kUpVZ]) {
     const double wx = s_w[i], wx1 = s_w1[i];
     Pack<FS, kUpVZ> o;
@@ -337,11 +332,20 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
     }
     FS* dst = pf + ((long long)(x0 + i) * Nf + y) * Nf + z0;
     if (full) {
-      *reinterpret_cast<Pack<FS, kUpVZ>*>(dst) = o;
+      // the fine state is read back only by the next launch: streamed past the caches
+      const __amdgpu_buffer_rsrc_t rf = plane_rsrc(pf, x0 + i, Nf, fbytes);
+      bstore<FS, kUpVZ, FDTD_UP_OUT>(rf, (unsigned)(y * Nf + z0) * (unsigned)sizeof(FS), o);
     } else {
 #pragma unroll
       for (int j = 0; j < kUpVZ; ++j)
         if (z0 + j < Nf) dst[j] = o.v[j];
+    }
+#pragma unroll
+    for (int j = 0; j < kUpVZ; ++j) {
+      double q;
+      if constexpr (sizeof(FS) == 2) q = (double)bf16_to_f32(o.v[j]);
+      else q = (double)o.v[j];
+      if (full || z0 + j < Nf) norm += q * q;
     }
   };
   double w[G + 1][kUpVZ];
@@ -370,6 +374,62 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
     for (int k = 0; k < G; ++k) load_plane(base + 1 + k, e[k]);
 #pragma unroll
     for (int k = 0; k < G; ++k) interp(e[k], w[k + 1]);
+  }
+}
+
+// The norm of the new state is reduced in the same pass (Sec. III: the state
+// is renormalised): each thread sums the squares of the values it stores, as
+// stored, in FP64; each work-group hands its sum to the last work-group (an
+// agent-scope atomic store completed before the group counts itself on the
+// member's counter, as the step kernel does), which adds the sums in work-group
+// order, sets the member's scale to 1 / sqrt(a^3 sum psi^2), writes the sum to
+// its observable record and re-arms the counter.  The counter must be 0 on
+// entry (it is after every completed step and after k_set_state).
+template <typename CS, typename FS, bool PAIR>
+__global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, int Nc, double ac,
+                                                     FS* __restrict__ pf, int Nf, double haf,
+                                                     UpNorm U) {
+  static_assert(!PAIR || sizeof(CS) == 2, "pair loads are for BF16 coarse states");
+  __shared__ int s_i0[kUpXC];
+  __shared__ double s_w[kUpXC], s_w1[kUpXC];  // weights of coarse planes i0 + 1, i0
+  __shared__ double s_red[kBlock / 64][1];
+  __shared__ int s_last;
+  const double cNf = (double)(Nf - 1), halfc = 0.5 * (double)(Nc - 1);
+  const int x0 = blockIdx.y * kUpXC;
+  const int nx = min(kUpXC, Nf - x0);
+  if ((int)threadIdx.x < nx) {
+    int i0;
+    double wlo, whi;
+    up_weight(x0 + threadIdx.x, Nf, Nc, cNf, haf, ac, halfc, i0, wlo, whi);
+    s_i0[threadIdx.x] = i0;
+    s_w[threadIdx.x] = whi;
+    s_w1[threadIdx.x] = wlo;
+  }
+  __syncthreads();
+  const int nzv = (Nf + kUpVZ - 1) / kUpVZ;
+  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double norm[1] = {0.0};
+  if (col < (long long)Nf * nzv) up_columns<CS, FS, PAIR>(pc, Nc, ac, pf, Nf, haf, col, nzv, x0, nx,
+                                                           s_i0, s_w, s_w1, norm[0]);
+  block_sum<1>(norm, s_red);
+  const unsigned nb = gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&U.partials[blockIdx.y * gridDim.x + blockIdx.x], norm[0], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the partial has reached the coherence point
+    const unsigned done = __hip_atomic_fetch_add(&U.st->counter, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = done == nb - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  double tot[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < nb; b += kBlock) tot[0] += ld_agent(U.partials[b]);
+  block_sum<1>(tot, s_red);
+  if (threadIdx.x == 0) {
+    U.obs[kS0] = tot[0];
+    U.st->scale = 1.0 / sqrt(U.a3 * tot[0]);
+    U.st->counter = 0u;
   }
 }
 
@@ -434,13 +494,18 @@ __global__ void k_set_state(MemberState* st, int member, double scale, long long
 // 256 x VZ consecutive sites of the flattened (y, z) plane and an x-range;
 // each lane keeps w of its sites for planes x - 1, x, x + 1 in registers (so
 // lambda and V come from HBM once), and forms the y / z neighbours' w from
-// loads the adjacent rows and lanes also make (served by L1 / L2).  Out-of-
-// range loads read 0 (zero ghosts).  Per site: lambda, V, psi_t, psi_{t+1}
-// and G read, lambda_t and G written.
-template <typename S, int VZ, int BT>
+// loads the adjacent rows and lanes also make (served by L1 / L2).  The loads
+// of plane x + 1 are issued before plane x is computed (one plane of
+// prefetch).  Out-of-range loads read 0 (zero ghosts).  Per site: lambda, V,
+// psi_t, psi_{t+1} and G read, lambda_t and G written.  G is of type GT: FP64
+// on the F64 path; FP32 on the F32 path, where it accumulates one checkpoint
+// segment (each increment is formed in FP64 and rounded once) and is folded
+// into the FP64 sum after the segment, so the adjoint step moves 28 bytes per
+// FP32 site instead of 36.
+template <typename S, typename GT, int VZ, int BT>
 __global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
   using C = typename std::conditional<sizeof(S) == 8, double, float>::type;
-  constexpr unsigned kES = sizeof(S);
+  constexpr unsigned kES = sizeof(S), kGS = sizeof(GT);
   const int N = a.N;
   const unsigned P = (unsigned)N * (unsigned)N, pb = P * kES;
   const unsigned F = (unsigned)BT * VZ;
@@ -449,6 +514,13 @@ __global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
   const double hdt = -0.5 * a.dt, std_ = (double)st;
   const int tid = threadIdx.x;
   auto wof = [&](C l, C v) -> C { return l * rcp_c(C(1) + eps * v); };
+  // the loads of one plane x: lambda and V of plane x + 1 at the lane's
+  // sites, their y and z neighbours on plane x, psi_t, psi_{t+1} and G on x
+  struct Plane {
+    C lp[VZ], vp[VZ], lym[VZ], vym[VZ], lyp[VZ], vyp[VZ], pt[VZ], pt1[VZ];
+    C lzm[1], vzm[1], lzp[1], vzp[1];
+    GT g[VZ];
+  };
   for (int it = blockIdx.x; it < nchunk * nx; it += gridDim.x) {
     const int ch = it % nchunk, xr = it / nchunk;
     const int xb = (int)(((long long)xr * N) / nx), xe = (int)(((long long)(xr + 1) * N) / nx);
@@ -460,6 +532,27 @@ __global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
     const bool zlo = ok && z0 > 0, zhi = ok && z0 + VZ < N;
     const unsigned off = fe * kES, offm = (fe - (unsigned)N) * kES, offp = (fe + (unsigned)N) * kES;
     const unsigned offzm = fe * kES - kES, offzp = fe * kES + VZ * kES;
+    auto load = [&](int x, Plane& q) {
+      const __amdgpu_buffer_rsrc_t rl1 = plane_rsrc(a.lam_in, x + 1, N, pb);
+      const __amdgpu_buffer_rsrc_t rv1 = plane_rsrc(a.V, x + 1, N, pb);
+      const __amdgpu_buffer_rsrc_t rl = plane_rsrc(a.lam_in, x, N, pb);
+      const __amdgpu_buffer_rsrc_t rv = plane_rsrc(a.V, x, N, pb);
+      bload<S, VZ, C>(rl1, off, q.lp);
+      bload<S, VZ, C>(rv1, off, q.vp);
+      bload<S, VZ, C>(rl, offm, q.lym);
+      bload<S, VZ, C>(rv, offm, q.vym);
+      bload<S, VZ, C>(rl, offp, q.lyp);
+      bload<S, VZ, C>(rv, offp, q.vyp);
+      bload<S, 1, C>(rl, offzm, q.lzm);
+      bload<S, 1, C>(rv, offzm, q.vzm);
+      bload<S, 1, C>(rl, offzp, q.lzp);
+      bload<S, 1, C>(rv, offzp, q.vzp);
+      // read once and written once: past the caches, which keep lambda and V
+      // for the neighbour re-reads
+      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t, x, N, pb), off, q.pt);
+      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t1, x, N, pb), off, q.pt1);
+      bload<GT, VZ, GT, kNT>(plane_rsrc(a.G, x, N, P * kGS), fe * kGS, q.g);
+    };
     // w of the lane's sites on planes x - 1 (wm) and x (wc); lambda, V on x
     C wm[VZ], wc[VZ], lc[VZ], vc[VZ];
     {
@@ -474,58 +567,50 @@ __global__ __launch_bounds__(BT) void k_adjoint_step(AdjArgs a) {
         wc[j] = wof(lc[j], vc[j]);
       }
     }
+    Plane cur, nxt;
+    load(xb, cur);
     for (int x = xb; x < xe; ++x) {
-      C lp[VZ], vp[VZ], lym[VZ], vym[VZ], lyp[VZ], vyp[VZ], pt[VZ], pt1[VZ];
-      C lzm[1], vzm[1], lzp[1], vzp[1];
-      const __amdgpu_buffer_rsrc_t rl1 = plane_rsrc(a.lam_in, x + 1, N, pb);
-      const __amdgpu_buffer_rsrc_t rv1 = plane_rsrc(a.V, x + 1, N, pb);
-      const __amdgpu_buffer_rsrc_t rl = plane_rsrc(a.lam_in, x, N, pb);
-      const __amdgpu_buffer_rsrc_t rv = plane_rsrc(a.V, x, N, pb);
-      bload<S, VZ, C>(rl1, off, lp);
-      bload<S, VZ, C>(rv1, off, vp);
-      bload<S, VZ, C>(rl, offm, lym);
-      bload<S, VZ, C>(rv, offm, vym);
-      bload<S, VZ, C>(rl, offp, lyp);
-      bload<S, VZ, C>(rv, offp, vyp);
-      bload<S, 1, C>(rl, offzm, lzm);
-      bload<S, 1, C>(rv, offzm, vzm);
-      bload<S, 1, C>(rl, offzp, lzp);
-      bload<S, 1, C>(rv, offzp, vzp);
-      // read once and written once: past the caches, which keep lambda and V
-      // for the neighbour re-reads
-      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t, x, N, pb), off, pt);
-      bload<S, VZ, C, kNT>(plane_rsrc(a.psi_t1, x, N, pb), off, pt1);
-      const __amdgpu_buffer_rsrc_t rg = plane_rsrc(a.G, x, N, P * 8u);
-      double gv[VZ];
-      bload<double, VZ, double, kNT>(rg, fe * 8u, gv);
+      if (x + 1 < xe) load(x + 1, nxt);
       C wp[VZ];
       Pack<S, VZ> o;
+      Pack<GT, VZ> go;
 #pragma unroll
-      for (int j = 0; j < VZ; ++j) wp[j] = wof(lp[j], vp[j]);
-      const C wzl = zlo ? wof(lzm[0], vzm[0]) : C(0), wzr = zhi ? wof(lzp[0], vzp[0]) : C(0);
+      for (int j = 0; j < VZ; ++j) wp[j] = wof(cur.lp[j], cur.vp[j]);
+      const C wzl = zlo ? wof(cur.lzm[0], cur.vzm[0]) : C(0);
+      const C wzr = zhi ? wof(cur.lzp[0], cur.vzp[0]) : C(0);
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         const C w = wc[j];
-        const C wym = wof(lym[j], vym[j]), wyp = wof(lyp[j], vyp[j]);
+        const C wym = wof(cur.lym[j], cur.vym[j]), wyp = wof(cur.lyp[j], cur.vyp[j]);
         const C wzm = j > 0 ? wc[j - 1] : wzl, wzp = j < VZ - 1 ? wc[j + 1] : wzr;
         const C lapw = (((wm[j] - w) + (wp[j] - w)) + ((wym - w) + (wyp - w))) + ((wzm - w) + (wzp - w));
         o.v[j] = (S)(st * (lc[j] + c * lapw - dt * vc[j] * w));
         const C B = rcp_c(C(1) + eps * vc[j]);
-        gv[j] += (double)lc[j] * (hdt * (double)B) * (std_ * (double)pt[j] + (double)pt1[j]);
+        const double inc = (double)lc[j] * (hdt * (double)B) * (std_ * (double)cur.pt[j] + (double)cur.pt1[j]);
+        go.v[j] = cur.g[j] + (GT)inc;
       }
       bstore<S, VZ, kNT>(plane_rsrc(a.lam_out, x, N, pb), off, o);
-      Pack<double, VZ> go;
-#pragma unroll
-      for (int j = 0; j < VZ; ++j) go.v[j] = gv[j];
-      bstore<double, VZ, kNT>(rg, fe * 8u, go);
+      bstore<GT, VZ, kNT>(plane_rsrc(a.G, x, N, P * kGS), fe * kGS, go);
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         wm[j] = wc[j];
         wc[j] = wp[j];
-        lc[j] = lp[j];
-        vc[j] = vp[j];
+        lc[j] = cur.lp[j];
+        vc[j] = cur.vp[j];
       }
+      cur = nxt;
     }
+  }
+}
+
+// End of a checkpoint segment on the F32 path: the segment's FP32 sums join
+// the FP64 accumulator and restart from 0.
+__global__ __launch_bounds__(kBlock) void k_fold_grad(double* __restrict__ G64, float* __restrict__ G32,
+                                                      long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    G64[i] += (double)G32[i];
+    G32[i] = 0.0f;
   }
 }
 
@@ -550,6 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_init(AdjInitArgs a) {
     const double hp = -a.kin_scale * lap + (double)V[s] * c0;
     lam[s] = (S)(2.0 * (hp - a.E * c0) / a.S0);
     a.G[s] = c0 * c0 / a.S0;
+    if (a.G32) a.G32[s] = 0.0f;
   }
 }
 
@@ -750,26 +836,27 @@ hipError_t convert_to(const SS* src, int ddtype, void* dst, long long n, double 
 
 template <typename CS>
 hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, void* pf, int Nf,
-                       double haf, hipStream_t s) {
+                       double haf, const UpNorm& u, hipStream_t s) {
   (void)hac;
   // (y, z-vector) columns of the fine lattice x fine x-ranges of kUpXC planes
   const long long cols = (long long)Nf * ((Nf + kUpVZ - 1) / kUpVZ);
   const dim3 g((unsigned)((cols + kBlock - 1) / kBlock), (unsigned)((Nf + kUpXC - 1) / kUpXC));
+  if ((long long)g.x * g.y != upsample_groups(Nf)) return hipErrorInvalidValue;
   if constexpr (sizeof(CS) == 2) {
     if (Nc % 2 == 0 && Nf >= 2 * Nc) {
       switch (fdtype) {
-        case kF64: hipLaunchKernelGGL((k_upsample<CS, double, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
-        case kF32: hipLaunchKernelGGL((k_upsample<CS, float, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
-        case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
+        case kF64: hipLaunchKernelGGL((k_upsample<CS, double, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf, u); break;
+        case kF32: hipLaunchKernelGGL((k_upsample<CS, float, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf, u); break;
+        case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, true>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf, u); break;
         default: return hipErrorInvalidValue;
       }
       return hipGetLastError();
     }
   }
   switch (fdtype) {
-    case kF64: hipLaunchKernelGGL((k_upsample<CS, double, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf); break;
-    case kF32: hipLaunchKernelGGL((k_upsample<CS, float, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf); break;
-    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf); break;
+    case kF64: hipLaunchKernelGGL((k_upsample<CS, double, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (double*)pf, Nf, haf, u); break;
+    case kF32: hipLaunchKernelGGL((k_upsample<CS, float, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (float*)pf, Nf, haf, u); break;
+    case kBF16: hipLaunchKernelGGL((k_upsample<CS, uint16_t, false>), g, dim3(kBlock), 0, s, pc, Nc, ac, (uint16_t*)pf, Nf, haf, u); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -787,11 +874,11 @@ hipError_t launch_convert(int sdtype, const void* src, int ddtype, void* dst, lo
 }
 
 hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, double ac, int fdtype,
-                           void* pf, int Nf, double haf, hipStream_t s) {
+                           void* pf, int Nf, double haf, const UpNorm& u, hipStream_t s) {
   switch (cdtype) {
-    case kF64: return upsample_to((const double*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
-    case kF32: return upsample_to((const float*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
-    case kBF16: return upsample_to((const uint16_t*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, s);
+    case kF64: return upsample_to((const double*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, u, s);
+    case kF32: return upsample_to((const float*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, u, s);
+    case kBF16: return upsample_to((const uint16_t*)pc, Nc, hac, ac, fdtype, pf, Nf, haf, u, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -864,12 +951,17 @@ hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s) {
   b.nx = (int)std::min<long long>(a.N, std::max<long long>(1, (2048 + nchunk - 1) / nchunk));
   const int g = (int)std::min<long long>(nchunk * b.nx, 1 << 20);
   if (dtype == kF64) {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, 2, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<double, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, double, 2, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<double, double, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
   } else {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, 4, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<float, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, float, 4, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<float, float, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_grad(double* G64, float* G32, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_grad, dim3(grid_for(n)), dim3(kBlock), 0, s, G64, G32, n);
   return hipGetLastError();
 }
 

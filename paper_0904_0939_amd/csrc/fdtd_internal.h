@@ -145,8 +145,23 @@ hipError_t launch_initial(int dtype, void* psi, int N, uint64_t seed, uint32_t m
                           uint32_t parity, hipStream_t s);
 hipError_t launch_convert(int sdtype, const void* src, int ddtype, void* dst, long long n,
                           double scale, hipStream_t s);
+// Renormalisation done by the upsample kernel itself: per-work-group FP64
+// partial sums (upsample_groups(Nf) of them) and the fine member's state and
+// observable record.
+struct UpNorm {
+  double* partials;
+  MemberState* st;   // its counter must be 0 on entry; receives the scale
+  double* obs;       // kRec doubles: obs[kS0] receives sum psi^2
+  double a3;         // fine a^3
+};
+constexpr int kUpSitesZ = 4;    // fine z sites per thread of the upsample kernel
+constexpr int kUpPlanes = 32;   // fine planes per work-group
+inline long long upsample_groups(int Nf) {
+  const long long nzv = (Nf + kUpSitesZ - 1) / kUpSitesZ;
+  return (((long long)Nf * nzv + kBlock - 1) / kBlock) * ((Nf + kUpPlanes - 1) / kUpPlanes);
+}
 hipError_t launch_upsample(int cdtype, const void* pc, int Nc, double hac, double ac, int fdtype,
-                           void* pf, int Nf, double haf, hipStream_t s);
+                           void* pf, int Nf, double haf, const UpNorm& u, hipStream_t s);
 hipError_t launch_reimpose(int dtype, void* psi, int N, uint32_t parity, hipStream_t s);
 hipError_t launch_set_state(MemberState* st, int member, double scale, long long step,
                             int reset_bad, hipStream_t s);
@@ -158,19 +173,24 @@ struct AdjArgs {
   void* lam_out;        // lambda_t
   const void* psi_t;    // psi_t  (as stored by the forward)
   const void* psi_t1;   // psi_{t+1}
-  double* G;            // dE/dV accumulator, FP64
+  void* G;              // dE/dV accumulator: FP64 on the F64 path; on the F32
+                        // path an FP32 accumulator of the current checkpoint
+                        // segment, folded into the FP64 sum by launch_fold_grad
   int N;
   int nx;               // x-ranges per chunk column (set by launch_adjoint_step)
   double c, dt;
   double s_t;           // scale applied in forward step t
 };
 hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s);
+// G64 += G32 and G32 = 0 over n sites (the end of a checkpoint segment).
+hipError_t launch_fold_grad(double* G64, float* G32, long long n, hipStream_t s);
 
 struct AdjInitArgs {
   const void* V;
   const void* psi;      // psi_T
   void* lam;            // out: 2 (H psi - E psi) / S0
   double* G;            // out: psi^2 / S0
+  float* G32;           // F32 path: out: 0 (the segment accumulator); else null
   int N;
   int pad0;
   double kin_scale;     // 1 / (2 m a^2)

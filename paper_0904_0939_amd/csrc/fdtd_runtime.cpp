@@ -96,6 +96,7 @@ struct fdtd_ctx {
   size_t ws_bytes = 0;
   bool ws_owned = false;
   size_t off_members = 0, off_states = 0, off_ring = 0, off_obs = 0, off_params = 0, off_ctrl = 0;
+  size_t off_upart = 0;  // partial sums of the upsample kernel's norm (largest member)
   size_t need_bytes = 0;
 
   // work items (library-allocated, depend on the tuning): d_items in member
@@ -130,6 +131,12 @@ struct fdtd_ctx {
   // projection scratch: per-work-group partial sums and the coefficients
   double* d_proj = nullptr;
 
+  // device memory of fdtd_energy_grad: bound by the caller, or allocated by
+  // the library and kept for later calls
+  char* gws = nullptr;
+  size_t gws_bytes = 0;
+  bool gws_owned = false;
+
   // counters (fdtd_get_counters)
   long long n_captures = 0;  // HIP graphs captured
   long long n_replays = 0;   // HIP graph launches
@@ -141,6 +148,7 @@ struct fdtd_ctx {
   double* d_obs() { return reinterpret_cast<double*>(ws + off_obs); }
   double* d_params() { return reinterpret_cast<double*>(ws + off_params); }
   Control* d_ctrl() { return reinterpret_cast<Control*>(ws + off_ctrl); }
+  double* d_upart() { return reinterpret_cast<double*>(ws + off_upart); }
   void* psi(int m, int b) { return ws + mem[m].off_psi[b]; }
   void* V(int m) { return ws + mem[m].off_V; }
 };
@@ -183,6 +191,10 @@ void compute_layout(fdtd_ctx* h) {
   off = align256(off + sizeof(double) * (kMaxParams + 64));
   h->off_ctrl = off;
   off = align256(off + sizeof(Control));
+  long long groups = 1;
+  for (auto& m : h->mem) groups = std::max(groups, upsample_groups(m.N));
+  h->off_upart = off;
+  off = align256(off + sizeof(double) * (size_t)groups);
   h->need_bytes = off;
 }
 
@@ -877,6 +889,7 @@ fdtd_status fdtd_destroy(fdtd_t h) {
   if (h->d_items) (void)hipFree(h->d_items);
   if (h->d_partials) (void)hipFree(h->d_partials);
   if (h->d_proj) (void)hipFree(h->d_proj);
+  if (h->gws && h->gws_owned) (void)hipFree(h->gws);
   for (auto& m : h->mem)
     if (m.proj) (void)hipFree(m.proj);
   if (h->ws && h->ws_owned) (void)hipFree(h->ws);
@@ -1181,6 +1194,36 @@ fdtd_status fdtd_get_state(fdtd_t h, int32_t member, void* dst, int32_t on_devic
   return FDTD_OK;
 }
 
+// The fine member's state <- trilinear interpolation of the coarse member's
+// (Sec. VI), renormalised by the kernel itself: `partials` holds
+// upsample_groups(N_fine) doubles.  The step counter restarts at 0.
+static fdtd_status upsample_into(fdtd_ctx* coarse, int cm, fdtd_ctx* fine, int fm, double* partials) {
+  const MemberHost& c = coarse->mem[cm];
+  MemberHost& f = fine->mem[fm];
+  HIP_TRY(hipSetDevice(fine->device));
+  // order the fine stream after the coarse work
+  if (coarse->stream != fine->stream) HIP_TRY(hipStreamSynchronize(coarse->stream));
+  HIP_TRY(launch_set_state(fine->d_states(), fm, 1.0, 0, 1, fine->stream));  // counter 0, step 0
+  UpNorm u;
+  u.partials = partials;
+  u.st = fine->d_states() + fm;
+  u.obs = fine->d_obs() + (size_t)fm * kRec;
+  u.a3 = f.a3;
+  HIP_TRY(launch_upsample(coarse->dtype, coarse->psi(cm, coarse->cur), c.N, c.ha, c.a, fine->dtype,
+                          fine->psi(fm, fine->cur), f.N, f.ha, u, fine->stream));
+  HIP_TRY(hipMemcpyAsync(fine->h_pin, u.obs + kS0, sizeof(double), hipMemcpyDeviceToHost, fine->stream));
+  HIP_TRY(hipStreamSynchronize(fine->stream));
+  const double s0 = fine->h_pin[0];
+  f.parity = c.parity;
+  f.hist_from = 0;
+  if (!(s0 > 0) || !std::isfinite(s0)) {
+    f.init_set = false;
+    return fail(FDTD_ENONFINITE, "upsample: the interpolated state has a zero or non-finite norm");
+  }
+  f.init_set = true;
+  return FDTD_OK;
+}
+
 // Checkpoint record: this header, then the stored state as held.
 struct CkptHeader {
   uint64_t magic;     // kCkptMagic
@@ -1280,14 +1323,7 @@ fdtd_status fdtd_upsample(fdtd_t coarse, int32_t cm, fdtd_t fine, int32_t fm) {
   if (!f.pot_set) return fail(FDTD_ENOTREADY, "upsample: fine potential not set");
   ST_TRY(ensure_memory(coarse));
   ST_TRY(ensure_memory(fine));
-  // order the fine stream after the coarse work
-  HIP_TRY(hipStreamSynchronize(coarse->stream));
-  HIP_TRY(launch_upsample(coarse->dtype, coarse->psi(cm, coarse->cur), c.N, c.ha, c.a, fine->dtype,
-                          fine->psi(fm, fine->cur), f.N, f.ha, fine->stream));
-  f.parity = c.parity;
-  ST_TRY(start_state(fine, fm));
-  HIP_TRY(hipStreamSynchronize(fine->stream));
-  return FDTD_OK;
+  return upsample_into(coarse, cm, fine, fm, fine->d_upart());
 }
 
 fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out) {
@@ -1536,6 +1572,60 @@ extern "C" fdtd_status fdtd_tune_cache_load(const char* path) {
 }
 
 // ---------------------------------------------------------------- gradient --
+namespace {
+// Layout of the gradient driver's device memory for T steps with checkpoints
+// every k: the checkpoints, one segment of recomputed states, two adjoint
+// fields, the FP64 dE/dV sum and (F32 states) its FP32 segment accumulator,
+// the recompute's member descriptors and states, and a small scratch area.
+struct GradLayout {
+  size_t ck, sg, lam0, lam1, G, G32, descs, cks, scratch, bytes;
+};
+
+GradLayout grad_layout(const fdtd_ctx* h, int T, int k) {
+  const MemberHost& m = h->mem[0];
+  const size_t fb = align256(elem_size(h->dtype) * (size_t)m.n3);
+  const int nck = (T + k - 1) / k;
+  const int seg = std::min(k, T);
+  GradLayout L;
+  size_t off = 0;
+  L.ck = off; off += fb * (size_t)nck;
+  L.sg = off; off += fb * (size_t)(seg + 1);
+  L.lam0 = off; off += fb;
+  L.lam1 = off; off += fb;
+  L.G = off; off += align256(sizeof(double) * (size_t)m.n3);
+  L.G32 = off; off += h->dtype == kF32 ? align256(sizeof(float) * (size_t)m.n3) : 0;
+  L.descs = off; off += align256(sizeof(MemberDev) * seg);
+  L.cks = off; off += align256(sizeof(MemberState) * (size_t)(nck + 1));
+  L.scratch = off; off += 65536 * sizeof(double);
+  L.bytes = off;
+  return L;
+}
+}  // namespace
+
+extern "C" fdtd_status fdtd_grad_workspace_size(fdtd_t h, int32_t steps, int32_t checkpoint_every,
+                                                size_t* bytes) {
+  if (!h || !bytes) return fail(FDTD_EINVAL, "grad_workspace_size: null argument");
+  if (steps < 1 || checkpoint_every < 1) return fail(FDTD_EINVAL, "grad_workspace_size: steps and checkpoint_every must be >= 1");
+  if (h->count != 1) return fail(FDTD_EINVAL, "grad_workspace_size: single-lattice handles only");
+  *bytes = grad_layout(h, steps, checkpoint_every).bytes;
+  return FDTD_OK;
+}
+
+extern "C" fdtd_status fdtd_bind_grad_workspace(fdtd_t h, void* dev_ptr, size_t bytes) {
+  if (!h) return fail(FDTD_EINVAL, "bind_grad_workspace: null handle");
+  if (dev_ptr && reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0)
+    return fail(FDTD_EINVAL, "bind_grad_workspace: pointer must be 256-byte aligned");
+  if (h->gws && h->gws_owned) {
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->gws);
+  }
+  h->gws = static_cast<char*>(dev_ptr);
+  h->gws_bytes = dev_ptr ? bytes : 0;
+  h->gws_owned = false;
+  return FDTD_OK;
+}
+
 extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpoint_every,
                                         const double* theta, int32_t ntheta, const int32_t* wrt,
                                         int32_t nwrt, void* dE_dV, double* dE_dtheta,
@@ -1573,28 +1663,34 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
   const int T = steps, k = checkpoint_every;
   const int nck = (T + k - 1) / k;
   const int seg = std::min(k, T);
-  // device buffers: checkpoints, one segment of states, two adjoints, G, descriptors
-  const size_t bytes = fb * (size_t)nck + fb * (size_t)(seg + 1) + 2 * fb +
-                       align256(sizeof(double) * (size_t)m.n3) + align256(sizeof(MemberDev) * seg) +
-                       align256(sizeof(MemberState) * (size_t)(nck + 1)) + 65536 * sizeof(double);
-  char* buf = nullptr;
-  hipError_t e = dev_malloc(h, (void**)&buf, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(FDTD_ENOMEM, "energy_grad: cannot allocate checkpoint memory");
+  const GradLayout GL = grad_layout(h, T, k);
+  if (h->gws && h->gws_bytes < GL.bytes) {
+    if (!h->gws_owned)
+      return fail(FDTD_ENOMEM, "energy_grad: the bound gradient workspace is smaller than fdtd_grad_workspace_size");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    (void)hipFree(h->gws);
+    h->gws = nullptr;
+    h->gws_bytes = 0;
   }
-  struct Free {
-    char* p;
-    ~Free() { if (p) (void)hipFree(p); }
-  } guard{buf};
-  char* q = buf;
-  char* ck = q; q += fb * (size_t)nck;
-  char* sg = q; q += fb * (size_t)(seg + 1);
-  char* lam[2] = {q, q + fb}; q += 2 * fb;
-  double* G = reinterpret_cast<double*>(q); q += align256(sizeof(double) * (size_t)m.n3);
-  MemberDev* descs = reinterpret_cast<MemberDev*>(q); q += align256(sizeof(MemberDev) * seg);
-  MemberState* cks = reinterpret_cast<MemberState*>(q); q += align256(sizeof(MemberState) * (size_t)(nck + 1));
-  double* scratch = reinterpret_cast<double*>(q);
+  if (!h->gws) {
+    hipError_t e = dev_malloc(h, (void**)&h->gws, GL.bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      h->gws = nullptr;
+      return fail(FDTD_ENOMEM, "energy_grad: cannot allocate checkpoint memory");
+    }
+    h->gws_bytes = GL.bytes;
+    h->gws_owned = true;
+  }
+  char* buf = h->gws;
+  char* ck = buf + GL.ck;
+  char* sg = buf + GL.sg;
+  char* lam[2] = {buf + GL.lam0, buf + GL.lam1};
+  double* G = reinterpret_cast<double*>(buf + GL.G);
+  float* G32 = h->dtype == kF32 ? reinterpret_cast<float*>(buf + GL.G32) : nullptr;
+  MemberDev* descs = reinterpret_cast<MemberDev*>(buf + GL.descs);
+  MemberState* cks = reinterpret_cast<MemberState*>(buf + GL.cks);
+  double* scratch = reinterpret_cast<double*>(buf + GL.scratch);
 
   std::vector<double> scales((size_t)T, 1.0);
   std::vector<double> rec((size_t)seg * kRec);
@@ -1613,11 +1709,14 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
     for (int i0 = 0; i0 < len; i0 += h->ring_cap) {
       const int n = std::min(len - i0, h->ring_cap);
       ST_TRY(launch_steps(h, n, 1, h->stream));
-      for (int i = i0; i < i0 + n; ++i) {
-        const long long t = t0 + i;
-        HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)i * kRec, h->d_ring() + (size_t)(t % h->ring_cap) * kRec,
-                               sizeof(double) * kRec, hipMemcpyDeviceToHost, h->stream));
-      }
+      // the n records, in at most two contiguous runs of the ring
+      const long long s0 = (t0 + i0) % h->ring_cap;
+      const int n1 = (int)std::min<long long>(n, h->ring_cap - s0);
+      HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)i0 * kRec, h->d_ring() + (size_t)s0 * kRec,
+                             sizeof(double) * kRec * n1, hipMemcpyDeviceToHost, h->stream));
+      if (n1 < n)
+        HIP_TRY(hipMemcpyAsync(rec.data() + (size_t)(i0 + n1) * kRec, h->d_ring(),
+                               sizeof(double) * kRec * (n - n1), hipMemcpyDeviceToHost, h->stream));
       HIP_TRY(hipStreamSynchronize(h->stream));
     }
     for (int i = 0; i < len; ++i) scales[(size_t)j * k + i] = rec[(size_t)i * kRec + kScale];
@@ -1639,6 +1738,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
     a.psi = h->psi(0, h->cur);
     a.lam = lam[0];
     a.G = G;
+    a.G32 = G32;
     a.N = m.N;
     a.kin_scale = m.kin_scale;
     a.E = E;
@@ -1682,7 +1782,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
       a.lam_out = lam[lc ^ 1];
       a.psi_t = sg + fb * i;
       a.psi_t1 = sg + fb * (i + 1);
-      a.G = G;
+      a.G = G32 ? static_cast<void*>(G32) : static_cast<void*>(G);
       a.N = m.N;
       a.c = m.c;
       a.dt = m.dt;
@@ -1690,6 +1790,7 @@ extern "C" fdtd_status fdtd_energy_grad(fdtd_t h, int32_t steps, int32_t checkpo
       HIP_TRY(launch_adjoint_step(h->dtype, a, h->stream));
       lc ^= 1;
     }
+    if (G32) HIP_TRY(launch_fold_grad(G, G32, m.n3, h->stream));
   }
   if (dE_dV) HIP_TRY(hipMemcpyAsync(dE_dV, G, sizeof(double) * (size_t)m.n3, hipMemcpyDeviceToDevice, h->stream));
   if (nwrt > 0) {

@@ -18,7 +18,8 @@ import re
 import torch  # noqa: F401  (must precede loading libfdtd)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfdtd.so")
+# FDTD_LIB_PATH: load another build of the same sources (the sanitizer build)
+LIB_PATH = os.environ.get("FDTD_LIB_PATH") or os.path.join(_HERE, "libfdtd.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "fdtd.h")
 
 OK, EINVAL, ENOMEM, EHIP, EUNSTABLE, ENOTREADY, ENONFINITE = range(7)
@@ -104,6 +105,8 @@ _SIGS = {
     "fdtd_energy_grad": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
                          C.POINTER(C.c_int32), C.c_int32, _P, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)],
+    "fdtd_grad_workspace_size": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "fdtd_bind_grad_workspace": [_P, _P, C.c_size_t],
     "fdtd_get_tuning": [_P, C.POINTER(fdtd_tuning)],
     "fdtd_set_tuning": [_P, C.POINTER(fdtd_tuning)],
     "fdtd_autotune": [_P, C.c_int32, C.POINTER(fdtd_tuning), C.POINTER(C.c_double)],
@@ -258,6 +261,16 @@ def fdtd_energy_grad(h, steps: int, checkpoint_every: int, theta=None, wrt=None,
     e = C.c_double()
     _call("fdtd_energy_grad", h, steps, checkpoint_every, th, nt, w, nw, dE_dV_ptr, g, C.byref(e))
     return e.value, [g[i] for i in range(nw)]
+
+
+def fdtd_grad_workspace_size(h, steps: int, checkpoint_every: int) -> int:
+    n = C.c_size_t()
+    _call("fdtd_grad_workspace_size", h, steps, checkpoint_every, C.byref(n))
+    return n.value
+
+
+def fdtd_bind_grad_workspace(h, ptr, nbytes: int):
+    _call("fdtd_bind_grad_workspace", h, ptr, nbytes)
 
 
 def fdtd_get_tuning(h) -> fdtd_tuning:

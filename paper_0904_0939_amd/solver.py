@@ -204,7 +204,16 @@ class Solver(_Handle):
 
     def energy_grad(self, steps: int, checkpoint_every: int, theta=None, wrt=None,
                     want_field: bool = False):
-        """(E_T, dE/dtheta list, dE/dV device tensor or None)."""
+        """(E_T, dE/dtheta list, dE/dV device tensor or None).  The driver's
+        checkpoints live in a torch tensor bound to the handle, kept between
+        calls and grown when a call needs more."""
+        need = F.fdtd_grad_workspace_size(self.h, steps, checkpoint_every)
+        gws = getattr(self, "_gws", None)
+        if gws is None or gws.numel() < need:
+            self._gws = None
+            F.fdtd_bind_grad_workspace(self.h, None, 0)
+            self._gws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{self.device}")
+            F.fdtd_bind_grad_workspace(self.h, self._gws.data_ptr(), need)
         G = None
         ptr = None
         if want_field:

@@ -341,3 +341,26 @@ def test_checkpoint_record_size_and_header_checks_without_device():
         assert status_of("fdtd_checkpoint_load", h, 0, None, 0) == F.EINVAL
     finally:
         F.fdtd_destroy(h)
+
+
+def test_gradient_workspace_size_and_binding_checks_without_device():
+    """fdtd_grad_workspace_size covers ceil(T/k) checkpoints, min(k, T) + 1
+    recomputed states and two adjoint fields of N^3 storage values, plus the
+    dE/dV sums; it grows with T and k; binds need 256-byte alignment."""
+    h = F.fdtd_create(cfg(N=16, dtype=F.F32))
+    h64 = F.fdtd_create(cfg(N=16, dtype=F.F64))
+    try:
+        fb = 16**3 * 4
+        a = F.fdtd_grad_workspace_size(h, 50, 10)
+        assert a >= (5 + 11 + 2) * fb + 16**3 * (8 + 4)
+        assert F.fdtd_grad_workspace_size(h, 100, 10) - a >= 5 * fb
+        assert F.fdtd_grad_workspace_size(h, 50, 25) - a >= (25 - 10) * fb - 5 * fb
+        assert F.fdtd_grad_workspace_size(h64, 50, 10) > a
+        n = C.c_size_t()
+        assert status_of("fdtd_grad_workspace_size", h, 0, 10, C.byref(n)) == F.EINVAL
+        assert status_of("fdtd_grad_workspace_size", h, 10, 0, C.byref(n)) == F.EINVAL
+        assert status_of("fdtd_bind_grad_workspace", h, C.c_void_p(4100), 1 << 20) == F.EINVAL
+        F.fdtd_bind_grad_workspace(h, None, 0)
+    finally:
+        F.fdtd_destroy(h)
+        F.fdtd_destroy(h64)

@@ -209,18 +209,52 @@ def test_energy_of_potential_without_grad_runs_no_adjoint():
     s.set_initial(3)
     psi0 = s.psi_tensor()
     V = torch.tensor(orc.potential(orc.POT_HO, [1, 1, 1], N, L), device="cuda")
-    a0 = s.counters()["allocations"]
     with torch.no_grad():
         e_ng = EnergyOfPotential.apply(V, s, psi0, 60, 20)
-    a1 = s.counters()["allocations"]
+    assert getattr(s, "_gws", None) is None  # no checkpoint workspace was needed
     Vg = V.clone().requires_grad_(True)
     e_g = EnergyOfPotential.apply(Vg, s, psi0, 60, 20)
-    a2 = s.counters()["allocations"]
-    assert float(e_ng) == pytest.approx(float(e_g), rel=1e-14)
-    assert a2 > a1  # the adjoint's checkpoint buffers
+    assert s._gws is not None
+    assert float(e_ng) == pytest.approx(float(e_g.detach()), rel=1e-14)
     e_g.backward()
     assert Vg.grad is not None and torch.isfinite(Vg.grad).all()
-    assert a1 - a0 <= a2 - a1
+
+
+def test_gradient_workspace_is_reused_and_a_small_bound_one_is_refused():
+    """Library-owned checkpoint memory is allocated once and kept for later
+    calls that fit; a caller-bound buffer below fdtd_grad_workspace_size is
+    refused with ENOMEM; a large enough one gives the same gradient."""
+    say("case: gradient workspace")
+    import torch
+
+    p = [1.0, 1.0, 1.0, 1.5, 0.3, 0.0, -0.2, 0.8]
+    out = []
+    for mode in ("library", "bound"):
+        s = Solver(16, 8.0, dtype="f32")
+        s.set_potential(F.POT_WELLS, p)
+        s.set_initial(14)
+        if mode == "library":
+            a0 = s.counters()["allocations"]
+            r = F.fdtd_energy_grad(s.h, 60, 20, p, [3, 7])
+            a1 = s.counters()["allocations"]
+            F.fdtd_energy_grad(s.h, 40, 20, p, [3, 7])  # fits: no new allocation
+            assert s.counters()["allocations"] == a1 == a0 + 1
+            s.set_initial(14)
+            r = F.fdtd_energy_grad(s.h, 60, 20, p, [3, 7])
+        else:
+            need = F.fdtd_grad_workspace_size(s.h, 60, 20)
+            small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+            F.fdtd_bind_grad_workspace(s.h, small.data_ptr(), need - 256)
+            with pytest.raises(F.FdtdError) as e:
+                F.fdtd_energy_grad(s.h, 60, 20, p, [3, 7])
+            assert e.value.status == F.ENOMEM
+            ws = torch.full((need,), 255, dtype=torch.uint8, device="cuda")  # NaN-filled
+            F.fdtd_bind_grad_workspace(s.h, ws.data_ptr(), need)
+            s.set_initial(14)
+            r = F.fdtd_energy_grad(s.h, 60, 20, p, [3, 7])
+        out.append(r)
+        s.close()
+    assert out[0] == out[1]
 
 
 # ------------------------------------------------- Sec. IV reimposition --
