@@ -31,10 +31,10 @@ BYTES_PER_SITE = {"f64": 24, "f32": 12, "bf16": 8}  # read psi + V, write psi'
 # FP32 adjoint step: read lambda, V, psi_t, psi_t+1 and G (the FP32 accumulator of
 # the checkpoint segment), write lambda and G
 ADJ_BYTES_PER_SITE = 4 * 4 + 4 + 4 + 4
-# the sources the step kernels are built from: a counter file is valid only
-# while their hash is the one it records
+# the sources the one-step kernels are built from: a counter file is valid
+# only while their hash is the one it records
 KERNEL_SRC = [os.path.join(ROOT, "paper_0904_0939_amd", "csrc", f)
-              for f in ("fdtd_step.hip", "fdtd_device.h", "fdtd_internal.h")]
+              for f in ("fdtd_step.hip", "fdtd_stepbody.h", "fdtd_device.h", "fdtd_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_traffic.json")
 
 
@@ -367,10 +367,12 @@ def gradient_256(steps=4000, k=100):
 
 def batch64(loop=4000, autotune=True):
     """64 random oscillator-plus-wells potentials on lattices of side 48..160,
-    FP32, the autotuned shape; with a persistent shape the `loop` steps of
-    every member run as one persistent launch, captured as one HIP graph
+    FP32, the autotuned shape, `loop` steps captured as one HIP graph
     (warm-up: one untimed loop, which also captures the graph), then one timed
-    loop."""
+    loop.  A persistent shape runs the whole loop as one persistent launch.
+    With a two-step shape (tblock 2) both forms are timed: one launch per pass
+    and one persistent launch of loop / 2 passes; the faster is the leg's
+    figure."""
     import torch
 
     from paper_0904_0939_amd import workloads as W
@@ -382,22 +384,32 @@ def batch64(loop=4000, autotune=True):
         b.set_potential(l.pot_kind, l.pot_params, member=m)
     b.set_initial(lats[0].seed)
     tun = b.autotune(10)[0] if autotune else b.tuning()
-    if tun["persist"] > 0:
-        # the whole loop as one persistent launch (measured equal to 64-step
-        # launches; the graph then holds one reset and one step kernel)
-        tun["persist"] = loop
-        b.set_tuning(**tun)
-    # check_every = loop: evolve() captures `loop` steps as one graph; with
-    # rel_tol 0 the one check at the end never stops the run
-    b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / loop
+
+    def timed(t):
+        b.set_tuning(**t)
+        # check_every = loop: evolve() captures `loop` steps as one graph; with
+        # rel_tol 0 the one check at the end never stops the run
+        b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.evolve(loop, check_every=loop, rel_tol=0.0, use_graph=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / loop
+
+    forms = {}
+    if tun.get("tblock", 0) == 2:
+        forms["one_launch_per_pass"] = dict(tun, persist=0)
+        forms["persistent_passes"] = dict(tun, persist=loop // 2)
+    elif tun["persist"] > 0:
+        forms["persistent"] = dict(tun, persist=loop)
+    else:
+        forms["one_launch_per_step"] = dict(tun)
+    times = {name: timed(t) for name, t in forms.items()}
+    best = min(times, key=times.get)
+    ms = times[best]
     sites = sum(l.sites for l in lats)
     obs = b.observables()
     b.close()
@@ -408,7 +420,8 @@ def batch64(loop=4000, autotune=True):
             "graph_steps": loop, "ms_per_step": ms, "site_updates_per_s": sites / (ms * 1e-3),
             "hbm_bytes_per_site_step": bps,
             "achieved_GBs": bps * sites / (ms * 1e-3) / 1e9,
-            "one_step_equivalent_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": tun,
+            "one_step_equivalent_GBs": 12 * sites / (ms * 1e-3) / 1e9, "tuning": forms[best],
+            "form": best, "ms_per_step_by_form": times,
             "energy_range": [min(o["energy"] for o in obs), max(o["energy"] for o in obs)]}
 
 

@@ -173,8 +173,9 @@ typedef struct {
  *         512 MiB); 1: large work-groups (1024 lanes, 512 for BF16) sharing
  *         an LDS copy of each plane (needs vz = the vector width, 2N / vz <=
  *         the work-group size and a tile of at most 64 KiB; ry is ignored);
- *  persist  0: one launch per step; n > 0: one persistent launch advances
- *         every member up to n steps (variant 0 only).  Its work-groups (grid,
+ *  persist  0: one launch per step (or pass); n > 0: one persistent launch
+ *         advances every member up to n steps (variant 0 only), or with
+ *         tblock = 2 up to n two-step passes (2n steps, n <= 32768).  Its work-groups (grid,
  *         0: one per CU) take (step, work item) tickets in order; a work item
  *         of step t first waits until its own lattice has finished step t - 1,
  *         so the end of one step overlaps the start of the next on a batch.
@@ -197,7 +198,9 @@ typedef struct {
  *         tile plus a one-site frame around it (and one plane on each side in
  *         x) by one step, in registers and LDS, then its own tile by the
  *         second.  Any lattice side (a multiple of vz), ry = 1, vz = the
- *         vector width, variant 0, persist 0; not inside fdtd_energy_grad.
+ *         vector width, variant 0; persist > 0 runs the passes persistently
+ *         (a tile of pass p waits until its lattice has finished pass p - 1;
+ *         the same bits as one launch per pass); not inside fdtd_energy_grad.
  *         The rescale can only follow a pass: one due after a pass's first
  *         step (renorm_every) is applied after its second.  With the rescale
  *         off the states are the same bits as one launch per step (shared

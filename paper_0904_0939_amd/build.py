@@ -2,9 +2,10 @@
 
     python -m paper_0904_0939_amd.build
 
-Compiles csrc/fdtd_step.hip (the fused step kernels), csrc/fdtd_aux.hip (set-up,
-upsample, adjoint and projection kernels) and csrc/fdtd_runtime.cpp with hipcc,
-in parallel, and links them into paper_0904_0939_amd/libfdtd.so.  Packed-FP32 instructions are
+Compiles csrc/fdtd_step.hip (the fused one-step kernels), csrc/fdtd_step2.hip
+(two steps per pass), csrc/fdtd_aux.hip (set-up, upsample, adjoint and
+projection kernels) and csrc/fdtd_runtime.cpp with hipcc, in parallel, and
+links them into paper_0904_0939_amd/libfdtd.so.  Packed-FP32 instructions are
 disabled for every device pass.
 """
 import os
@@ -18,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfdtd.so")
 ARCH = os.environ.get("FDTD_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["fdtd_step.hip", "fdtd_aux.hip", "fdtd_runtime.cpp"]
+SOURCES = ["fdtd_step.hip", "fdtd_step2.hip", "fdtd_aux.hip", "fdtd_runtime.cpp"]
 
 
 def hipcc() -> str:
@@ -28,7 +29,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the library is HIP-only")
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 4) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     common = [

@@ -190,6 +190,11 @@ __device__ __forceinline__ void up_weight(int j, int Nf, int Nc, double cNf, dou
   }
 }
 
+// The exact-doubling kernel k_upsample2x for Nf = 2 Nc (1: on).
+#ifndef FDTD_UP_2X
+#define FDTD_UP_2X 1
+#endif
+
 // Cache policy of the fine stores (kNT: past the caches; the state is read
 // back only by the next launch).
 #ifndef FDTD_UP_OUT
@@ -377,6 +382,160 @@ __device__ __forceinline__ void up_columns(const CS* __restrict__ pc, int Nc, do
   }
 }
 
+// The norm hand-off at the end of an upsample kernel: the work-group's sum
+// of squares to its partial slot (an agent-scope atomic store completed
+// before the group counts itself on the member's counter), and in the last
+// work-group the sum over the slots in work-group order, the member's scale
+// 1 / sqrt(a^3 sum psi^2), the sum in its observable record, the counter
+// re-armed.
+__device__ __forceinline__ void up_norm_finish(const UpNorm& U, double (&norm)[1],
+                                               double (&s_red)[kBlock / 64][1], int& s_last) {
+  block_sum<1>(norm, s_red);
+  const unsigned nb = gridDim.x * gridDim.y;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&U.partials[blockIdx.y * gridDim.x + blockIdx.x], norm[0], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the partial has reached the coherence point
+    const unsigned done = __hip_atomic_fetch_add(&U.st->counter, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = done == nb - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  double tot[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < nb; b += kBlock) tot[0] += ld_agent(U.partials[b]);
+  block_sum<1>(tot, s_red);
+  if (threadIdx.x == 0) {
+    U.obs[kS0] = tot[0];
+    U.st->scale = 1.0 / sqrt(U.a3 * tot[0]);
+    U.st->counter = 0u;
+  }
+}
+
+// The exact doubling of the multi-resolution chain (Nf = 2 Nc, Nc even).
+// Cell-centred sites put fine site 2i at coarse position i - 1/4 and fine
+// site 2i + 1 at i + 1/4, so every weight is 1/4 or 3/4, exactly, and the
+// sums are the general kernel's (the same FP64 products in the same order,
+// mirror-exact by construction).  A thread owns 4 fine z sites (coarse z
+// 2q - 1 .. 2q + 2) of 2 fine rows (coarse rows r - 1, r, r + 1) and streams
+// kUp2Planes coarse planes (twice as many fine planes): per coarse plane it
+// loads 3 x 3 values (a single site, an aligned pair, a single site per row),
+// forms their (z, y) interpolation once, and every fine plane then costs one
+// lerp along x.  No weight search and no per-site selection of coarse values,
+// which bounded the general kernel (instruction issue).
+constexpr int kUp2Planes = 16;
+
+template <typename CS, typename FS>
+__global__ __launch_bounds__(kBlock) void k_upsample2x(const CS* __restrict__ pc, int Nc,
+                                                       FS* __restrict__ pf, UpNorm U) {
+  using CE = typename std::conditional<sizeof(CS) == 8, double, float>::type;
+  __shared__ double s_red[kBlock / 64][1];
+  __shared__ int s_last;
+  const int Nf = 2 * Nc, half = Nc / 2;
+  const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double norm[1] = {0.0};
+  if (col < (long long)Nc * half) {
+    const int r = (int)(col / half), q = (int)(col - (long long)r * half);
+    const unsigned dead = kDeadLane * (unsigned)sizeof(CS);
+    const unsigned pbytes = (unsigned)Nc * (unsigned)Nc * (unsigned)sizeof(CS);
+    // offsets of the single sites 2q - 1, 2q + 2 and the pair 2q, 2q + 1 of
+    // coarse rows r - 1, r, r + 1 (outside the lattice: past the plane)
+    unsigned o_lo[3], o_pr[3], o_hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int rr = r - 1 + k;
+      const bool row = rr >= 0 && rr < Nc;
+      const unsigned base = (unsigned)(rr * Nc + 2 * q);
+      o_lo[k] = (row && q > 0) ? (base - 1u) * (unsigned)sizeof(CS) : dead;
+      o_pr[k] = row ? base * (unsigned)sizeof(CS) : dead;
+      o_hi[k] = (row && q < half - 1) ? (base + 2u) * (unsigned)sizeof(CS) : dead;
+    }
+    // the 12 coarse values of plane c: e[row][0..3] = sites 2q - 1 .. 2q + 2
+    auto load = [&](int c, CE (&e)[3][4]) {
+      const __amdgpu_buffer_rsrc_t rp = plane_rsrc(pc, c, Nc, pbytes);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        CE a[1], d[1], pr[2];
+        bload<CS, 1, CE>(rp, o_lo[k], a);
+        bload<CS, 2, CE>(rp, o_pr[k], pr);
+        bload<CS, 1, CE>(rp, o_hi[k], d);
+        e[k][0] = a[0];
+        e[k][1] = pr[0];
+        e[k][2] = pr[1];
+        e[k][3] = d[0];
+      }
+    };
+    // (z, y) interpolation at the thread's 2 x 4 fine (y, z) sites
+    auto interp = [&](const CE (&e)[3][4], double (&w)[2][4]) {
+      double v[3][4];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const double a = (double)e[k][0], b = (double)e[k][1], d = (double)e[k][2], f = (double)e[k][3];
+        v[k][0] = 0.25 * a + 0.75 * b;
+        v[k][1] = 0.75 * b + 0.25 * d;
+        v[k][2] = 0.25 * b + 0.75 * d;
+        v[k][3] = 0.75 * d + 0.25 * f;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        w[0][j] = 0.25 * v[0][j] + 0.75 * v[1][j];
+        w[1][j] = 0.75 * v[1][j] + 0.25 * v[2][j];
+      }
+    };
+    const unsigned fbytes = (unsigned)Nf * (unsigned)Nf * (unsigned)sizeof(FS);
+    const unsigned fo0 = (unsigned)((2 * r) * Nf + 4 * q) * (unsigned)sizeof(FS);
+    const unsigned fo1 = fo0 + (unsigned)Nf * (unsigned)sizeof(FS);
+    // fine plane x = lo_w * lo + hi_w * hi at the thread's sites
+    auto emit = [&](int x, double lw, const double (&lo)[2][4], double hw, const double (&hi)[2][4]) {
+      const __amdgpu_buffer_rsrc_t rf = plane_rsrc(pf, x, Nf, fbytes);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        Pack<FS, 4> o;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double v = lw * lo[k][j] + hw * hi[k][j];
+          double stored;
+          if constexpr (sizeof(FS) == 2) {
+            o.v[j] = f32_to_bf16((float)v);
+            stored = (double)bf16_to_f32(o.v[j]);
+          } else {
+            o.v[j] = (FS)v;
+            stored = (double)o.v[j];
+          }
+          norm[0] += stored * stored;
+        }
+        bstore<FS, 4, FDTD_UP_OUT>(rf, k ? fo1 : fo0, o);
+      }
+    };
+    const int p0 = blockIdx.y * kUp2Planes, p1 = min(p0 + kUp2Planes, Nc);
+    double wprev[2][4], wcur[2][4], wnext[2][4];
+    CE e0[3][4], e1[3][4];
+    load(p0 - 1, e0);
+    load(p0, e1);
+    interp(e0, wprev);
+    interp(e1, wcur);
+    load(p0 + 1, e1);
+    for (int p = p0; p < p1; ++p) {
+      if (p + 2 <= p1) load(p + 2, e0);  // one plane of prefetch
+      interp(e1, wnext);
+      emit(2 * p, 0.25, wprev, 0.75, wcur);
+      emit(2 * p + 1, 0.75, wcur, 0.25, wnext);
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          wprev[k][j] = wcur[k][j];
+          wcur[k][j] = wnext[k][j];
+        }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e1[k][j] = e0[k][j];
+    }
+  }
+  up_norm_finish(U, norm, s_red, s_last);
+}
+
 // The norm of the new state is reduced in the same pass (Sec. III: the state
 // is renormalised): each thread sums the squares of the values it stores, as
 // stored, in FP64; each work-group hands its sum to the last work-group (an
@@ -411,26 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_upsample(const CS* __restrict__ pc, 
   double norm[1] = {0.0};
   if (col < (long long)Nf * nzv) up_columns<CS, FS, PAIR>(pc, Nc, ac, pf, Nf, haf, col, nzv, x0, nx,
                                                            s_i0, s_w, s_w1, norm[0]);
-  block_sum<1>(norm, s_red);
-  const unsigned nb = gridDim.x * gridDim.y;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&U.partials[blockIdx.y * gridDim.x + blockIdx.x], norm[0], __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the partial has reached the coherence point
-    const unsigned done = __hip_atomic_fetch_add(&U.st->counter, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    s_last = done == nb - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  double tot[1] = {0.0};
-  for (unsigned b = threadIdx.x; b < nb; b += kBlock) tot[0] += ld_agent(U.partials[b]);
-  block_sum<1>(tot, s_red);
-  if (threadIdx.x == 0) {
-    U.obs[kS0] = tot[0];
-    U.st->scale = 1.0 / sqrt(U.a3 * tot[0]);
-    U.st->counter = 0u;
-  }
+  up_norm_finish(U, norm, s_red, s_last);
 }
 
 // ----------------------------------------------------- parity reimposed ----
@@ -842,6 +982,18 @@ hipError_t upsample_to(const CS* pc, int Nc, double hac, double ac, int fdtype, 
   const long long cols = (long long)Nf * ((Nf + kUpVZ - 1) / kUpVZ);
   const dim3 g((unsigned)((cols + kBlock - 1) / kBlock), (unsigned)((Nf + kUpXC - 1) / kUpXC));
   if ((long long)g.x * g.y != upsample_groups(Nf)) return hipErrorInvalidValue;
+  if (Nf == 2 * Nc && Nc % 2 == 0 && FDTD_UP_2X) {
+    const long long c2 = (long long)Nc * (Nc / 2);
+    const dim3 g2((unsigned)((c2 + kBlock - 1) / kBlock), (unsigned)((Nc + kUp2Planes - 1) / kUp2Planes));
+    if ((long long)g2.x * g2.y > upsample_groups(Nf)) return hipErrorInvalidValue;
+    switch (fdtype) {
+      case kF64: hipLaunchKernelGGL((k_upsample2x<CS, double>), g2, dim3(kBlock), 0, s, pc, Nc, (double*)pf, u); break;
+      case kF32: hipLaunchKernelGGL((k_upsample2x<CS, float>), g2, dim3(kBlock), 0, s, pc, Nc, (float*)pf, u); break;
+      case kBF16: hipLaunchKernelGGL((k_upsample2x<CS, uint16_t>), g2, dim3(kBlock), 0, s, pc, Nc, (uint16_t*)pf, u); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if constexpr (sizeof(CS) == 2) {
     if (Nc % 2 == 0 && Nf >= 2 * Nc) {
       switch (fdtype) {
@@ -937,25 +1089,38 @@ hipError_t launch_set_state(MemberState* st, int member, double scale, long long
   return hipGetLastError();
 }
 
+// Lanes per work-group of the adjoint step: a chunk of the flattened plane is
+// kAdjBT x VZ sites, and the y-neighbour rows at its two edges are re-read.
+#ifndef FDTD_ADJ_BT
+#define FDTD_ADJ_BT 256
+#endif
+constexpr int kAdjBT = FDTD_ADJ_BT;
+// Work items (chunk x x-range) an adjoint step aims at: each x-range re-reads
+// the lambda and V planes on both sides of it.
+#ifndef FDTD_ADJ_ITEMS
+#define FDTD_ADJ_ITEMS 2048
+#endif
+constexpr int kAdjItems = FDTD_ADJ_ITEMS;
+
 hipError_t launch_adjoint_step(int dtype, const AdjArgs& a, hipStream_t s) {
   if (a.N < 1 || (dtype != kF64 && dtype != kF32)) return hipErrorInvalidValue;
   // VZ sites per lane when N allows (a lane's vector stays within a z-row),
   // else one
   const int vz = dtype == kF64 ? 2 : 4;
   const bool vec = a.N % vz == 0;
-  const long long P = (long long)a.N * a.N, F = (long long)kBlock * (vec ? vz : 1);
+  const long long P = (long long)a.N * a.N, F = (long long)kAdjBT * (vec ? vz : 1);
   const long long nchunk = (P + F - 1) / F;
   AdjArgs b = a;
   // x split into ranges for about 2048 work items (measured at 256^3 FP32:
   // 256 to 4096 items and 256 to 1024 lanes per work-group within 3%)
-  b.nx = (int)std::min<long long>(a.N, std::max<long long>(1, (2048 + nchunk - 1) / nchunk));
+  b.nx = (int)std::min<long long>(a.N, std::max<long long>(1, (kAdjItems + nchunk - 1) / nchunk));
   const int g = (int)std::min<long long>(nchunk * b.nx, 1 << 20);
   if (dtype == kF64) {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, double, 2, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<double, double, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<double, double, 2, kAdjBT>), dim3(g), dim3(kAdjBT), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<double, double, 1, kAdjBT>), dim3(g), dim3(kAdjBT), 0, s, b);
   } else {
-    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, float, 4, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((k_adjoint_step<float, float, 1, kBlock>), dim3(g), dim3(kBlock), 0, s, b);
+    if (vec) hipLaunchKernelGGL((k_adjoint_step<float, float, 4, kAdjBT>), dim3(g), dim3(kAdjBT), 0, s, b);
+    else hipLaunchKernelGGL((k_adjoint_step<float, float, 1, kAdjBT>), dim3(g), dim3(kAdjBT), 0, s, b);
   }
   return hipGetLastError();
 }

@@ -109,10 +109,13 @@ hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int gr
 // are tiles of kTbRows(dtype) x kTbCols(dtype) sites of the (y, z) plane,
 // whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype) sites
 // per lane (256 lanes); depth 1..3; partials for 2 * slot_stride slots.
+// persist: one persistent launch of a.steps passes (2 a.steps steps; `grid`
+// work-groups take (pass, tile) tickets, a tile of pass p waiting until its
+// member has finalised pass p - 1); launch_persist_reset must run first.
 constexpr int kTbVec(int dtype) { return dtype == kF64 ? 2 : 4; }  // sites per lane
 constexpr int kTbCols(int dtype) { return dtype == kF64 ? 32 : 64; }
 constexpr int kTbRows(int dtype) { return 256 * kTbVec(dtype) / kTbCols(dtype); }
-hipError_t launch_step2(int dtype, int depth, bool fv, int grid, const StepArgs& a,
+hipError_t launch_step2(int dtype, int depth, bool fv, int grid, bool persist, const StepArgs& a,
                         hipStream_t s);
 
 // Persistent form of launch_step (update only): `grid` work-groups take

@@ -583,7 +583,35 @@ fdtd_status observe(fdtd_ctx* h, int member, bool set_scale) {
 // n steps: one launch per step, or with tun.persist > 0 persistent launches
 // of up to tun.persist steps each (a reset kernel before each).
 fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
-  if (h->tun.persist > 0) {
+  if (h->tun.persist > 0 && h->tun.tblock == 2 && !h->table_v_only) {
+    // persistent two-step passes; an odd last step runs as a one-step launch
+    int done = 0;
+    while (n - done >= 2) {
+      const int k = std::min({h->tun.persist, (n - done) / 2,
+                              std::max(1, (1 << 30) / std::max(1, h->n_titems))});
+      StepArgs a = base_args(h);
+      a.renorm_every = renorm_every;
+      a.items = h->d_titems;
+      a.n_items = h->n_titems;
+      a.slot_stride = h->n_titems;
+      a.steps = k;
+      a.spin_limit = h->spin_limit;
+      a.ctrl = h->d_ctrl();
+      const int grid = h->tun.grid > 0 ? h->tun.grid : h->n_cu;
+      HIP_TRY(launch_persist_reset(a.ctrl, a.states, h->count, s));
+      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), grid, true, a, s));
+      if (k & 1) h->cur ^= 1;
+      done += 2 * k;
+    }
+    for (; done < n; ++done) {
+      StepArgs a = base_args(h);
+      a.renorm_every = renorm_every;
+      HIP_TRY(launch_kernel(h, true, launch_grid(h, a.n_items), a, s));
+      h->cur ^= 1;
+    }
+    return FDTD_OK;
+  }
+  if (h->tun.persist > 0 && h->tun.tblock != 2) {
     for (int done = 0; done < n;) {
       // tickets (steps x items) stay below 2^30
       const int k = std::min({h->tun.persist, n - done, std::max(1, (1 << 30) / std::max(1, h->n_items))});
@@ -610,7 +638,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
       a.items = h->d_titems;
       a.n_items = h->n_titems;
       a.slot_stride = h->n_titems;
-      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), launch_grid(h, a.n_items), a, s));
+      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), launch_grid(h, a.n_items), false, a, s));
       h->cur ^= 1;  // psi_{t+2} is in the other buffer
     }
   }
@@ -822,10 +850,12 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
     return fail(FDTD_EINVAL, "tuning: variant 3 needs vz = the dtype's vector width and ry <= 2");
   if (t.persist < 0 || t.persist > 65536) return fail(FDTD_EINVAL, "tuning: persist must be in [0, 65536]");
   if (t.persist > 0 && t.variant != 0) return fail(FDTD_EINVAL, "tuning: persistent launches need variant 0");
+  if (t.persist > 0 && t.tblock == 2 && t.persist > 32768)
+    return fail(FDTD_EINVAL, "tuning: persistent two-step launches take at most 32768 passes");
   if (t.vfuse != 0 && t.vfuse != 1) return fail(FDTD_EINVAL, "tuning: vfuse must be 0 or 1");
   if (t.tblock != 0 && t.tblock != 2) return fail(FDTD_EINVAL, "tuning: tblock must be 0 or 2");
   if (t.tblock == 2) {
-    if (t.variant != 0 || t.persist != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0 and persist 0");
+    if (t.variant != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0");
     if (t.ry != 1 || t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs ry = 1 and vz = the dtype's vector width");
     for (auto& m : h->mem)
       if (m.N % kTbVec(h->dtype) != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs every N to be a multiple of its lane vector");
@@ -1482,12 +1512,14 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
         if (!go || xc > maxN || !all_div) continue;
         go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 1});
       }
-    // two steps per pass (validation drops the shapes it does not cover)
+    // two steps per pass (validation drops the shapes it does not cover),
+    // one launch per pass or (batches) persistent passes
     for (int xc : {0, 32, 64, 128, 256})
-      for (int depth : {1, 2}) {
-        if (!go || xc > maxN || !all_div) continue;
-        go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, 0, 0, 2});
-      }
+      for (int depth : {1, 2})
+        for (int persist : persists) {
+          if (!go || xc > maxN || !all_div) continue;
+          go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, persist / 2, 0, 2});
+        }
   }
   // restore
   h->cur = cur0;

@@ -1,0 +1,440 @@
+// Temporal blocking (two steps per pass over HBM) of the fused step: the
+// k_step2 kernel and its dispatch.  The per-site arithmetic is the one-step
+// kernel's (fdtd_stepbody.h), so with the rescale off a two-step pass
+// stores the same bits as two one-step launches.
+#include "fdtd_stepbody.h"
+
+#pragma clang fp contract(off)
+
+namespace fdtd {
+namespace {
+
+// -------------------------------------- temporal blocking: two steps ----
+// k_step2 advances every member two steps per pass over HBM (psi and V read
+// once, psi'' written once).  A work item owns a tile of kTbRows(DT) x
+// kTbCols(DT) sites of the (y, z) plane and streams x; each lane holds one
+// vector of VZ consecutive z sites (a tile row is 256 bytes of F32 / F64; BF16
+// lattices use the F32 tile, 4 sites per lane).
+// Step t runs on the tile's own vectors and on a frame of single halo sites
+// (the rows y0 - 1 and y0 + rows, the columns z0 - 1 and z0 + cols), with the
+// loads and arithmetic of the one-step kernel; its results stay in registers
+// (planes x - 1, x, x + 1 of the own vectors) and go to an LDS copy of the
+// framed tile for the y / z neighbours.  Step t + 1 follows one plane behind,
+// from registers and LDS.  Per-site arithmetic is that of the one-step
+// kernel, so with the rescale off the states are the same bits; the
+// reductions group their sums by tile instead of by flattened chunk (FP64
+// summation order only).  Step t never rescales; step t + 1 takes a rescale
+// due after either step.
+
+// V of a tile's sites is read again as the halo frame of its neighbours, so
+// the two-step kernel keeps V loads in the caches.
+#ifndef FDTD_TB_AUX_V
+#define FDTD_TB_AUX_V 0
+#endif
+constexpr int kTbVAux = FDTD_TB_AUX_V;
+
+template <int DT, int VZ, int D, bool FV>
+struct Step2 {
+  static constexpr int BT = 256;
+  static constexpr int TZ = kTbCols(DT);            // tile columns (z sites)
+  static constexpr int LPR = TZ / VZ;               // lanes per tile row
+  static constexpr int TY = BT / LPR;               // tile rows
+  static constexpr int NH = 2 * TZ + 2 * TY;        // halo sites, one per lane
+  static constexpr int NHW = (NH + 63) / 64;        // waves that carry halo sites
+  static constexpr int RP = TZ + 8;                 // LDS row pitch: own z at 4 .. 4 + TZ - 1
+  static constexpr int TS = (TY + 2) * RP;          // LDS plane: rows y0 - 1 .. y0 + TY
+  static_assert(TY == kTbRows(DT) && TZ % VZ == 0, "tile shape");
+  static_assert(NH <= BT, "one halo site per lane");
+  using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
+  using H = StepBody<DT, 1, 1, true, FV>;   // halo sites
+  using C = typename B::C;
+
+  struct Rings {
+    C qs[6][1][VZ];          // psi_t of planes, own vectors
+    C vs[6][1][VZ];          // V of planes
+    PlaneIn<1, VZ, C> nb[6]; // y / z neighbours of psi_t planes
+    C qh[6][1][1];           // the same for the lane's halo site
+    C vh[6][1][1];
+    PlaneIn<1, 1, C> nh[6];
+    C us[3][1][VZ];          // step-t results, own vectors
+  };
+
+  // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
+  // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
+  // plane X - 1, then the work-group barrier.
+  template <int SL, bool STEP2>
+  static __device__ __forceinline__ void stage(const typename B::Ctx& kb,
+                                               const typename H::Ctx& kh,
+                                               const typename B::Ctx& k2,
+                                               const Lane<1, VZ, C>& lb, const Lane<1, 1, C>& lh,
+                                               bool own, bool halo_wave, int obase, int hidx,
+                                               int X, int xb, int xe, unsigned N, C* tile,
+                                               Rings& g, double (&acc1)[5], double (&acc2)[5]) {
+    B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
+    B::template fetch_v<kTbVAux>(kb, lb, X + D, g.vs[(SL + D) % 6]);
+    B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
+    if (halo_wave) {
+      H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % 6]);
+      H::template fetch_v<kTbVAux>(kh, lh, X + D, g.vh[(SL + D) % 6]);
+      H::fetch(kh, lh, X + D, g.nh[(SL + D) % 6]);
+    }
+    // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
+    // one-step kernel drops their stores; here they feed step t + 1)
+    const bool inx = (unsigned)X < N;
+    C* t = tile + (X & 1) * TS;
+    {
+      // step t, own vectors: the work item's planes [xb, xe) count in the
+      // reductions, the halo planes xb - 1 and xe do not
+      double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      C un[1][VZ];
+      B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                              g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
+                                              tmp, true, un);
+      if (X >= xb && X < xe) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc1[q] += tmp[q];
+      }
+      Pack<C, VZ> pk;
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        pk.v[j] = inx ? un[0][j] : C(0);
+        g.us[SL % 3][0][j] = pk.v[j];
+      }
+      *reinterpret_cast<Pack<C, VZ>*>(t + obase) = pk;
+    }
+    if (halo_wave) {
+      // step t, halo site (no reductions: another work item owns it)
+      double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      C uh[1][1];
+      H::template update_core<false, true, 0>(kh, lh, X, g.qh[SL % 6], g.qh[(SL + 1) % 6],
+                                              g.qh[(SL + 2) % 6], g.vh[SL % 6], g.nh[SL % 6],
+                                              tmp, true, uh);
+      if ((int)threadIdx.x < NH) t[hidx] = inx ? uh[0][0] : C(0);
+    }
+    if constexpr (STEP2) {
+      // step t + 1 at plane X - 1: psi_{t+1} planes X - 2, X - 1, X in
+      // registers, the y / z neighbours of plane X - 1 from LDS.  A vector
+      // outside the lattice gets zero neighbours, as its loads in the
+      // one-step kernel: its result is not stored, but it enters the norm.
+      const C* tp = tile + ((X - 1) & 1) * TS;
+      PlaneIn<1, VZ, C> d;
+      const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase - RP);
+      const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase + RP);
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) {
+        d.ym[0][j] = own ? pm.v[j] : C(0);
+        d.yp[0][j] = own ? pp.v[j] : C(0);
+      }
+      d.zm[0] = own ? tp[obase - 1] : C(0);
+      d.zp[0] = own ? tp[obase + VZ] : C(0);
+      B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
+                                g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
+    }
+    lds_barrier();
+  }
+};
+
+// Lane vector r of a temporally blocked work item: site f of the flattened
+// plane (ok: a lattice site), with every offset the one-step loads use.
+template <typename Body, int RYL, int VZ, typename C>
+__device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f, bool ok,
+                                        const MemberDev& M, int N, double cN, double ha) {
+  constexpr unsigned kES = sizeof(typename Body::S);
+  using TV = typename Body::TV;
+  const unsigned fe = ok ? f : kDeadLane;
+  const int y = ok ? (int)(f / (unsigned)N) : 0;
+  const int z0 = ok ? (int)(f - (unsigned)y * N) : 0;
+  ln.off[r] = fe * kES;
+  ln.voff[r] = fe * (unsigned)sizeof(TV);
+  ln.offm[r] = (fe - (unsigned)N) * kES;
+  ln.offp[r] = (fe + (unsigned)N) * kES;
+  ln.offzm[r] = fe * kES - kES;
+  ln.offzp[r] = fe * kES + VZ * kES;
+  ln.zmask_lo[r] = (ok && z0 > 0) ? 1.f : 0.f;
+  ln.zmask_hi[r] = (ok && z0 + VZ < N) ? 1.f : 0.f;
+  const double yc = (2.0 * y - cN) * ha;
+  const int cy = min(y, N - 1 - y);
+  uint32_t key[VZ];
+#pragma unroll
+  for (int j = 0; j < VZ; ++j) {
+    const double zc = (2.0 * (z0 + j) - cN) * ha;
+    ln.w2[r][j] = (C)(yc * yc + zc * zc);
+    Body::vlane(ln, r, j, M.vkind, M.vp, M.a, yc, zc);
+    const int z = z0 + j;
+    key[j] = (uint32_t)cy * (uint32_t)N + (uint32_t)min(z, N - 1 - z);
+  }
+  Body::hash_lane(ln, r, N, key);
+}
+
+#ifndef FDTD_TB_MIN_WAVES
+#define FDTD_TB_MIN_WAVES 1  // waves per SIMD the register budget must allow
+#endif
+
+// One tile work item of a two-step pass reading buffer src (see k_step2).
+// FENCE: the persistent form, where the next pass's tiles (on any XCD) read
+// this pass's state within the same launch: the partials are published with
+// a full release fence, as the persistent one-step kernel does.
+template <int DT, int VZ, int D, bool FV, bool FENCE>
+__device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int src,
+                                        typename Step2<DT, VZ, D, FV>::C* tile,
+                                        double (&s_red)[256 / 64][5], int& s_last) {
+  using T = Step2<DT, VZ, D, FV>;
+  using B = typename T::B;
+  using H = typename T::H;
+  using C = typename T::C;
+  using TV = typename B::TV;
+  constexpr int BT = 256;
+  constexpr unsigned kES = sizeof(typename B::S);
+  const int tid = threadIdx.x;
+  // the waves that carry halo sites (uniform per wave)
+  const bool halo_wave = __builtin_amdgcn_readfirstlane(tid >> 6) < T::NHW;
+  {
+    const int m = item.member;
+    const MemberDev& M = A.members[m];
+    const int N = M.N;
+    const unsigned P = (unsigned)M.plane;
+    const double cN = (double)(N - 1), ha = M.ha;
+    const long long step = ld_agent(A.states[m].step);
+    const int y0 = item.f0 / N, z0 = item.f0 - y0 * N;  // tile origin
+
+    typename B::Ctx kb;
+    kb.in = M.psi[src];
+    kb.out = M.psi[src ^ 1];  // unused: step t goes to registers
+    kb.Vf = static_cast<const TV*>(M.V);
+    kb.pbytes = P * kES;
+    kb.vbytes = P * (unsigned)sizeof(TV);
+    kb.N = N;
+    kb.xe = item.xe + 1;  // step t also runs on plane xe (the halo plane)
+    kb.c = (C)M.c;
+    kb.dt = (C)M.dt;
+    kb.eps = (C)(0.5 * M.dt);
+    kb.sc = (C)ld_agent(A.states[m].scale);
+    kb.ha = ha;
+    kb.cN = cN;
+    kb.smix = hash32((uint32_t)step);
+    if constexpr (FV) B::vcoef(kb, M.vkind, M.vp, M.a);
+    typename H::Ctx kh;
+    kh.in = kb.in;
+    kh.out = kb.out;
+    kh.Vf = kb.Vf;
+    kh.pbytes = kb.pbytes;
+    kh.vbytes = kb.vbytes;
+    kh.N = N;
+    kh.xe = kb.xe;
+    kh.c = kb.c;
+    kh.dt = kb.dt;
+    kh.eps = kb.eps;
+    kh.sc = kb.sc;
+    kh.ha = ha;
+    kh.cN = cN;
+    kh.smix = kb.smix;
+    if constexpr (FV) H::vcoef(kh, M.vkind, M.vp, M.a);
+    typename B::Ctx k2 = kb;
+    k2.xe = item.xe;
+    k2.sc = C(1);  // no rescale between the two steps of a pass
+    k2.smix = hash32((uint32_t)(step + 1));
+
+    // own vector: row tid / LPR, columns (tid % LPR) * VZ of the tile
+    const int ly = tid / T::LPR, lz = (tid % T::LPR) * VZ;
+    const int yo = y0 + ly, zo = z0 + lz;
+    const bool own = yo < N && zo < N;
+    const int obase = (ly + 1) * T::RP + 4 + lz;
+    Lane<1, VZ, C> lb;
+    tb_lane<B>(lb, 0, (unsigned)(yo * N + zo), own, M, N, cN, ha);
+    // halo site of lanes below NH: row y0 - 1, row y0 + TY, column z0 - 1,
+    // column z0 + TZ
+    int hy, hz, hidx;
+    if (tid < T::TZ) {
+      hy = y0 - 1, hz = z0 + tid, hidx = 4 + tid;
+    } else if (tid < 2 * T::TZ) {
+      hy = y0 + T::TY, hz = z0 + tid - T::TZ, hidx = (T::TY + 1) * T::RP + 4 + tid - T::TZ;
+    } else if (tid < 2 * T::TZ + T::TY) {
+      hy = y0 + tid - 2 * T::TZ, hz = z0 - 1, hidx = (tid - 2 * T::TZ + 1) * T::RP + 3;
+    } else {
+      hy = y0 + tid - 2 * T::TZ - T::TY, hz = z0 + T::TZ;
+      hidx = (tid - 2 * T::TZ - T::TY + 1) * T::RP + 4 + T::TZ;
+    }
+    const bool hok = tid < T::NH && hy >= 0 && hy < N && hz >= 0 && hz < N;
+    Lane<1, 1, C> lh;
+    tb_lane<H>(lh, 0, hok ? (unsigned)(hy * N + hz) : 0u, hok, M, N, cN, ha);
+
+    double acc1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, acc2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    typename T::Rings g;
+    const int xb = item.xb, xe = item.xe, base = xb - 1;
+#pragma unroll
+    for (int i = 0; i < D + 2; ++i) B::fetch_own(kb, lb, base - 1 + i, g.qs[i]);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      B::template fetch_v<kTbVAux>(kb, lb, base + i, g.vs[i]);
+      B::fetch(kb, lb, base + i, g.nb[i]);
+    }
+    if (halo_wave) {
+#pragma unroll
+      for (int i = 0; i < D + 2; ++i) H::fetch_own(kh, lh, base - 1 + i, g.qh[i]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        H::template fetch_v<kTbVAux>(kh, lh, base + i, g.vh[i]);
+        H::fetch(kh, lh, base + i, g.nh[i]);
+      }
+    }
+#define FDTD_STAGE2(SL, S2, XX)                                                                  \
+  T::template stage<SL, S2>(kb, kh, k2, lb, lh, own, halo_wave, obase, hidx, XX, xb, xe,         \
+                            (unsigned)N, tile, g, acc1, acc2)
+    // planes xb - 1 and xb: step t only; then both steps, six stages a trip
+    FDTD_STAGE2(0, false, base);
+    FDTD_STAGE2(1, false, base + 1);
+    int X = xb + 1;
+    for (; X + 6 <= xe + 1; X += 6) {
+      FDTD_STAGE2(2, true, X);
+      FDTD_STAGE2(3, true, X + 1);
+      FDTD_STAGE2(4, true, X + 2);
+      FDTD_STAGE2(5, true, X + 3);
+      FDTD_STAGE2(0, true, X + 4);
+      FDTD_STAGE2(1, true, X + 5);
+    }
+    if (X <= xe) FDTD_STAGE2(2, true, X);
+    if (X + 1 <= xe) FDTD_STAGE2(3, true, X + 1);
+    if (X + 2 <= xe) FDTD_STAGE2(4, true, X + 2);
+    if (X + 3 <= xe) FDTD_STAGE2(5, true, X + 3);
+    if (X + 4 <= xe) FDTD_STAGE2(0, true, X + 4);
+#undef FDTD_STAGE2
+
+    // ---- partials of both steps; the member's last work-group finalises them
+    block_sum<5, BT / 64>(acc1, s_red);
+    block_sum<5, BT / 64>(acc2, s_red);
+    if (tid == 0) {
+      double* p1 = A.partials + (long long)item.slot * kRec;
+      double* p2 = A.partials + (long long)(A.slot_stride + item.slot) * kRec;
+      double* const dst[2] = {p1, p2};
+      const double v[2][5] = {{acc1[0], acc1[1], acc1[2], acc1[3], acc1[4]},
+                              {acc2[0], acc2[1], acc2[2], acc2[3], acc2[4]}};
+      unsigned int done;
+      if constexpr (FENCE) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          p1[q] = v[0][q];
+          p2[q] = v[1][q];
+        }
+        __threadfence();
+        done = atomicAdd(&A.states[m].counter, 1u);
+      } else {
+        done = publish_partials<2>(dst, v, &A.states[m].counter);
+      }
+      s_last = (done + 1u == (unsigned int)(M.tb_end - M.tb_begin));
+    }
+    __syncthreads();
+    if (s_last) {
+      if constexpr (FENCE) __threadfence();
+      double t1[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, t2[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = M.tb_begin + tid; i < M.tb_end; i += BT) {
+        const double* p1 = A.partials + (long long)i * kRec;
+        const double* p2 = A.partials + (long long)(A.slot_stride + i) * kRec;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          t1[q] += FENCE ? p1[q] : ld_agent(p1[q]);
+          t2[q] += FENCE ? p2[q] : ld_agent(p2[q]);
+        }
+      }
+      block_sum<5, BT / 64>(t1, s_red);
+      block_sum<5, BT / 64>(t2, s_red);
+      if (tid == 0) {
+        finalize(A, M, m, t1, true, 0);  // never rescales: step t + 1 already ran
+        finalize(A, M, m, t2, true, 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int DT, int VZ, int D, bool FV>
+__global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
+  using T = Step2<DT, VZ, D, FV>;
+  __shared__ __align__(16) typename T::C tile[2 * T::TS];
+  __shared__ double s_red[256 / 64][5];
+  __shared__ int s_last;
+  for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
+    tb_item<DT, VZ, D, FV, false>(A, A.items[A.item_offset + li], A.src, tile, s_red, s_last);
+}
+
+// Persistent two-step passes: A.steps passes (2 A.steps steps) of every
+// member in one launch.  Work-groups take tickets k = p * n_items + i in
+// increasing order (tile i in processing order, pass p; buffers alternate
+// with p).  Before tile i of pass p, thread 0 polls until the tile's member
+// has finalised both steps of pass p - 1 (its `fin` counter, reset to 0
+// before the launch, reaches 2p; each finalised step raises it by one).  The
+// waits end for the reason the persistent one-step kernel's do: the tiles
+// waited on hold smaller tickets.  The same bounded poll and abort flag guard
+// them.  Per-tile arithmetic, partial slots and summation order are those of
+// k_step2: the same bits as one launch per pass.
+template <int DT, int VZ, int D, bool FV>
+__global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2_persist(StepArgs A) {
+  using T = Step2<DT, VZ, D, FV>;
+  __shared__ __align__(16) typename T::C tile[2 * T::TS];
+  __shared__ double s_red[256 / 64][5];
+  __shared__ int s_last;
+  __shared__ int s_tk;
+  const int tid = threadIdx.x;
+  const int total = A.steps * A.n_items;
+  for (;;) {
+    if (tid == 0) {
+      int tk = (int)atomicAdd(&A.ctrl->ticket, 1u);
+      if (tk < total) {
+        const unsigned need = 2u * (unsigned)(tk / A.n_items);
+        unsigned int* fin = &A.states[A.items[tk % A.n_items].member].fin;
+        unsigned polls = 0;
+        while (__hip_atomic_load(fin, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (__hip_atomic_load(&A.ctrl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+              ++polls > A.spin_limit) {
+            __hip_atomic_store(&A.ctrl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tk = total;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(4);
+        }
+      }
+      s_tk = tk;
+    }
+    __syncthreads();
+    const int tk = s_tk;
+    if (tk >= total) break;
+    const int pass = tk / A.n_items;
+    tb_item<DT, VZ, D, FV, true>(A, A.items[tk % A.n_items], A.src ^ (pass & 1), tile, s_red, s_last);
+  }
+}
+
+
+template <int DT, int D, bool FV>
+hipError_t step2_one(int grid, bool persist, const StepArgs& a, hipStream_t s) {
+  if (persist)
+    hipLaunchKernelGGL((k_step2_persist<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int DT, bool FV>
+hipError_t step2_depth(int depth, int grid, bool persist, const StepArgs& a, hipStream_t s) {
+  switch (depth) {
+    case 1: return step2_one<DT, 1, FV>(grid, persist, a, s);
+    case 2: return step2_one<DT, 2, FV>(grid, persist, a, s);
+    case 3: return step2_one<DT, 3, FV>(grid, persist, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_step2(int dtype, int depth, bool fv, int grid, bool persist, const StepArgs& a,
+                        hipStream_t s) {
+  if (grid < 1 || (persist && (a.steps < 1 || !a.ctrl))) return hipErrorInvalidValue;
+  switch (dtype) {
+    case kF64: return fv ? hipErrorInvalidValue : step2_depth<kF64, false>(depth, grid, persist, a, s);
+    case kF32: return fv ? step2_depth<kF32, true>(depth, grid, persist, a, s)
+                         : step2_depth<kF32, false>(depth, grid, persist, a, s);
+    case kBF16: return fv ? step2_depth<kBF16, true>(depth, grid, persist, a, s)
+                          : step2_depth<kBF16, false>(depth, grid, persist, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace fdtd

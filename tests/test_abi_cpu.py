@@ -157,8 +157,9 @@ def test_write_through_variant_rules_and_default():
 
 
 def test_two_step_passes_validation():
-    """tblock = 2: full vectors, ry = 1, variant 0 without persistence; any
-    side (tiles of the (y, z) plane), every dtype."""
+    """tblock = 2: full vectors, ry = 1, variant 0, persistent passes
+    allowed (up to 32768 per launch); any side (tiles of the (y, z) plane),
+    every dtype."""
     h32 = F.fdtd_create(cfg(N=64, dtype=F.F32))
     h64 = F.fdtd_create(cfg(N=64, dtype=F.F64))
     hb = F.fdtd_create(cfg(N=64, dtype=F.BF16))
@@ -171,8 +172,10 @@ def test_two_step_passes_validation():
                     F.fdtd_tuning(4, 2, 0, 0, 1, 1, 0, 0, 1, 2),   # ry 2
                     F.fdtd_tuning(1, 1, 0, 0, 1, 1, 0, 0, 1, 2),   # scalar lanes
                     F.fdtd_tuning(4, 1, 0, 0, 1, 1, 2, 0, 1, 2),   # variant 2
-                    F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 8, 1, 2)]:  # persistent
+                    F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 32769, 1, 2)]:  # too many passes
             assert status_of("fdtd_set_tuning", h32, C.byref(bad)) == F.EINVAL
+        F.fdtd_set_tuning(h32, F.fdtd_tuning(4, 1, 0, 0, 1, 2, 0, 8, 1, 2))  # persistent passes
+        assert F.fdtd_get_tuning(h32).persist == 8
         F.fdtd_set_tuning(h64, F.fdtd_tuning(2, 1, 0, 0, 1, 3, 0, 0, 1, 2))
         F.fdtd_set_tuning(hb, F.fdtd_tuning(8, 1, 0, 0, 1, 2, 0, 0, 1, 2))
         assert status_of("fdtd_set_tuning", hb, C.byref(F.fdtd_tuning(1, 1, 0, 0, 1, 1, 0, 0, 1, 2))) == F.EINVAL

@@ -327,12 +327,17 @@ def test_upsample_fp64_dyadic_and_general_ratio():
 @pytest.mark.parametrize("Nc,cd,Nf,fd", [(33, "f64", 65, "f64"), (50, "f64", 77, "f64"),
                                          (40, "f64", 24, "f64"), (31, "bf16", 62, "f64"),
                                          (26, "f32", 45, "f32"), (40, "bf16", 90, "f64"),
-                                         (34, "bf16", 100, "f32"), (2, "bf16", 9, "f64")])
+                                         (34, "bf16", 100, "f32"), (2, "bf16", 9, "f64"),
+                                         (26, "f32", 52, "f64"), (20, "bf16", 40, "bf16"),
+                                         (2, "f64", 4, "f32"), (18, "f64", 36, "bf16"),
+                                         (35, "f32", 70, "f32")])
 def test_upsample_ragged_sides_and_coarser_targets(Nc, cd, Nf, fd):
     """Fine sides that are not a multiple of the kernel's 4-site vectors,
     non-integer ratios, a target coarser than the source (several coarse
-    planes between two fine ones), and BF16 sources of even side under fine
-    sides of at least twice theirs (the coarse rows read as site pairs)."""
+    planes between two fine ones), BF16 sources of even side under fine
+    sides of at least twice theirs (the coarse rows read as site pairs), and
+    exact doublings of even sides (the dedicated 2x kernel, every storage
+    type; 35 -> 70 is odd and takes the general kernel)."""
     say(f"case: upsample {Nc} {cd} -> {Nf} {fd}")
     L = 9.0
     c = Solver(Nc, L, dtype=cd)
@@ -347,7 +352,8 @@ def test_upsample_ragged_sides_and_coarser_targets(Nc, cd, Nf, fd):
     elif cd == "f32":
         coarse = coarse.astype(np.float32).astype(np.float64)
     ref = orc.upsample(coarse, Nf, L)
-    tol = 1e-12 if fd == "f64" else 1e-6
+    # BF16 fine storage: the interpolated values rounded once to 8 bits (2^-9)
+    tol = {"f64": 1e-12, "f32": 1e-6, "bf16": 2.0 ** -8}[fd]
     np.testing.assert_allclose(f.psi(), ref, rtol=0, atol=tol * np.abs(ref).max())
     c.close()
     f.close()

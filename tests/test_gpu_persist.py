@@ -105,3 +105,56 @@ def test_bounded_wait_reports_an_error():
     s.set_tuning(t["vz"], t["ry"], 0, 0, 1, 1, 0, 8)
     s.evolve(16)
     assert s.observables()[0]["step"] == 16
+
+
+@pytest.mark.parametrize("passes,steps,graph", [(5, 150, True), (64, 151, False), (1, 40, True)])
+def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps, graph):
+    """Persistent two-step passes (tblock 2 with persist = passes per launch):
+    the same bits, histories and observables as one launch per pass of the
+    same tiles, odd step counts included (the last step runs alone)."""
+    say(f"case: persistent two-step batch passes={passes} steps={steps} graph={graph}")
+    out = []
+    for persist in (0, passes):
+        b, lats = make_batch()
+        b.set_tuning(4, 1, 0, 0, 1, 2, 0, persist, 1, 2)
+        b.evolve(steps, use_graph=graph)
+        out.append(([b.state(m) for m in range(len(lats))],
+                    [b.history(m, steps) for m in range(len(lats))], b.observables()))
+        b.close()
+    for m in range(len(out[0][0])):
+        assert np.array_equal(out[0][0][m], out[1][0][m]), m
+        assert out[0][1][m] == out[1][1][m], m
+    assert out[0][2] == out[1][2]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_single_lattice_persistent_two_step_equals_per_pass(dtype):
+    say(f"case: persistent two-step single {dtype}")
+    vz = {"f64": 2, "bf16": 8}[dtype]
+    out = []
+    for persist in (0, 8):
+        s = Solver(72, 10.0, dtype=dtype)
+        s.set_potential(F.POT_CORNELL, W.CORNELL_PARAMS)
+        s.set_initial(2, parity=W.parity_word(z=2))
+        s.set_tuning(vz, 1, 0, 0, 1, 2, 0, persist, 1, 2)
+        s.evolve(61)
+        out.append((s.state(), s.observables()[0]))
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
+def test_persistent_two_step_bounded_wait_reports_an_error():
+    say("case: persistent two-step wait bound")
+    os.environ["FDTD_PERSIST_SPIN_LIMIT"] = "0"
+    try:
+        s = Solver(64, 10.0, dtype="f32")
+    finally:
+        del os.environ["FDTD_PERSIST_SPIN_LIMIT"]
+    s.set_potential(F.POT_HO, [1, 1, 1])
+    s.set_initial(1)
+    s.set_tuning(4, 1, 0, 0, 1, 2, 0, 4, 0, 2)
+    with pytest.raises(F.FdtdError) as ei:
+        s.evolve(8, use_graph=False)
+    assert ei.value.status == F.EHIP and "dependency wait" in str(ei.value)
+    s.close()
