@@ -331,6 +331,21 @@ fdtd_status fdtd_checkpoint_load(fdtd_t h, int32_t member, const void* src, int3
  * fine member needs its potential set; psi dtypes may differ. */
 fdtd_status fdtd_upsample(fdtd_t coarse, int32_t coarse_member, fdtd_t fine, int32_t fine_member);
 
+/* fdtd_upsample for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, bit for bit, with the kernel's per-work-group partial sums
+ * of the norm in a static device array of 1 MiB per GPU (held until the
+ * process ends) instead of the fine handle's workspace.  Calls no hipMalloc,
+ * hipFree or other allocating routine.  Both handles must already have their
+ * device memory (a bound workspace, or any earlier call that set the coarse
+ * state and the fine potential): FDTD_ENOTREADY otherwise.  Fine sides above
+ * 1620 need more partial sums than the array holds: FDTD_EINVAL.  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams or threads) race and must be serialised by the caller.  Errors and
+ * the remaining behaviour as fdtd_upsample. */
+fdtd_status fdtd_upsample_noalloc(fdtd_t coarse, int32_t coarse_member, fdtd_t fine,
+                                  int32_t fine_member);
+
 /* Gradient of the energy after `steps` renormalised steps from the current
  * state of a single-lattice handle, held fixed, with respect to V: reverse-mode
  * differentiation of Eq. (updateeq) (adjoint stencil with the same A, B),

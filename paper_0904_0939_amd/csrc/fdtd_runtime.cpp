@@ -1356,6 +1356,52 @@ fdtd_status fdtd_upsample(fdtd_t coarse, int32_t cm, fdtd_t fine, int32_t fm) {
   return upsample_into(coarse, cm, fine, fm, fine->d_upart());
 }
 
+// ---- the upsample for callers that cannot allocate ----------------------
+// Partial sums of the upsample kernel's norm in a fixed device array instead
+// of the fine handle's workspace.  Each GPU holds its own copy of the array;
+// host code reaches it only through the address hipGetSymbolAddress gives on
+// that device (the array's name is a host-side stand-in), taken once per
+// device on the first call there.
+constexpr size_t kNoAllocScratchDoubles = 131072;  // 1 MiB: fine sides up to 1620
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+
+static fdtd_status scratch_on_device(int device, double** out) {
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return fail(FDTD_EINVAL, "upsample_noalloc: device ordinal out of range");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[device]) {
+    HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    ptr[device] = static_cast<double*>(p);
+  }
+  *out = ptr[device];
+  return FDTD_OK;
+}
+
+fdtd_status fdtd_upsample_noalloc(fdtd_t coarse, int32_t cm, fdtd_t fine, int32_t fm) {
+  if (!coarse || !fine) return fail(FDTD_EINVAL, "upsample_noalloc: null handle");
+  ST_TRY(check_member(coarse, cm, false));
+  ST_TRY(check_member(fine, fm, false));
+  const MemberHost& c = coarse->mem[cm];
+  const MemberHost& f = fine->mem[fm];
+  if ((size_t)upsample_groups(f.N) > kNoAllocScratchDoubles)
+    return fail(FDTD_EINVAL, "upsample_noalloc: the fine side " + std::to_string(f.N) +
+                                 " needs more partial sums than the static scratch holds (fine sides up to 1620)");
+  if (coarse->device != fine->device) return fail(FDTD_EINVAL, "upsample_noalloc: handles on different devices");
+  if (std::fabs(c.L - f.L) > 1e-12 * std::max(c.L, f.L)) return fail(FDTD_EINVAL, "upsample_noalloc: box lengths differ");
+  if (!c.init_set) return fail(FDTD_ENOTREADY, "upsample_noalloc: coarse state not set");
+  if (!f.pot_set) return fail(FDTD_ENOTREADY, "upsample_noalloc: fine potential not set");
+  if (!coarse->ws || !fine->ws || !fine->h_pin)
+    return fail(FDTD_ENOTREADY, "upsample_noalloc: the handles' device memory is not set up");
+  double* p = nullptr;
+  ST_TRY(scratch_on_device(fine->device, &p));
+  return upsample_into(coarse, cm, fine, fm, p);
+}
+
 fdtd_status fdtd_get_tuning(fdtd_t h, fdtd_tuning* out) {
   if (!h || !out) return fail(FDTD_EINVAL, "get_tuning: null argument");
   *out = h->tun;

@@ -102,6 +102,7 @@ _SIGS = {
     "fdtd_checkpoint_save": [_P, C.c_int32, _P, C.c_int32],
     "fdtd_checkpoint_load": [_P, C.c_int32, _P, C.c_int32],
     "fdtd_upsample": [_P, C.c_int32, _P, C.c_int32],
+    "fdtd_upsample_noalloc": [_P, C.c_int32, _P, C.c_int32],
     "fdtd_energy_grad": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int32,
                          C.POINTER(C.c_int32), C.c_int32, _P, C.POINTER(C.c_double),
                          C.POINTER(C.c_double)],
@@ -250,6 +251,10 @@ def fdtd_checkpoint_load(h, member: int, ptr: int, on_device: int):
 
 def fdtd_upsample(coarse, cm: int, fine, fm: int):
     _call("fdtd_upsample", coarse, cm, fine, fm)
+
+
+def fdtd_upsample_noalloc(coarse, cm: int, fine, fm: int):
+    _call("fdtd_upsample_noalloc", coarse, cm, fine, fm)
 
 
 def fdtd_energy_grad(h, steps: int, checkpoint_every: int, theta=None, wrt=None, dE_dV_ptr=None):
