@@ -1098,7 +1098,7 @@ constexpr int kAdjBT = FDTD_ADJ_BT;
 // Work items (chunk x x-range) an adjoint step aims at: each x-range re-reads
 // the lambda and V planes on both sides of it.
 #ifndef FDTD_ADJ_ITEMS
-#define FDTD_ADJ_ITEMS 2048
+#define FDTD_ADJ_ITEMS 8192
 #endif
 constexpr int kAdjItems = FDTD_ADJ_ITEMS;
 

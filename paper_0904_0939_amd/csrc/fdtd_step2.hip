@@ -33,6 +33,40 @@ namespace {
 #endif
 constexpr int kTbVAux = FDTD_TB_AUX_V;
 
+// FP32-arithmetic lattices (F32, BF16): step t's y / z neighbours of the
+// tile's own vectors from an LDS copy of the framed psi_t plane, written one
+// stage ahead from the lanes' own loads and the halo lanes' loads, instead of
+// per-lane neighbour loads and their register ring (1); with it, and two
+// waves per SIMD, a 512^3 F32 step took 206 us against 225 us (one wave, the
+// loads).  FP64 lattices keep the loads: with one wave the staging measured
+// slower (485 against 433 us per step), and two waves would spill a hundred
+// registers.  0: the loads for every dtype.
+#ifndef FDTD_TB_LDS_PSI
+#define FDTD_TB_LDS_PSI 1
+#endif
+constexpr bool tb_lds_psi(int dt) { return FDTD_TB_LDS_PSI != 0 && dt != kF64; }
+
+// Step t's results of the planes step t + 1 reads (X - 2, X - 1, X) from a
+// triple-buffered LDS tile (1) instead of a three-plane register ring (0);
+// measured no faster (210 against 206 us per 512^3 F32 step): off.
+#ifndef FDTD_TB_LDS_U
+#define FDTD_TB_LDS_U 0
+#endif
+constexpr bool kTbLdsU = FDTD_TB_LDS_U != 0;
+constexpr int kTbTileBufs = kTbLdsU ? 3 : 2;
+
+// Waves per SIMD the two-step kernel's register budget must allow: two for
+// FP32 arithmetic (F32 and BF16 states; a few registers then spill, and two
+// tiles per CU hide each other's latency), one for FP64 (two would spill
+// about a hundred).
+#ifndef FDTD_TB_MIN_WAVES_F32
+#define FDTD_TB_MIN_WAVES_F32 2
+#endif
+#ifndef FDTD_TB_MIN_WAVES_F64
+#define FDTD_TB_MIN_WAVES_F64 1
+#endif
+constexpr int tb_min_waves(int dt) { return dt == kF64 ? FDTD_TB_MIN_WAVES_F64 : FDTD_TB_MIN_WAVES_F32; }
+
 template <int DT, int VZ, int D, bool FV>
 struct Step2 {
   static constexpr int BT = 256;
@@ -43,6 +77,7 @@ struct Step2 {
   static constexpr int NHW = (NH + 63) / 64;        // waves that carry halo sites
   static constexpr int RP = TZ + 8;                 // LDS row pitch: own z at 4 .. 4 + TZ - 1
   static constexpr int TS = (TY + 2) * RP;          // LDS plane: rows y0 - 1 .. y0 + TY
+  static constexpr bool kPsi = tb_lds_psi(DT);       // neighbours of step t from LDS
   static_assert(TY == kTbRows(DT) && TZ % VZ == 0, "tile shape");
   static_assert(NH <= BT, "one halo site per lane");
   using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
@@ -56,12 +91,31 @@ struct Step2 {
     C qh[6][1][1];           // the same for the lane's halo site
     C vh[6][1][1];
     PlaneIn<1, 1, C> nh[6];
-    C us[3][1][VZ];          // step-t results, own vectors
+    C us[kTbLdsU ? 1 : 3][1][VZ];  // step-t results, own vectors (register ring form)
   };
 
   // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
   // plane X - 1, then the work-group barrier.
+  // Buffer of plane X (X >= -2) in the LDS tile of step-t results.
+  static __device__ __forceinline__ int tbuf(int X) {
+    return kTbLdsU ? (X + 3) % 3 : (X & 1);
+  }
+
+  // psi_t of plane X + 1 (slot SL + 2: own vector, halo site) into the LDS
+  // copy `ptile` + ((X + 1) & 1) * TS, read by step t at plane X + 1 in the
+  // next stage.
+  template <int SL>
+  static __device__ __forceinline__ void stage_psi(bool halo_wave, int obase, int hidx, int X,
+                                                   C* ptile, const Rings& g) {
+    C* p = ptile + ((X + 1) & 1) * TS;
+    Pack<C, VZ> pk;
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) pk.v[j] = g.qs[(SL + 2) % 6][0][j];
+    *reinterpret_cast<Pack<C, VZ>*>(p + obase) = pk;
+    if (halo_wave && (int)threadIdx.x < NH) p[hidx] = g.qh[(SL + 2) % 6][0][0];
+  }
+
   template <int SL, bool STEP2>
   static __device__ __forceinline__ void stage(const typename B::Ctx& kb,
                                                const typename H::Ctx& kh,
@@ -69,10 +123,11 @@ struct Step2 {
                                                const Lane<1, VZ, C>& lb, const Lane<1, 1, C>& lh,
                                                bool own, bool halo_wave, int obase, int hidx,
                                                int X, int xb, int xe, unsigned N, C* tile,
-                                               Rings& g, double (&acc1)[5], double (&acc2)[5]) {
+                                               C* ptile, Rings& g, double (&acc1)[5],
+                                               double (&acc2)[5]) {
     B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
     B::template fetch_v<kTbVAux>(kb, lb, X + D, g.vs[(SL + D) % 6]);
-    B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
+    if constexpr (!kPsi) B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
     if (halo_wave) {
       H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % 6]);
       H::template fetch_v<kTbVAux>(kh, lh, X + D, g.vh[(SL + D) % 6]);
@@ -81,15 +136,33 @@ struct Step2 {
     // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
     // one-step kernel drops their stores; here they feed step t + 1)
     const bool inx = (unsigned)X < N;
-    C* t = tile + (X & 1) * TS;
+    C* t = tile + tbuf(X) * TS;
     {
       // step t, own vectors: the work item's planes [xb, xe) count in the
       // reductions, the halo planes xb - 1 and xe do not
       double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       C un[1][VZ];
-      B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
-                                              g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
-                                              tmp, true, un);
+      if constexpr (kPsi) {
+        // y / z neighbours of plane X from the LDS copy written last stage
+        // (zero for a vector outside the lattice, as its loads would read)
+        const C* pp0 = ptile + (X & 1) * TS;
+        PlaneIn<1, VZ, C> d;
+        const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(pp0 + obase - RP);
+        const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(pp0 + obase + RP);
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          d.ym[0][j] = own ? pm.v[j] : C(0);
+          d.yp[0][j] = own ? pp.v[j] : C(0);
+        }
+        d.zm[0] = own ? pp0[obase - 1] : C(0);
+        d.zp[0] = own ? pp0[obase + VZ] : C(0);
+        B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                                g.qs[(SL + 2) % 6], g.vs[SL % 6], d, tmp, true, un);
+      } else {
+        B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                                g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
+                                                tmp, true, un);
+      }
       if (X >= xb && X < xe) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) acc1[q] += tmp[q];
@@ -98,7 +171,7 @@ struct Step2 {
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         pk.v[j] = inx ? un[0][j] : C(0);
-        g.us[SL % 3][0][j] = pk.v[j];
+        if constexpr (!kTbLdsU) g.us[SL % 3][0][j] = pk.v[j];
       }
       *reinterpret_cast<Pack<C, VZ>*>(t + obase) = pk;
     }
@@ -116,7 +189,7 @@ struct Step2 {
       // registers, the y / z neighbours of plane X - 1 from LDS.  A vector
       // outside the lattice gets zero neighbours, as its loads in the
       // one-step kernel: its result is not stored, but it enters the norm.
-      const C* tp = tile + ((X - 1) & 1) * TS;
+      const C* tp = tile + tbuf(X - 1) * TS;
       PlaneIn<1, VZ, C> d;
       const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase - RP);
       const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase + RP);
@@ -127,9 +200,26 @@ struct Step2 {
       }
       d.zm[0] = own ? tp[obase - 1] : C(0);
       d.zp[0] = own ? tp[obase + VZ] : C(0);
-      B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
-                                g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
+      if constexpr (kTbLdsU) {
+        // planes X - 2, X - 1, X of the lane's own vector (X: written by this
+        // lane in this stage, so no barrier is needed for it)
+        C u0[1][VZ], u1[1][VZ], u2[1][VZ];
+        const Pack<C, VZ> a0 = *reinterpret_cast<const Pack<C, VZ>*>(tile + tbuf(X - 2) * TS + obase);
+        const Pack<C, VZ> a1 = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase);
+        const Pack<C, VZ> a2 = *reinterpret_cast<const Pack<C, VZ>*>(tile + tbuf(X) * TS + obase);
+#pragma unroll
+        for (int j = 0; j < VZ; ++j) {
+          u0[0][j] = a0.v[j];
+          u1[0][j] = a1.v[j];
+          u2[0][j] = a2.v[j];
+        }
+        B::template update<false>(k2, lb, X - 1, u0, u1, u2, g.vs[(SL + 5) % 6], d, acc2);
+      } else {
+        B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
+                                  g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
+      }
     }
+    if constexpr (kPsi) stage_psi<SL>(halo_wave, obase, hidx, X, ptile, g);
     lds_barrier();
   }
 };
@@ -166,9 +256,6 @@ __device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f,
   Body::hash_lane(ln, r, N, key);
 }
 
-#ifndef FDTD_TB_MIN_WAVES
-#define FDTD_TB_MIN_WAVES 1  // waves per SIMD the register budget must allow
-#endif
 
 // One tile work item of a two-step pass reading buffer src (see k_step2).
 // FENCE: the persistent form, where the next pass's tiles (on any XCD) read
@@ -177,6 +264,7 @@ __device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f,
 template <int DT, int VZ, int D, bool FV, bool FENCE>
 __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int src,
                                         typename Step2<DT, VZ, D, FV>::C* tile,
+                                        typename Step2<DT, VZ, D, FV>::C* ptile,
                                         double (&s_red)[256 / 64][5], int& s_last) {
   using T = Step2<DT, VZ, D, FV>;
   using B = typename T::B;
@@ -266,7 +354,7 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
 #pragma unroll
     for (int i = 0; i < D; ++i) {
       B::template fetch_v<kTbVAux>(kb, lb, base + i, g.vs[i]);
-      B::fetch(kb, lb, base + i, g.nb[i]);
+      if constexpr (!T::kPsi) B::fetch(kb, lb, base + i, g.nb[i]);
     }
     if (halo_wave) {
 #pragma unroll
@@ -277,9 +365,14 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
         H::fetch(kh, lh, base + i, g.nh[i]);
       }
     }
+    if constexpr (T::kPsi) {
+      // the LDS copy of plane base (slot 1), read by the first stage
+      T::template stage_psi<5>(halo_wave, obase, hidx, base - 1, ptile, g);
+      lds_barrier();
+    }
 #define FDTD_STAGE2(SL, S2, XX)                                                                  \
   T::template stage<SL, S2>(kb, kh, k2, lb, lh, own, halo_wave, obase, hidx, XX, xb, xe,         \
-                            (unsigned)N, tile, g, acc1, acc2)
+                            (unsigned)N, tile, ptile, g, acc1, acc2)
     // planes xb - 1 and xb: step t only; then both steps, six stages a trip
     FDTD_STAGE2(0, false, base);
     FDTD_STAGE2(1, false, base + 1);
@@ -347,13 +440,15 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
 }
 
 template <int DT, int VZ, int D, bool FV>
-__global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
+__global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2(StepArgs A) {
   using T = Step2<DT, VZ, D, FV>;
-  __shared__ __align__(16) typename T::C tile[2 * T::TS];
+  __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
+  __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
   __shared__ double s_red[256 / 64][5];
   __shared__ int s_last;
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
-    tb_item<DT, VZ, D, FV, false>(A, A.items[A.item_offset + li], A.src, tile, s_red, s_last);
+    tb_item<DT, VZ, D, FV, false>(A, A.items[A.item_offset + li], A.src, tile, ptile, s_red,
+                                  s_last);
 }
 
 // Persistent two-step passes: A.steps passes (2 A.steps steps) of every
@@ -367,9 +462,10 @@ __global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2(StepArgs A) {
 // them.  Per-tile arithmetic, partial slots and summation order are those of
 // k_step2: the same bits as one launch per pass.
 template <int DT, int VZ, int D, bool FV>
-__global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2_persist(StepArgs A) {
+__global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2_persist(StepArgs A) {
   using T = Step2<DT, VZ, D, FV>;
-  __shared__ __align__(16) typename T::C tile[2 * T::TS];
+  __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
+  __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
   __shared__ double s_red[256 / 64][5];
   __shared__ int s_last;
   __shared__ int s_tk;
@@ -398,7 +494,8 @@ __global__ __launch_bounds__(256, FDTD_TB_MIN_WAVES) void k_step2_persist(StepAr
     const int tk = s_tk;
     if (tk >= total) break;
     const int pass = tk / A.n_items;
-    tb_item<DT, VZ, D, FV, true>(A, A.items[tk % A.n_items], A.src ^ (pass & 1), tile, s_red, s_last);
+    tb_item<DT, VZ, D, FV, true>(A, A.items[tk % A.n_items], A.src ^ (pass & 1), tile, ptile,
+                                 s_red, s_last);
   }
 }
 
