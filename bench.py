@@ -708,7 +708,7 @@ def main():
     if not args.no_extras and args.dtype != "bf16":
         # temporal blocking: two steps per pass over HBM, (y, z) tiles
         vw = {"f32": 4, "f64": 2}[args.dtype]
-        s.set_tuning(vw, 1, 0, 0, 1, 2, 0, 0, 0, 2)
+        s.set_tuning(vw, 1, 0, 0, 1, 3, 0, 0, 0, 2)
         ms_2 = timed(args.steps, args.warmup)[0] / args.steps
         note(f"two steps per pass: {ms_2:.4f} ms/step")
         b_2 = BYTES_PER_SITE[args.dtype] / 2  # psi and V in, psi'' out, per two steps

@@ -168,6 +168,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, i
   return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, in ? (int)bytes : 0, kRsrcWord3);
 }
 
+// The same for a plane index held in a scalar register (a loop counter):
+// the select is on the index, not on the product, so it stays a scalar
+// select.  The select of the product becomes a uniform branch, and the
+// branches split an unrolled plane loop into blocks into which the compiler
+// sinks earlier stages' arithmetic, keeping its operands live.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_u(const void* base, int x, int N,
+                                                              unsigned bytes) {
+  const bool in = x >= 0 && x < N;
+  const unsigned xs = in ? (unsigned)x : 0u;
+  char* p = const_cast<char*>(static_cast<const char*>(base)) + (unsigned long long)xs * bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, in ? (int)bytes : 0, kRsrcWord3);
+}
+
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 

@@ -1565,7 +1565,7 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     // two steps per pass (validation drops the shapes it does not cover),
     // one launch per pass or (batches) persistent passes
     for (int xc : {0, 32, 64, 128, 256})
-      for (int depth : {1, 2})
+      for (int depth : {1, 2, 3})
         for (int persist : persists) {
           if (!go || xc > maxN || !all_div) continue;
           go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, persist / 2, 0, 2});

@@ -37,8 +37,8 @@ constexpr int kTbVAux = FDTD_TB_AUX_V;
 // tile's own vectors from an LDS copy of the framed psi_t plane, written one
 // stage ahead from the lanes' own loads and the halo lanes' loads, instead of
 // per-lane neighbour loads and their register ring (1); with it, and two
-// waves per SIMD, a 512^3 F32 step took 206 us against 225 us (one wave, the
-// loads).  FP64 lattices keep the loads: with one wave the staging measured
+// waves per SIMD, a 512^3 F32 step takes 192 us (depth 3) against 225 us (one
+// wave, the loads).  FP64 lattices keep the loads: with one wave the staging measured
 // slower (485 against 433 us per step), and two waves would spill a hundred
 // registers.  0: the loads for every dtype.
 #ifndef FDTD_TB_LDS_PSI
@@ -56,9 +56,9 @@ constexpr bool kTbLdsU = FDTD_TB_LDS_U != 0;
 constexpr int kTbTileBufs = kTbLdsU ? 3 : 2;
 
 // Waves per SIMD the two-step kernel's register budget must allow: two for
-// FP32 arithmetic (F32 and BF16 states; a few registers then spill, and two
-// tiles per CU hide each other's latency), one for FP64 (two would spill
-// about a hundred).
+// FP32 arithmetic (F32 and BF16 states: 195-215 VGPRs with the reductions
+// pinned per plane, and two tiles per CU hide each other's latency), one for
+// FP64 (two would spill about a hundred).
 #ifndef FDTD_TB_MIN_WAVES_F32
 #define FDTD_TB_MIN_WAVES_F32 2
 #endif

@@ -41,7 +41,10 @@ enum VKind { kVConst = 0, kVHO = 1, kVCoulomb = 2, kVCoulombReg = 3, kVCornell =
 
 // FV: the potential is evaluated in the kernel from the site coordinates
 // (member kinds kVConst..kVCornell) instead of read from the V table.
-template <int DT, int VZ, int RY, bool UPD, bool FV = false, int OUT = FDTD_AUX_OUT>
+// USEL: plane indices are loop counters in scalar registers (the one-step
+// kernels), so the resources take the branch-free form (plane_rsrc_u).
+template <int DT, int VZ, int RY, bool UPD, bool FV = false, int OUT = FDTD_AUX_OUT,
+          bool USEL = false>
 struct StepBody {
   using S = typename Types<DT>::S;
   using TV = typename Types<DT>::V;
@@ -50,6 +53,13 @@ struct StepBody {
   // z neighbours across vector boundaries by cross-lane reads (measured
   // faster for FP32 and FP64; BF16 lanes hold 8 sites and gain nothing)
   static constexpr bool kSHZ = kShuffleZ && DT != kBF16;
+  static constexpr bool kPinSums = DT != kF64;
+
+  static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int x, int N,
+                                                                unsigned bytes) {
+    if constexpr (USEL) return plane_rsrc_u(base, x, N, bytes);
+    else return plane_rsrc(base, x, N, bytes);
+  }
 
   struct Ctx {
     const void* in;
@@ -115,7 +125,7 @@ struct StepBody {
   // Issue the loads of the y and z neighbours of plane x (needed for x < xe).
   static __device__ __forceinline__ void fetch(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                PlaneIn<RY, VZ, C>& d) {
-    const __amdgpu_buffer_rsrc_t rc = plane_rsrc(k.in, x, min(k.N, k.xe), k.pbytes);
+    const __amdgpu_buffer_rsrc_t rc = rsrc(k.in, x, min(k.N, k.xe), k.pbytes);
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
       C zz[1];
@@ -149,7 +159,7 @@ struct StepBody {
           v[r][j] = rr < k.va ? C(0) : vv;
         }
     } else {
-      const __amdgpu_buffer_rsrc_t rv = plane_rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
+      const __amdgpu_buffer_rsrc_t rv = rsrc(k.Vf, x, min(k.N, k.xe), k.vbytes);
 #pragma unroll
       for (int r = 0; r < RY; ++r) bload<TV, VZ, C, VAUX>(rv, ln.voff[r], v[r]);
     }
@@ -158,7 +168,7 @@ struct StepBody {
   // Own sites of plane x (needed for x <= xe).
   static __device__ __forceinline__ void fetch_own(const Ctx& k, const Lane<RY, VZ, C>& ln, int x,
                                                    C (&q)[RY][VZ]) {
-    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(k.in, x, min(k.N, k.xe + 1), k.pbytes);
+    const __amdgpu_buffer_rsrc_t r0 = rsrc(k.in, x, min(k.N, k.xe + 1), k.pbytes);
 #pragma unroll
     for (int r = 0; r < RY; ++r) bload<S, VZ, C, FDTD_AUX_PSI>(r0, ln.off[r], q[r]);
   }
@@ -193,7 +203,7 @@ struct StepBody {
                                                      C (&outv)[NO][VZ]) {
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
-    const __amdgpu_buffer_rsrc_t ro = plane_rsrc(k.out, x, k.N, k.pbytes);
+    const __amdgpu_buffer_rsrc_t ro = rsrc(k.out, x, k.N, k.pbytes);
     const uint32_t hx = hash32((uint32_t)min(x, k.N - 1 - x) + k.smix);  // uniform
     C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
     const int lane = __lane_id();
@@ -270,6 +280,12 @@ struct StepBody {
     acc[2] += (double)pot;
     acc[3] += (double)r2 + (double)rx2 * (double)s0;
     acc[4] += (double)s1;
+    // FP32 arithmetic: keep this plane's sums here.  Without the pin the
+    // compiler sinks the reductions of every stage to the end of the
+    // unrolled trip, which keeps all their operands live at once (~90 more
+    // registers per lane).  FP64 kernels are compiled without it.
+    if constexpr (kPinSums)
+      asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]));
   }
 
   // Update plane X = xb + 6 i + SL of a work item whose planes live in rings
@@ -307,7 +323,10 @@ template <int DT, int VZ, int RY, bool UPD, int D, int BT, bool FV = false, int 
           bool FENCE = false>
 __device__ __forceinline__ void run_item(const StepArgs& A, const Item& item, int src,
                                          double (&s_red)[BT / 64][5], int& s_last) {
-  using Body = StepBody<DT, VZ, RY, UPD, FV, OUT>;
+  // BF16 states: branch-free plane resources (in-kernel V, sums pinned: 512^3
+  // 225.7 -> 221.4 us, 256^3 36.7 -> 34.9 us per step); FP32 states keep the
+  // branch form (in-kernel V at 512^3: 215 us with it, 260 us without)
+  using Body = StepBody<DT, VZ, RY, UPD, FV, OUT, DT == kBF16>;
   using S = typename Body::S;
   using TV = typename Body::TV;
   using C = typename Body::C;
