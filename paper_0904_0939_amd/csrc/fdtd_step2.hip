@@ -97,6 +97,28 @@ struct Step2 {
   // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
   // plane X - 1, then the work-group barrier.
+  // The y / z neighbours of the lane's own vector from an LDS plane, zero for
+  // a vector outside the lattice (its result, zero, is then the boundary
+  // value its neighbours read).  FP32 arithmetic only: the reads are
+  // unconditional and the zeros come from masks; written as selects of the
+  // reads, they become a branch around the reads with zero moves on the
+  // other path, in every stage (the FP64 kernel keeps that form).
+  static __device__ __forceinline__ void lds_nbrs(bool own, const C* p, int obase,
+                                                  PlaneIn<1, VZ, C>& d) {
+    static_assert(sizeof(C) == 4, "FP32 arithmetic");
+    const unsigned m = own ? 0xffffffffu : 0u;
+    const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(p + obase - RP);
+    const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(p + obase + RP);
+    const C zm = p[obase - 1], zp = p[obase + VZ];
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) {
+      d.ym[0][j] = __uint_as_float(__float_as_uint(pm.v[j]) & m);
+      d.yp[0][j] = __uint_as_float(__float_as_uint(pp.v[j]) & m);
+    }
+    d.zm[0] = __uint_as_float(__float_as_uint(zm) & m);
+    d.zp[0] = __uint_as_float(__float_as_uint(zp) & m);
+  }
+
   // Buffer of plane X (X >= -2) in the LDS tile of step-t results.
   static __device__ __forceinline__ int tbuf(int X) {
     return kTbLdsU ? (X + 3) % 3 : (X & 1);
@@ -139,23 +161,16 @@ struct Step2 {
     C* t = tile + tbuf(X) * TS;
     {
       // step t, own vectors: the work item's planes [xb, xe) count in the
-      // reductions, the halo planes xb - 1 and xe do not
-      double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      // reductions, the halo planes xb - 1 and xe do not.  FP32 arithmetic:
+      // the sums start from -0, so the first addition folds away (x + -0 = x)
+      constexpr double kZ = DT == kF64 ? 0.0 : -0.0;
+      double tmp[5] = {kZ, kZ, kZ, kZ, kZ};
       C un[1][VZ];
       if constexpr (kPsi) {
         // y / z neighbours of plane X from the LDS copy written last stage
         // (zero for a vector outside the lattice, as its loads would read)
-        const C* pp0 = ptile + (X & 1) * TS;
         PlaneIn<1, VZ, C> d;
-        const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(pp0 + obase - RP);
-        const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(pp0 + obase + RP);
-#pragma unroll
-        for (int j = 0; j < VZ; ++j) {
-          d.ym[0][j] = own ? pm.v[j] : C(0);
-          d.yp[0][j] = own ? pp.v[j] : C(0);
-        }
-        d.zm[0] = own ? pp0[obase - 1] : C(0);
-        d.zp[0] = own ? pp0[obase + VZ] : C(0);
+        lds_nbrs(own, ptile + (X & 1) * TS, obase, d);
         B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
                                                 g.qs[(SL + 2) % 6], g.vs[SL % 6], d, tmp, true, un);
       } else {
@@ -191,15 +206,19 @@ struct Step2 {
       // one-step kernel: its result is not stored, but it enters the norm.
       const C* tp = tile + tbuf(X - 1) * TS;
       PlaneIn<1, VZ, C> d;
-      const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase - RP);
-      const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase + RP);
+      if constexpr (DT == kF64) {
+        const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase - RP);
+        const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(tp + obase + RP);
 #pragma unroll
-      for (int j = 0; j < VZ; ++j) {
-        d.ym[0][j] = own ? pm.v[j] : C(0);
-        d.yp[0][j] = own ? pp.v[j] : C(0);
+        for (int j = 0; j < VZ; ++j) {
+          d.ym[0][j] = own ? pm.v[j] : C(0);
+          d.yp[0][j] = own ? pp.v[j] : C(0);
+        }
+        d.zm[0] = own ? tp[obase - 1] : C(0);
+        d.zp[0] = own ? tp[obase + VZ] : C(0);
+      } else {
+        lds_nbrs(own, tp, obase, d);
       }
-      d.zm[0] = own ? tp[obase - 1] : C(0);
-      d.zp[0] = own ? tp[obase + VZ] : C(0);
       if constexpr (kTbLdsU) {
         // planes X - 2, X - 1, X of the lane's own vector (X: written by this
         // lane in this stage, so no barrier is needed for it)

@@ -275,17 +275,19 @@ struct StepBody {
       }
       if constexpr (UPD && !TOREG) bstore<S, VZ, OUT>(ro, ln.off[r], o);
     }
-    acc[0] += (double)s0;
-    acc[1] += (double)kin;
-    acc[2] += (double)pot;
-    acc[3] += (double)r2 + (double)rx2 * (double)s0;
-    acc[4] += (double)s1;
-    // FP32 arithmetic: keep this plane's sums here.  Without the pin the
-    // compiler sinks the reductions of every stage to the end of the
-    // unrolled trip, which keeps all their operands live at once (~90 more
-    // registers per lane).  FP64 kernels are compiled without it.
-    if constexpr (kPinSums)
-      asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]));
+    if constexpr (NRED > 0) {
+      acc[0] += (double)s0;
+      acc[1] += (double)kin;
+      acc[2] += (double)pot;
+      acc[3] += (double)r2 + (double)rx2 * (double)s0;
+      acc[4] += (double)s1;
+      // FP32 arithmetic: keep this plane's sums here.  Without the pin the
+      // compiler sinks the reductions of every stage to the end of the
+      // unrolled trip, which keeps all their operands live at once (~90 more
+      // registers per lane).  FP64 kernels are compiled without it.
+      if constexpr (kPinSums)
+        asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]));
+    }
   }
 
   // Update plane X = xb + 6 i + SL of a work item whose planes live in rings
