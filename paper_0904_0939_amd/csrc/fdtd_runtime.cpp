@@ -401,13 +401,14 @@ long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
 // the CUs an item.  On a batch, items of uneven length are handed out longest
 // first and about two per CU balance best (64 lattices of side 48..160: 530
 // items of at most 128 planes 234 us, 374 whole-N items 258 us, 850 of 64
-// planes 244 us).  Two-step tiles: two per CU on FP32-arithmetic lattices,
-// whose two-step kernel runs two waves per SIMD (512^3 F32: 512 tiles of 256
-// planes 206 us per step, 256 of 512 planes 297 us), one per CU for FP64 (one
-// wave per SIMD: 433 against 441 us).
+// planes 244 us).  Two-step tiles: one per CU; a CU holds one 512-lane tile
+// of an FP32-arithmetic lattice (two waves per SIMD) or one 256-lane FP64
+// tile (one wave per SIMD: 433 against 441 us with two).  With 256-lane F32
+// tiles two per CU were best (512^3: 512 tiles of 256 planes 206 us per
+// step, 256 of 512 planes 297 us).
 int auto_xchunk(const fdtd_ctx* h, const fdtd_tuning& t) {
   const long long cu = std::max(1, h->n_cu);
-  const long long need = t.tblock == 2 ? (h->dtype == kF64 ? cu : 2 * cu)
+  const long long need = t.tblock == 2 ? (h->dtype == kF64 || kTbThreads(h->dtype) > 256 ? cu : 2 * cu)
                                        : (h->count > 1 ? 2 * cu : (4 * cu + 4) / 5);
   for (int xc : {512, 256, 128, 64, 32, 16}) {
     long long items = 0;

@@ -56,9 +56,9 @@ constexpr bool kTbLdsU = FDTD_TB_LDS_U != 0;
 constexpr int kTbTileBufs = kTbLdsU ? 3 : 2;
 
 // Waves per SIMD the two-step kernel's register budget must allow: two for
-// FP32 arithmetic (F32 and BF16 states: 195-215 VGPRs with the reductions
-// pinned per plane, and two tiles per CU hide each other's latency), one for
-// FP64 (two would spill about a hundred).
+// FP32 arithmetic (F32 and BF16 states: 200-225 VGPRs with the reductions
+// pinned per plane; a 512-lane tile per CU), one for FP64 (two would spill
+// about a hundred).
 #ifndef FDTD_TB_MIN_WAVES_F32
 #define FDTD_TB_MIN_WAVES_F32 2
 #endif
@@ -69,7 +69,7 @@ constexpr int tb_min_waves(int dt) { return dt == kF64 ? FDTD_TB_MIN_WAVES_F64 :
 
 template <int DT, int VZ, int D, bool FV>
 struct Step2 {
-  static constexpr int BT = 256;
+  static constexpr int BT = kTbThreads(DT);
   static constexpr int TZ = kTbCols(DT);            // tile columns (z sites)
   static constexpr int LPR = TZ / VZ;               // lanes per tile row
   static constexpr int TY = BT / LPR;               // tile rows
@@ -92,7 +92,81 @@ struct Step2 {
     C vh[6][1][1];
     PlaneIn<1, 1, C> nh[6];
     C us[kTbLdsU ? 1 : 3][1][VZ];  // step-t results, own vectors (register ring form)
+    // F32 states (kShare): the x-differences carried from plane to plane
+    // (step t, step t + 1), and B, dt V of the own vectors of the last two
+    // planes (written by step t, read by step t + 1 one plane later)
+    C dx1[VZ], dx2[VZ];
+    C bw[2][VZ], dw[2][VZ];
   };
+
+  // F32 states share work between neighbouring sites and between the two
+  // steps (update_tb); BF16 states sum the Laplacian without differences,
+  // FP64 keeps the one-step body as it is.
+  static constexpr bool kShare = DT == kF32 && !kTbLdsU;
+
+  // update_core's arithmetic for the lane's own vector (F32 states), bit for
+  // bit, with what a pass of two steps can share.  (1) A difference along x
+  // or z is computed once per pair of sites: the one a site takes towards
+  // x - 1 (z - 1) is the negation of the one its neighbour took towards
+  // x + 1 (z + 1), the same value in round to nearest (an exact zero may
+  // change sign, which no pair sum of the Laplacian keeps).  dxc carries
+  // q(x) - q(x - 1) in and q(x + 1) - q(x) out.  (2) Step t computes B =
+  // 1 / (1 + dt V / 2) and dt V of its own vectors and keeps them (BM = 1);
+  // step t + 1 takes them one plane later (BM = 2).  TOREG: return the new
+  // values (step t) instead of storing them (step t + 1).
+  template <bool TOREG, int BM>
+  static __device__ __forceinline__ void update_tb(const typename B::Ctx& k,
+                                                   const Lane<1, VZ, C>& ln, int x,
+                                                   const C (&pc)[VZ], const C (&pn)[VZ],
+                                                   C (&dxc)[VZ], const C (&vv)[VZ],
+                                                   const PlaneIn<1, VZ, C>& d, C (&bw)[VZ],
+                                                   C (&dw)[VZ], double (&acc)[5], C (&outv)[VZ]) {
+    static_assert(DT == kF32, "F32 states");
+    const double xc = (2.0 * x - k.cN) * k.ha;
+    const C rx2 = (C)(xc * xc);
+    C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
+    const C lo = d.zm[0] * (C)ln.zmask_lo[0];
+    const C hi = d.zp[0] * (C)ln.zmask_hi[0];
+    // zd[j]: site j's difference towards z - 1; zd[VZ]: the last site's
+    // towards z + 1
+    C zd[VZ + 1];
+    zd[0] = lo - pc[0];
+#pragma unroll
+    for (int j = 1; j < VZ; ++j) zd[j] = pc[j - 1] - pc[j];
+    zd[VZ] = hi - pc[VZ - 1];
+    Pack<C, VZ> o;
+#pragma unroll
+    for (int j = 0; j < VZ; ++j) {
+      const C p = pc[j];
+      const C dxm = -dxc[j];
+      const C dxp = pn[j] - p;
+      dxc[j] = dxp;
+      const C dzr = j < VZ - 1 ? -zd[j + 1] : zd[VZ];
+      const C lap = ((dxm + dxp) + ((d.ym[0][j] - p) + (d.yp[0][j] - p))) + (zd[j] + dzr);
+      const C p2 = p * p;
+      const C v = vv[j];
+      s0 += p2;
+      kin = fma_c(p, lap, kin);
+      pot = fma_c(v, p2, pot);
+      r2 = fma_c(ln.w2[0][j], p2, r2);
+      if constexpr (BM != 2) {
+        bw[j] = rcp_c(fma_c(k.eps, v, C(1)));
+        dw[j] = k.dt * v;
+      }
+      const C g = fma_c(k.c, lap, -(dw[j] * p));  // c lap - dt V psi
+      const C nv = k.sc * fma_c(bw[j], g, p);
+      o.v[j] = nv;
+      s1 = fma_c(nv, nv, s1);
+      if constexpr (TOREG) outv[j] = nv;
+    }
+    if constexpr (!TOREG) bstore<C, VZ, FDTD_AUX_OUT>(plane_rsrc(k.out, x, k.N, k.pbytes), ln.off[0], o);
+    acc[0] += (double)s0;
+    acc[1] += (double)kin;
+    acc[2] += (double)pot;
+    acc[3] += (double)r2 + (double)rx2 * (double)s0;
+    acc[4] += (double)s1;
+    asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]));
+  }
 
   // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
@@ -171,8 +245,14 @@ struct Step2 {
         // (zero for a vector outside the lattice, as its loads would read)
         PlaneIn<1, VZ, C> d;
         lds_nbrs(own, ptile + (X & 1) * TS, obase, d);
-        B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
-                                                g.qs[(SL + 2) % 6], g.vs[SL % 6], d, tmp, true, un);
+        if constexpr (kShare) {
+          update_tb<true, 1>(kb, lb, X, g.qs[(SL + 1) % 6][0], g.qs[(SL + 2) % 6][0], g.dx1,
+                             g.vs[SL % 6][0], d, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
+        } else {
+          B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
+                                                  g.qs[(SL + 2) % 6], g.vs[SL % 6], d, tmp, true,
+                                                  un);
+        }
       } else {
         B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
                                                 g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
@@ -233,6 +313,11 @@ struct Step2 {
           u2[0][j] = a2.v[j];
         }
         B::template update<false>(k2, lb, X - 1, u0, u1, u2, g.vs[(SL + 5) % 6], d, acc2);
+      } else if constexpr (kShare) {
+        C unused[VZ];
+        update_tb<false, 2>(k2, lb, X - 1, g.us[(SL + 2) % 3][0], g.us[SL % 3][0], g.dx2,
+                            g.vs[(SL + 5) % 6][0], d, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2], acc2,
+                            unused);
       } else {
         B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
                                   g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
@@ -284,13 +369,13 @@ template <int DT, int VZ, int D, bool FV, bool FENCE>
 __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int src,
                                         typename Step2<DT, VZ, D, FV>::C* tile,
                                         typename Step2<DT, VZ, D, FV>::C* ptile,
-                                        double (&s_red)[256 / 64][5], int& s_last) {
+                                        double (&s_red)[kTbThreads(DT) / 64][5], int& s_last) {
   using T = Step2<DT, VZ, D, FV>;
   using B = typename T::B;
   using H = typename T::H;
   using C = typename T::C;
   using TV = typename B::TV;
-  constexpr int BT = 256;
+  constexpr int BT = kTbThreads(DT);
   constexpr unsigned kES = sizeof(typename B::S);
   const int tid = threadIdx.x;
   // the waves that carry halo sites (uniform per wave)
@@ -392,9 +477,19 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
 #define FDTD_STAGE2(SL, S2, XX)                                                                  \
   T::template stage<SL, S2>(kb, kh, k2, lb, lh, own, halo_wave, obase, hidx, XX, xb, xe,         \
                             (unsigned)N, tile, ptile, g, acc1, acc2)
+    // the x-difference step t carries into plane base: q(base) - q(base - 1)
+    if constexpr (T::kShare) {
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) g.dx1[j] = g.qs[1][0][j] - g.qs[0][0][j];
+    }
     // planes xb - 1 and xb: step t only; then both steps, six stages a trip
     FDTD_STAGE2(0, false, base);
     FDTD_STAGE2(1, false, base + 1);
+    // the x-difference step t + 1 carries into plane xb: u(xb) - u(xb - 1)
+    if constexpr (T::kShare) {
+#pragma unroll
+      for (int j = 0; j < VZ; ++j) g.dx2[j] = g.us[1][0][j] - g.us[0][0][j];
+    }
     int X = xb + 1;
     for (; X + 6 <= xe + 1; X += 6) {
       FDTD_STAGE2(2, true, X);
@@ -459,11 +554,11 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
 }
 
 template <int DT, int VZ, int D, bool FV>
-__global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2(StepArgs A) {
+__global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2(StepArgs A) {
   using T = Step2<DT, VZ, D, FV>;
   __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
   __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
-  __shared__ double s_red[256 / 64][5];
+  __shared__ double s_red[kTbThreads(DT) / 64][5];
   __shared__ int s_last;
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
     tb_item<DT, VZ, D, FV, false>(A, A.items[A.item_offset + li], A.src, tile, ptile, s_red,
@@ -481,11 +576,11 @@ __global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2(StepArgs A) {
 // them.  Per-tile arithmetic, partial slots and summation order are those of
 // k_step2: the same bits as one launch per pass.
 template <int DT, int VZ, int D, bool FV>
-__global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2_persist(StepArgs A) {
+__global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2_persist(StepArgs A) {
   using T = Step2<DT, VZ, D, FV>;
   __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
   __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
-  __shared__ double s_red[256 / 64][5];
+  __shared__ double s_red[kTbThreads(DT) / 64][5];
   __shared__ int s_last;
   __shared__ int s_tk;
   const int tid = threadIdx.x;
@@ -522,9 +617,9 @@ __global__ __launch_bounds__(256, tb_min_waves(DT)) void k_step2_persist(StepArg
 template <int DT, int D, bool FV>
 hipError_t step2_one(int grid, bool persist, const StepArgs& a, hipStream_t s) {
   if (persist)
-    hipLaunchKernelGGL((k_step2_persist<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_step2_persist<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(kTbThreads(DT)), 0, s, a);
   else
-    hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(kTbThreads(DT)), 0, s, a);
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.
 
 # (dtype, N, potential, xchunk, depth, vfuse): tiles ragged in y and z,
 # several x-ranges per lattice, the in-kernel potential, and sides beyond
-# 256 vz (F32 tiles are 32 x 32 sites, F64 16 x 32)
+# 256 vz (F32 and BF16 tiles are 32 x 64 sites, F64 16 x 32)
 CASES = [
     ("f32", 40, "cornell", 0, 1, 0),
     ("f32", 64, "ho", 8, 2, 0),
