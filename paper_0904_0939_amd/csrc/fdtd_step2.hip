@@ -78,6 +78,10 @@ struct Step2 {
   static constexpr int RP = TZ + 8;                 // LDS row pitch: own z at 4 .. 4 + TZ - 1
   static constexpr int TS = (TY + 2) * RP;          // LDS plane: rows y0 - 1 .. y0 + TY
   static constexpr bool kPsi = tb_lds_psi(DT);       // neighbours of step t from LDS
+  // register rings: RS plane slots (an unrolled trip of RS stages; a load
+  // D planes ahead needs D + 3 slots), US slots of step-t results
+  static constexpr int RS = D <= 3 ? 6 : 8;
+  static constexpr int US = D <= 3 ? 3 : 4;
   static_assert(TY == kTbRows(DT) && TZ % VZ == 0, "tile shape");
   static_assert(NH <= BT, "one halo site per lane");
   using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
@@ -85,13 +89,13 @@ struct Step2 {
   using C = typename B::C;
 
   struct Rings {
-    C qs[6][1][VZ];          // psi_t of planes, own vectors
-    C vs[6][1][VZ];          // V of planes
-    PlaneIn<1, VZ, C> nb[6]; // y / z neighbours of psi_t planes
-    C qh[6][1][1];           // the same for the lane's halo site
-    C vh[6][1][1];
-    PlaneIn<1, 1, C> nh[6];
-    C us[kTbLdsU ? 1 : 3][1][VZ];  // step-t results, own vectors (register ring form)
+    C qs[RS][1][VZ];          // psi_t of planes, own vectors
+    C vs[RS][1][VZ];          // V of planes
+    PlaneIn<1, VZ, C> nb[RS]; // y / z neighbours of psi_t planes
+    C qh[RS][1][1];           // the same for the lane's halo site
+    C vh[RS][1][1];
+    PlaneIn<1, 1, C> nh[RS];
+    C us[kTbLdsU ? 1 : US][1][VZ];  // step-t results, own vectors (register ring form)
     // F32 states (kShare): the x-differences carried from plane to plane
     // (step t, step t + 1), and B, dt V of the own vectors of the last two
     // planes (written by step t, read by step t + 1 one plane later)
@@ -168,7 +172,7 @@ struct Step2 {
     asm volatile("" : "+v"(acc[0]), "+v"(acc[1]), "+v"(acc[2]), "+v"(acc[3]), "+v"(acc[4]));
   }
 
-  // Stage X (slot SL = (X - base) % 6, base = xb - 1): prefetch, step t at
+  // Stage X (slot SL = (X - base) % RS, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
   // plane X - 1, then the work-group barrier.
   // The y / z neighbours of the lane's own vector from an LDS plane, zero for
@@ -207,9 +211,9 @@ struct Step2 {
     C* p = ptile + ((X + 1) & 1) * TS;
     Pack<C, VZ> pk;
 #pragma unroll
-    for (int j = 0; j < VZ; ++j) pk.v[j] = g.qs[(SL + 2) % 6][0][j];
+    for (int j = 0; j < VZ; ++j) pk.v[j] = g.qs[(SL + 2) % RS][0][j];
     *reinterpret_cast<Pack<C, VZ>*>(p + obase) = pk;
-    if (halo_wave && (int)threadIdx.x < NH) p[hidx] = g.qh[(SL + 2) % 6][0][0];
+    if (halo_wave && (int)threadIdx.x < NH) p[hidx] = g.qh[(SL + 2) % RS][0][0];
   }
 
   template <int SL, bool STEP2>
@@ -221,13 +225,13 @@ struct Step2 {
                                                int X, int xb, int xe, unsigned N, C* tile,
                                                C* ptile, Rings& g, double (&acc1)[5],
                                                double (&acc2)[5]) {
-    B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % 6]);
-    B::template fetch_v<kTbVAux>(kb, lb, X + D, g.vs[(SL + D) % 6]);
-    if constexpr (!kPsi) B::fetch(kb, lb, X + D, g.nb[(SL + D) % 6]);
+    B::fetch_own(kb, lb, X + 1 + D, g.qs[(SL + 2 + D) % RS]);
+    B::template fetch_v<kTbVAux>(kb, lb, X + D, g.vs[(SL + D) % RS]);
+    if constexpr (!kPsi) B::fetch(kb, lb, X + D, g.nb[(SL + D) % RS]);
     if (halo_wave) {
-      H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % 6]);
-      H::template fetch_v<kTbVAux>(kh, lh, X + D, g.vh[(SL + D) % 6]);
-      H::fetch(kh, lh, X + D, g.nh[(SL + D) % 6]);
+      H::fetch_own(kh, lh, X + 1 + D, g.qh[(SL + 2 + D) % RS]);
+      H::template fetch_v<kTbVAux>(kh, lh, X + D, g.vh[(SL + D) % RS]);
+      H::fetch(kh, lh, X + D, g.nh[(SL + D) % RS]);
     }
     // planes -1 and N lie outside the lattice: psi_{t+1} = 0 there (the
     // one-step kernel drops their stores; here they feed step t + 1)
@@ -246,16 +250,16 @@ struct Step2 {
         PlaneIn<1, VZ, C> d;
         lds_nbrs(own, ptile + (X & 1) * TS, obase, d);
         if constexpr (kShare) {
-          update_tb<true, 1>(kb, lb, X, g.qs[(SL + 1) % 6][0], g.qs[(SL + 2) % 6][0], g.dx1,
-                             g.vs[SL % 6][0], d, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
+          update_tb<true, 1>(kb, lb, X, g.qs[(SL + 1) % RS][0], g.qs[(SL + 2) % RS][0], g.dx1,
+                             g.vs[SL % RS][0], d, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
         } else {
-          B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
-                                                  g.qs[(SL + 2) % 6], g.vs[SL % 6], d, tmp, true,
+          B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % RS], g.qs[(SL + 1) % RS],
+                                                  g.qs[(SL + 2) % RS], g.vs[SL % RS], d, tmp, true,
                                                   un);
         }
       } else {
-        B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % 6], g.qs[(SL + 1) % 6],
-                                                g.qs[(SL + 2) % 6], g.vs[SL % 6], g.nb[SL % 6],
+        B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % RS], g.qs[(SL + 1) % RS],
+                                                g.qs[(SL + 2) % RS], g.vs[SL % RS], g.nb[SL % RS],
                                                 tmp, true, un);
       }
       if (X >= xb && X < xe) {
@@ -266,7 +270,7 @@ struct Step2 {
 #pragma unroll
       for (int j = 0; j < VZ; ++j) {
         pk.v[j] = inx ? un[0][j] : C(0);
-        if constexpr (!kTbLdsU) g.us[SL % 3][0][j] = pk.v[j];
+        if constexpr (!kTbLdsU) g.us[SL % US][0][j] = pk.v[j];
       }
       *reinterpret_cast<Pack<C, VZ>*>(t + obase) = pk;
     }
@@ -274,8 +278,8 @@ struct Step2 {
       // step t, halo site (no reductions: another work item owns it)
       double tmp[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       C uh[1][1];
-      H::template update_core<false, true, 0>(kh, lh, X, g.qh[SL % 6], g.qh[(SL + 1) % 6],
-                                              g.qh[(SL + 2) % 6], g.vh[SL % 6], g.nh[SL % 6],
+      H::template update_core<false, true, 0>(kh, lh, X, g.qh[SL % RS], g.qh[(SL + 1) % RS],
+                                              g.qh[(SL + 2) % RS], g.vh[SL % RS], g.nh[SL % RS],
                                               tmp, true, uh);
       if ((int)threadIdx.x < NH) t[hidx] = inx ? uh[0][0] : C(0);
     }
@@ -312,15 +316,15 @@ struct Step2 {
           u1[0][j] = a1.v[j];
           u2[0][j] = a2.v[j];
         }
-        B::template update<false>(k2, lb, X - 1, u0, u1, u2, g.vs[(SL + 5) % 6], d, acc2);
+        B::template update<false>(k2, lb, X - 1, u0, u1, u2, g.vs[(SL + RS - 1) % RS], d, acc2);
       } else if constexpr (kShare) {
         C unused[VZ];
-        update_tb<false, 2>(k2, lb, X - 1, g.us[(SL + 2) % 3][0], g.us[SL % 3][0], g.dx2,
-                            g.vs[(SL + 5) % 6][0], d, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2], acc2,
+        update_tb<false, 2>(k2, lb, X - 1, g.us[(SL + US - 1) % US][0], g.us[SL % US][0], g.dx2,
+                            g.vs[(SL + RS - 1) % RS][0], d, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2], acc2,
                             unused);
       } else {
-        B::template update<false>(k2, lb, X - 1, g.us[(SL + 1) % 3], g.us[(SL + 2) % 3],
-                                  g.us[SL % 3], g.vs[(SL + 5) % 6], d, acc2);
+        B::template update<false>(k2, lb, X - 1, g.us[(SL + US - 2) % US], g.us[(SL + US - 1) % US],
+                                  g.us[SL % US], g.vs[(SL + RS - 1) % RS], d, acc2);
       }
     }
     if constexpr (kPsi) stage_psi<SL>(halo_wave, obase, hidx, X, ptile, g);
@@ -471,7 +475,7 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
     }
     if constexpr (T::kPsi) {
       // the LDS copy of plane base (slot 1), read by the first stage
-      T::template stage_psi<5>(halo_wave, obase, hidx, base - 1, ptile, g);
+      T::template stage_psi<T::RS - 1>(halo_wave, obase, hidx, base - 1, ptile, g);
       lds_barrier();
     }
 #define FDTD_STAGE2(SL, S2, XX)                                                                  \
@@ -491,19 +495,40 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
       for (int j = 0; j < VZ; ++j) g.dx2[j] = g.us[1][0][j] - g.us[0][0][j];
     }
     int X = xb + 1;
-    for (; X + 6 <= xe + 1; X += 6) {
-      FDTD_STAGE2(2, true, X);
-      FDTD_STAGE2(3, true, X + 1);
-      FDTD_STAGE2(4, true, X + 2);
-      FDTD_STAGE2(5, true, X + 3);
-      FDTD_STAGE2(0, true, X + 4);
-      FDTD_STAGE2(1, true, X + 5);
+    if constexpr (T::RS == 6) {
+      for (; X + 6 <= xe + 1; X += 6) {
+        FDTD_STAGE2(2, true, X);
+        FDTD_STAGE2(3, true, X + 1);
+        FDTD_STAGE2(4, true, X + 2);
+        FDTD_STAGE2(5, true, X + 3);
+        FDTD_STAGE2(0, true, X + 4);
+        FDTD_STAGE2(1, true, X + 5);
+      }
+      if (X <= xe) FDTD_STAGE2(2, true, X);
+      if (X + 1 <= xe) FDTD_STAGE2(3, true, X + 1);
+      if (X + 2 <= xe) FDTD_STAGE2(4, true, X + 2);
+      if (X + 3 <= xe) FDTD_STAGE2(5, true, X + 3);
+      if (X + 4 <= xe) FDTD_STAGE2(0, true, X + 4);
+    } else {
+      static_assert(T::RS == 8, "ring of 6 or 8 slots");
+      for (; X + 8 <= xe + 1; X += 8) {
+        FDTD_STAGE2(2, true, X);
+        FDTD_STAGE2(3, true, X + 1);
+        FDTD_STAGE2(4, true, X + 2);
+        FDTD_STAGE2(5, true, X + 3);
+        FDTD_STAGE2(6, true, X + 4);
+        FDTD_STAGE2(7, true, X + 5);
+        FDTD_STAGE2(0, true, X + 6);
+        FDTD_STAGE2(1, true, X + 7);
+      }
+      if (X <= xe) FDTD_STAGE2(2, true, X);
+      if (X + 1 <= xe) FDTD_STAGE2(3, true, X + 1);
+      if (X + 2 <= xe) FDTD_STAGE2(4, true, X + 2);
+      if (X + 3 <= xe) FDTD_STAGE2(5, true, X + 3);
+      if (X + 4 <= xe) FDTD_STAGE2(6, true, X + 4);
+      if (X + 5 <= xe) FDTD_STAGE2(7, true, X + 5);
+      if (X + 6 <= xe) FDTD_STAGE2(0, true, X + 6);
     }
-    if (X <= xe) FDTD_STAGE2(2, true, X);
-    if (X + 1 <= xe) FDTD_STAGE2(3, true, X + 1);
-    if (X + 2 <= xe) FDTD_STAGE2(4, true, X + 2);
-    if (X + 3 <= xe) FDTD_STAGE2(5, true, X + 3);
-    if (X + 4 <= xe) FDTD_STAGE2(0, true, X + 4);
 #undef FDTD_STAGE2
 
     // ---- partials of both steps; the member's last work-group finalises them
@@ -629,6 +654,9 @@ hipError_t step2_depth(int depth, int grid, bool persist, const StepArgs& a, hip
     case 1: return step2_one<DT, 1, FV>(grid, persist, a, s);
     case 2: return step2_one<DT, 2, FV>(grid, persist, a, s);
     case 3: return step2_one<DT, 3, FV>(grid, persist, a, s);
+    case 4:  // FP32-arithmetic lattices only (a ring of 8 plane slots)
+      if constexpr (DT != kF64) return step2_one<DT, 4, FV>(grid, persist, a, s);
+      else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }

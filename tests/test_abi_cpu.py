@@ -129,6 +129,25 @@ def test_tuning_validation_is_host_side():
         F.fdtd_destroy(h)
 
 
+def test_depth_four_is_for_two_step_passes_of_fp32_arithmetic_states():
+    """depth 4 (an 8-slot register ring) exists for the two-step pass of F32
+    and BF16 states only: one-step shapes and F64 handles refuse it."""
+    f32 = F.fdtd_create(cfg(N=64, dtype=F.F32))
+    f64 = F.fdtd_create(cfg(N=64, dtype=F.F64))
+    try:
+        ok = F.fdtd_tuning(4, 1, 0, 0, 1, 4, 0, 0, 0, 2)
+        F.fdtd_set_tuning(f32, ok)
+        assert F.fdtd_get_tuning(f32).depth == 4
+        one_step = F.fdtd_tuning(4, 1, 0, 0, 1, 4, 0, 0, 0, 0)
+        assert status_of("fdtd_set_tuning", f32, C.byref(one_step)) == F.EINVAL
+        assert "depth 4" in F.fdtd_last_error()
+        for bad in (F.fdtd_tuning(2, 1, 0, 0, 1, 4, 0, 0, 0, 2), F.fdtd_tuning(4, 1, 0, 0, 1, 5, 0, 0, 0, 2)):
+            assert status_of("fdtd_set_tuning", f64 if bad.depth == 4 else f32, C.byref(bad)) == F.EINVAL
+    finally:
+        F.fdtd_destroy(f32)
+        F.fdtd_destroy(f64)
+
+
 def test_write_through_variant_rules_and_default():
     """variant 3 (variant 0 with written-through stores): full vectors, ry <=
     2, no persistence; the default for a single lattice whose two state

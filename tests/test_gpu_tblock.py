@@ -39,7 +39,9 @@ def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.
     s = Solver(N, L, dtype=dtype)
     s.set_potential(*POT[pot])
     s.set_initial(seed)
-    s.set_tuning(VW[dtype], 1, xchunk, 0, 1, depth, 0, 0, vfuse, tblock)
+    # one-step launches prefetch at most 3 planes (depth 4 is the two-step pass's)
+    s.set_tuning(VW[dtype], 1, xchunk, 0, 1, depth if tblock == 2 else min(depth, 3), 0, 0,
+                 vfuse, tblock)
     s.evolve(steps, renorm_every=renorm, use_graph=graph)
     out = (s.state(), s.observables()[0], s.history(0, steps))
     s.close()
@@ -58,6 +60,10 @@ CASES = [
     ("f64", 300, "cornell", 32, 1, 0),
     ("bf16", 64, "cornell", 0, 2, 0),
     ("bf16", 96, "ho", 24, 3, 1),
+    # prefetch depth 4 (an 8-slot ring): whole trips, every tail length
+    ("f32", 72, "cornell", 0, 4, 0),
+    ("f32", 100, "ho", 30, 4, 1),
+    ("bf16", 64, "cornell", 0, 4, 1),
 ]
 
 
