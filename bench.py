@@ -740,6 +740,18 @@ def main():
                     "tuning": s.tuning(),
                     "note": "the same steps (V table) with two steps per pass over HBM "
                             "(tblock = 2); the rescale then follows every second step"}
+        if args.dtype == "f32":
+            # the library's default potential source for analytic kinds: V
+            # evaluated in the kernel (8 B per site and pass), prefetch depth 4
+            s.set_tuning(vw, 1, 0, 0, 1, 4, 0, 0, 1, 2)
+            ms_2v = timed(args.steps, args.warmup)[0] / args.steps
+            note(f"two steps per pass, in-kernel potential: {ms_2v:.4f} ms/step")
+            two_step["in_kernel_v"] = {
+                "ms_per_step": ms_2v, "site_updates_per_s": sites / (ms_2v * 1e-3),
+                "hbm_bytes_per_site_step": 4.0,
+                "achieved_GBs": 4.0 * sites / (ms_2v * 1e-3) / 1e9,
+                "frac_of_hbm_peak": 4.0 * sites / (ms_2v * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "tuning": s.tuning()}
     out = {
         "metric": METRIC,
         "value": rate,

@@ -1568,8 +1568,10 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
         go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 1});
       }
     // two steps per pass (validation drops the shapes it does not cover),
-    // one launch per pass or (batches) persistent passes
-    for (int xc : {0, 32, 64, 128, 256})
+    // one launch per pass or (batches) persistent passes; the x-chunks
+    // between 64 and 128 matter on batches (64 lattices of side 48..160,
+    // depth 4: x-chunk 64 151.1 us per step, 80 140.7, 96 147.4)
+    for (int xc : {0, 32, 64, 80, 96, 128, 256})
       for (int depth : {1, 2, 3, 4})
         for (int persist : persists) {
           if (!go || xc > maxN || !all_div || (depth == 4 && h->dtype == kF64)) continue;
