@@ -107,16 +107,17 @@ def test_bounded_wait_reports_an_error():
     assert s.observables()[0]["step"] == 16
 
 
-@pytest.mark.parametrize("passes,steps,graph", [(5, 150, True), (64, 151, False), (1, 40, True)])
-def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps, graph):
+@pytest.mark.parametrize("passes,steps,graph,depth", [(5, 150, True, 2), (64, 151, False, 2),
+                                                     (1, 40, True, 2), (8, 97, True, 4)])
+def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps, graph, depth):
     """Persistent two-step passes (tblock 2 with persist = passes per launch):
     the same bits, histories and observables as one launch per pass of the
     same tiles, odd step counts included (the last step runs alone)."""
-    say(f"case: persistent two-step batch passes={passes} steps={steps} graph={graph}")
+    say(f"case: persistent two-step batch passes={passes} steps={steps} graph={graph} depth={depth}")
     out = []
     for persist in (0, passes):
         b, lats = make_batch()
-        b.set_tuning(4, 1, 0, 0, 1, 2, 0, persist, 1, 2)
+        b.set_tuning(4, 1, 0, 0, 1, depth, 0, persist, 1, 2)
         b.evolve(steps, use_graph=graph)
         out.append(([b.state(m) for m in range(len(lats))],
                     [b.history(m, steps) for m in range(len(lats))], b.observables()))
@@ -127,16 +128,16 @@ def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps,
     assert out[0][2] == out[1][2]
 
 
-@pytest.mark.parametrize("dtype", ["f64", "bf16"])
-def test_single_lattice_persistent_two_step_equals_per_pass(dtype):
-    say(f"case: persistent two-step single {dtype}")
-    vz = {"f64": 2, "bf16": 8}[dtype]
+@pytest.mark.parametrize("dtype,depth", [("f64", 2), ("bf16", 2), ("f32", 4)])
+def test_single_lattice_persistent_two_step_equals_per_pass(dtype, depth):
+    say(f"case: persistent two-step single {dtype} depth={depth}")
+    vz = {"f64": 2, "bf16": 8, "f32": 4}[dtype]
     out = []
     for persist in (0, 8):
         s = Solver(72, 10.0, dtype=dtype)
         s.set_potential(F.POT_CORNELL, W.CORNELL_PARAMS)
         s.set_initial(2, parity=W.parity_word(z=2))
-        s.set_tuning(vz, 1, 0, 0, 1, 2, 0, persist, 1, 2)
+        s.set_tuning(vz, 1, 0, 0, 1, depth, 0, persist, 1, 2)
         s.evolve(61)
         out.append((s.state(), s.observables()[0]))
         s.close()
