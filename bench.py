@@ -253,21 +253,21 @@ def plain_fp32_to_e(e_star, N=512, max_s=30.0):
 
 
 def multires_to_e(e_star, N_levels=(128, 256, 512), coarse_steps=(3000, 6000), max_s=75.0,
-                  seed=None):
+                  seed=None, coarse_dtype="bf16"):
     """The multi-resolution chain on the Cornell lattice: BF16 storage on the
     coarse levels, each relaxed for a fixed number of steps (an energy-change
     test cannot stop them: stochastic rounding makes the BF16 energy jitter by
     ~1e-4 relative from check to check), trilinear reseeding, FP32 on the
     finest level, run until E is within 1e-6 of e_star.  The budgets, 3000
     steps at 128^3 (20.6 time units) and 6000 at 256^3 (10.3), had the best
-    mean over three noise seeds.  Returns the finest level's rows and a
-    per-level log."""
+    mean over three noise seeds.  coarse_dtype "f32": the same chain in FP32
+    on every level.  Returns the finest level's rows and a per-level log."""
     from paper_0904_0939_amd import fdtd as F
     from paper_0904_0939_amd import workloads as W
     from paper_0904_0939_amd.solver import Solver
 
     K = 100
-    dtypes = ["bf16"] * (len(N_levels) - 1) + ["f32"]
+    dtypes = [coarse_dtype] * (len(N_levels) - 1) + ["f32"]
     t0 = _timer()
     prev = None
     rows = []
@@ -331,6 +331,9 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
         rows, _ = multires_to_e(e_star, N_levels, coarse_steps, max_plain_s, seed=sd)
         held_out[sd] = _first_within(rows, e_star, 1e-6)[0]
     note(f"multi-resolution chain, held-out seeds: {held_out}")
+    # the same chain with FP32 storage on the coarse levels too
+    multi32, _ = multires_to_e(e_star, N_levels, coarse_steps, max_plain_s, coarse_dtype="f32")
+    t_multi32, _ = _first_within(multi32, e_star, 1e-6)
     p32 = plain_fp32_to_e(e_star, N_levels[-1])
     note(f"plain FP32 to E: {len(p32)} checks")
     t_p32, n_p32 = _first_within(p32, e_star, 1e-6)
@@ -349,6 +352,8 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
         "speedup_worst_held_out": (t_plain / max(held_out.values()))
         if (t_plain and all(held_out.values())) else None,
         "plain_fp32_seconds": t_p32, "plain_fp32_steps": n_p32,
+        "multires_fp32_coarse_seconds": t_multi32,
+        "speedup_fp32_coarse": (t_plain / t_multi32) if (t_plain and t_multi32) else None,
     }
 
 
