@@ -276,10 +276,13 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned off, c
 // Branch-free: Inf keeps its all-zero low half, so adding r16 < 2^16 leaves
 // it Inf; a NaN magnitude is first replaced by the quiet NaN 0x7fc00000,
 // which the addition cannot carry out of the NaN range.
-__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t r16) {
+// Returns the rounded value as an FP32 bit pattern whose low 16 bits are
+// zero: the high half is the BF16 value, and the whole is its FP32 value, so
+// the stored bits and the value the norm sums come from one mask-and-or.
+__device__ __forceinline__ uint32_t f32_to_bf16_sr_bits(float f, uint32_t r16) {
   const uint32_t u = __float_as_uint(f);
   const uint32_t mag = min(u & 0x7fffffffu, 0x7fc00000u);
-  return (uint16_t)(((u & 0x80000000u) | (mag + r16)) >> 16);
+  return ((mag + r16) & 0x7fff0000u) | (u & 0x80000000u);
 }
 
 // 32-bit integer hash (lowbias32, C. Wellons): random bits of the rounding.

@@ -263,12 +263,18 @@ struct StepBody {
           const C B = rcp_c(fma_c(k.eps, v, C(1)));
           const C g = fma_c(k.c, lap, -((k.dt * v) * p));  // c lap - dt V psi
           const C nv = k.sc * fma_c(B, g, p);
+          C od;
           if constexpr (sizeof(S) == 2) {
-            o.v[j] = f32_to_bf16_sr((float)nv, rb[j]);
+            uint32_t ob = f32_to_bf16_sr_bits((float)nv, rb[j]);
+            // one register for the stored bits and the value the norm sums
+            // (else both are built, by two different instructions)
+            asm volatile("" : "+v"(ob));
+            o.v[j] = (S)(ob >> 16);
+            od = __uint_as_float(ob);
           } else {
             o.v[j] = (S)nv;
+            od = to_c<S, C>(o.v[j]);
           }
-          const C od = to_c<S, C>(o.v[j]);
           if (r < NRED) s1 = live ? fma_c(od, od, s1) : s1;
           if constexpr (TOREG) outv[r][j] = od;
         }
