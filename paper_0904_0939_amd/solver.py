@@ -238,12 +238,14 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
              max_steps: Sequence[int] = (200000,), check_every: int = 100,
              dt_over_a2: float = 0.125, mass: float = 1.0, parity: int = 0,
              use_graph: bool = True, v_inf: float = 0.0, project: Optional[Dict] = None,
-             project_every: int = 10, keep: bool = False):
+             project_every: int = 10, keep: bool = False, two_step: bool = False):
     """Multi-resolution chain (Sec. VI): relax from noise on levels[0], then
     reseed each finer level by trilinear interpolation of the previous one.
     project: optional {N: [states]} projected out every project_every steps
     on level N (excited states, Sec. III).  keep: also return each level's
-    final state (FP32 device tensor) in a dict.  Returns (final Solver,
+    final state (FP32 device tensor) in a dict.  two_step: every level whose
+    side the dtype's vector width divides runs two steps per pass over HBM
+    (prefetch depth 4 for F32 states, 3 otherwise).  Returns (final Solver,
     per-level [(N, steps, converged)][, kept states])."""
     prev = None
     log = []
@@ -251,6 +253,10 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
     for i, N in enumerate(levels):
         s = Solver(N, L, mass=mass, dtype=dtypes[i], dt_over_a2=dt_over_a2, v_inf=v_inf)
         s.set_potential(kind, params)
+        vw = {"f32": 4, "f64": 2, "bf16": 8}[dtypes[i]]
+        if two_step and N % vw == 0:
+            s.set_tuning(vw, 1, 0, 0, 1, 4 if dtypes[i] == "f32" else 3, 0, 0,
+                         s.tuning()["vfuse"], 2)
         if prev is None:
             s.set_initial(seed, parity=parity)
         else:

@@ -173,13 +173,18 @@ def test_readout_conversions():
     assert np.abs(b16 - ref).max() <= 2.0 ** -8 * np.abs(ref).max()
 
 
-def test_multires_chain_reaches_the_oracle_ground_state():
+@pytest.mark.parametrize("two_step", [False, True])
+def test_multires_chain_reaches_the_oracle_ground_state(two_step):
     """BF16 16^3 -> FP32 32^3 (HO, L = 10): the chain's converged energy equals
-    the oracle's converged FP64 energy on 32^3 from noise."""
-    say("case: multires 16 -> 32")
+    the oracle's converged FP64 energy on 32^3 from noise, with one or two
+    steps per pass."""
+    say(f"case: multires 16 -> 32 two_step={two_step}")
     L = 10.0
     s, log = multires([16, 32], L, F.POT_HO, [1, 1, 1], ["bf16", "f32"], seed=3,
-                      rel_tol=(1e-5, 1e-8), max_steps=(4000, 40000), check_every=50)
+                      rel_tol=(1e-5, 1e-8), max_steps=(4000, 40000), check_every=50,
+                      two_step=two_step)
+    if two_step:
+        assert s.tuning()["tblock"] == 2 and s.tuning()["depth"] == 4
     assert [n for n, _, _ in log] == [16, 32]
     assert log[-1][2], log  # the FP32 level converged
     e = s.observables()[0]["energy"]
