@@ -123,14 +123,21 @@ struct Step2 {
                                                    const Lane<1, VZ, C>& ln, int x,
                                                    const C (&pc)[VZ], const C (&pn)[VZ],
                                                    C (&dxc)[VZ], const C (&vv)[VZ],
-                                                   const PlaneIn<1, VZ, C>& d, C (&bw)[VZ],
-                                                   C (&dw)[VZ], double (&acc)[5], C (&outv)[VZ]) {
+                                                   const PlaneIn<1, VZ, C>& d, bool own,
+                                                   C (&bw)[VZ], C (&dw)[VZ], double (&acc)[5],
+                                                   C (&outv)[VZ]) {
     static_assert(DT == kF32, "F32 states");
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
     C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
-    const C lo = d.zm[0] * (C)ln.zmask_lo[0];
-    const C hi = d.zp[0] * (C)ln.zmask_hi[0];
+    // d holds the LDS values unmasked.  Beyond the lattice's z ends they are
+    // the frame's or the outside lanes' zeros, so no z mask is needed.  A
+    // vector outside the lattice has psi = 0 (its loads read zeros) and takes
+    // c = 0: its result and its sums are +0 whatever its neighbours hold, as
+    // with zero neighbours
+    const C cl = own ? k.c : C(0);
+    const C lo = d.zm[0];
+    const C hi = d.zp[0];
     // zd[j]: site j's difference towards z - 1; zd[VZ]: the last site's
     // towards z + 1
     C zd[VZ + 1];
@@ -157,7 +164,7 @@ struct Step2 {
         bw[j] = rcp_c(fma_c(k.eps, v, C(1)));
         dw[j] = k.dt * v;
       }
-      const C g = fma_c(k.c, lap, -(dw[j] * p));  // c lap - dt V psi
+      const C g = fma_c(cl, lap, -(dw[j] * p));  // c lap - dt V psi
       const C nv = k.sc * fma_c(bw[j], g, p);
       o.v[j] = nv;
       s1 = fma_c(nv, nv, s1);
@@ -175,16 +182,18 @@ struct Step2 {
   // Stage X (slot SL = (X - base) % RS, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
   // plane X - 1, then the work-group barrier.
-  // The y / z neighbours of the lane's own vector from an LDS plane, zero for
-  // a vector outside the lattice (its result, zero, is then the boundary
-  // value its neighbours read).  FP32 arithmetic only: the reads are
-  // unconditional and the zeros come from masks; written as selects of the
-  // reads, they become a branch around the reads with zero moves on the
-  // other path, in every stage (the FP64 kernel keeps that form).
+  // The y / z neighbours of the lane's own vector from an LDS plane; with
+  // MASK, zero for a vector outside the lattice (its result, zero, is then the
+  // boundary value its neighbours read; F32 states skip the masks, see
+  // update_tb).  FP32 arithmetic only: the reads are unconditional and the
+  // zeros come from masks; written as selects of the reads, they become a
+  // branch around the reads with zero moves on the other path, in every stage
+  // (the FP64 kernel keeps that form).
+  template <bool MASK = true>
   static __device__ __forceinline__ void lds_nbrs(bool own, const C* p, int obase,
                                                   PlaneIn<1, VZ, C>& d) {
     static_assert(sizeof(C) == 4, "FP32 arithmetic");
-    const unsigned m = own ? 0xffffffffu : 0u;
+    const unsigned m = own || !MASK ? 0xffffffffu : 0u;
     const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(p + obase - RP);
     const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(p + obase + RP);
     const C zm = p[obase - 1], zp = p[obase + VZ];
@@ -248,10 +257,10 @@ struct Step2 {
         // y / z neighbours of plane X from the LDS copy written last stage
         // (zero for a vector outside the lattice, as its loads would read)
         PlaneIn<1, VZ, C> d;
-        lds_nbrs(own, ptile + (X & 1) * TS, obase, d);
+        lds_nbrs<!kShare>(own, ptile + (X & 1) * TS, obase, d);
         if constexpr (kShare) {
           update_tb<true, 1>(kb, lb, X, g.qs[(SL + 1) % RS][0], g.qs[(SL + 2) % RS][0], g.dx1,
-                             g.vs[SL % RS][0], d, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
+                             g.vs[SL % RS][0], d, own, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
         } else {
           B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % RS], g.qs[(SL + 1) % RS],
                                                   g.qs[(SL + 2) % RS], g.vs[SL % RS], d, tmp, true,
@@ -301,7 +310,7 @@ struct Step2 {
         d.zm[0] = own ? tp[obase - 1] : C(0);
         d.zp[0] = own ? tp[obase + VZ] : C(0);
       } else {
-        lds_nbrs(own, tp, obase, d);
+        lds_nbrs<!kShare>(own, tp, obase, d);
       }
       if constexpr (kTbLdsU) {
         // planes X - 2, X - 1, X of the lane's own vector (X: written by this
@@ -320,8 +329,8 @@ struct Step2 {
       } else if constexpr (kShare) {
         C unused[VZ];
         update_tb<false, 2>(k2, lb, X - 1, g.us[(SL + US - 1) % US][0], g.us[SL % US][0], g.dx2,
-                            g.vs[(SL + RS - 1) % RS][0], d, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2], acc2,
-                            unused);
+                            g.vs[(SL + RS - 1) % RS][0], d, own, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2],
+                            acc2, unused);
       } else {
         B::template update<false>(k2, lb, X - 1, g.us[(SL + US - 2) % US], g.us[(SL + US - 1) % US],
                                   g.us[SL % US], g.vs[(SL + RS - 1) % RS], d, acc2);
