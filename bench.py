@@ -601,9 +601,11 @@ def main():
     args = ap.parse_args()
     if args.summarize_rocprof:
         f, w, st = args.summarize_rocprof
-        tb = args.tuning.count(",") == 9 and args.tuning.split(",")[9].strip() == "2"
+        parts = [v.strip() for v in args.tuning.split(",")] if args.tuning else []
+        tb = len(parts) >= 10 and parts[9] == "2"
+        wide = len(parts) >= 11 and parts[10] == "1"
         summarize_rocprof(f, w, st if st != "-" else None,
-                          f"cornell{args.n}_{args.dtype}" + ("_tb2" if tb else ""),
+                          f"cornell{args.n}_{args.dtype}" + ("_tb2" if tb else "") + ("w" if wide else ""),
                           args.n ** 3, args.dtype)
         return
     if args.gpus != 1:
@@ -713,7 +715,7 @@ def main():
     cal = torch.empty((N, N, N), dtype=es, device="cuda")
     F.fdtd_get_state(s.h, 0, cal.data_ptr(), 1)
     del cal
-    key = f"cornell{N}_{args.dtype}" + ("_tb2" if tb else "")
+    key = f"cornell{N}_{args.dtype}" + ("_tb2" if tb else "") + ("w" if tun.get("tile", 0) == 1 else "")
     traffic = measured_traffic(key, sites)
     in_kernel_v = None
     if not args.no_extras and args.dtype != "f64":
@@ -733,7 +735,12 @@ def main():
     if not args.no_extras and args.dtype != "bf16":
         # temporal blocking: two steps per pass over HBM, (y, z) tiles
         vw = {"f32": 4, "f64": 2}[args.dtype]
-        s.set_tuning(vw, 1, 0, 0, 1, 3, 0, 0, 0, 2)
+        if args.dtype == "f32":
+            # V table: 16 x 128 tiles (half the frame's column sites, whose
+            # cache lines the L2s miss) and prefetch depth 4
+            s.set_tuning(vw, 1, 0, 0, 1, 4, 0, 0, 0, 2, 1)
+        else:
+            s.set_tuning(vw, 1, 0, 0, 1, 3, 0, 0, 0, 2)
         ms_2 = timed(args.steps, args.warmup)[0] / args.steps
         note(f"two steps per pass: {ms_2:.4f} ms/step")
         b_2 = BYTES_PER_SITE[args.dtype] / 2  # psi and V in, psi'' out, per two steps

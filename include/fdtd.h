@@ -208,9 +208,16 @@ typedef struct {
  *         per-site arithmetic; BF16: the same rounding bits); the reductions
  *         then differ only in their summation order (per tile instead of per
  *         flattened chunk; BF16 lanes also hold 4 sites instead of 8).  An odd
- *         remainder of steps runs one launch per step. */
+ *         remainder of steps runs one launch per step;
+ *  tile   two-step tile shape of F32 / BF16 states (tblock = 2; 0 otherwise):
+ *         0 (default) 32 x 64 sites, 1: 16 x 128.  The wide tile's frame has
+ *         half as many column sites (each its own cache line) and more row
+ *         sites (contiguous): fewer HBM bytes per pass, more arithmetic for the
+ *         frame.  It wins where the pass streams the V table from HBM, and
+ *         loses where the pass evaluates V itself or on small lattices; the
+ *         same bits either way. */
 typedef struct {
-  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse, tblock;
+  int32_t vz, ry, xchunk, grid, xcd_remap, depth, variant, persist, vfuse, tblock, tile;
 } fdtd_tuning;
 
 /* ---- lifetime -------------------------------------------------------------*/
@@ -406,7 +413,7 @@ fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen
 /* The autotuner's cache as a text file, so that a later process starts from
  * the shapes an earlier one measured.  One line per entry: the key (no
  * spaces; e.g. gfx950/256cu:1:512 for one F32 lattice of side 512), then the
- * ten fdtd_tuning fields in their declaration order; lines starting with '#'
+ * eleven fdtd_tuning fields in their declaration order; lines starting with '#'
  * are comments.
  * save: writes every entry of this process's cache to `path` (created or
  *   truncated).  EINVAL if the file cannot be written.

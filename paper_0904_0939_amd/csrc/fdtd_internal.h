@@ -106,25 +106,33 @@ enum DType { kF64 = 0, kF32 = 1, kBF16 = 2 };
 hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int grid, int bt,
                        bool fv, bool wt, const StepArgs& a, hipStream_t s);
 // Two steps per pass (temporal blocking, update only): work items
-// are tiles of kTbRows(dtype) x kTbCols(dtype) sites of the (y, z) plane,
-// whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype) sites
-// per lane (kTbThreads(dtype) lanes); depth 1..3; partials for 2 *
-// slot_stride slots.
+// are tiles of kTbRows(dtype, wide) x kTbCols(dtype, wide) sites of the (y, z)
+// plane, whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype)
+// sites per lane (kTbThreads(dtype) lanes); depth 1..4 (4: F32 / BF16);
+// partials for 2 * slot_stride slots.
 // persist: one persistent launch of a.steps passes (2 a.steps steps; `grid`
 // work-groups take (pass, tile) tickets, a tile of pass p waiting until its
 // member has finalised pass p - 1); launch_persist_reset must run first.
 // Lanes of a two-step work-group: 512 for FP32-arithmetic lattices (a 32 x
 // 64 tile: its one-site halo frame is 9% of its sites, against 16% for the
 // 16 x 64 tile of 256 lanes; 512^3 F32 197 -> 175 us per step), 256 for F64.
+// wide (F32 / BF16 only): 16 x 128 tiles instead of 32 x 64.  Their frame has
+// half as many column sites, each a separate cache line that an L2 can miss,
+// and more row sites, which are contiguous: fewer HBM bytes per pass (a 512^3
+// F32 pass with the V table 176 -> 160 us per step at depth 4), but 288 halo
+// sites on five waves instead of 192 on three (more arithmetic: slower where
+// the pass is bound by it, as with the in-kernel potential).
 #ifndef FDTD_TB_THREADS_F32
 #define FDTD_TB_THREADS_F32 512
 #endif
 constexpr int kTbThreads(int dtype) { return dtype == kF64 ? 256 : FDTD_TB_THREADS_F32; }  // lanes
 constexpr int kTbVec(int dtype) { return dtype == kF64 ? 2 : 4; }  // sites per lane
-constexpr int kTbCols(int dtype) { return dtype == kF64 ? 32 : 64; }
-constexpr int kTbRows(int dtype) { return kTbThreads(dtype) * kTbVec(dtype) / kTbCols(dtype); }
-hipError_t launch_step2(int dtype, int depth, bool fv, int grid, bool persist, const StepArgs& a,
-                        hipStream_t s);
+constexpr int kTbCols(int dtype, bool wide = false) { return dtype == kF64 ? 32 : (wide ? 128 : 64); }
+constexpr int kTbRows(int dtype, bool wide = false) {
+  return kTbThreads(dtype) * kTbVec(dtype) / kTbCols(dtype, wide);
+}
+hipError_t launch_step2(int dtype, int depth, bool fv, bool wide, int grid, bool persist,
+                        const StepArgs& a, hipStream_t s);
 
 // Persistent form of launch_step (update only): `grid` work-groups take
 // (step, item) tickets in order and advance every member a.steps steps; an

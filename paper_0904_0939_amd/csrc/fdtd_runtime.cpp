@@ -381,11 +381,15 @@ long long chunk_sites(const fdtd_ctx* h, const fdtd_tuning& t) {
 int x_parts(int N, int xc) { return (N + std::max(1, std::min(xc, N)) - 1) / std::max(1, std::min(xc, N)); }
 int x_bound(int N, int nx, int b) { return (int)(((long long)b * N) / nx); }
 
+// Two-step tiles of the tuning t: 16 x 128 (tile = 1, F32 / BF16) instead of
+// the dtype's default shape.
+bool tb_wide(const fdtd_ctx* h, const fdtd_tuning& t) { return t.tile == 1 && h->dtype != kF64; }
+
 // Work items per plane of a lattice of side N: chunks of the flattened plane,
 // or (two steps per pass) tiles of the (y, z) plane.
 long long plane_items(const fdtd_ctx* h, const fdtd_tuning& t, int N) {
   if (t.tblock == 2) {
-    const long long ty = kTbRows(h->dtype), tz = kTbCols(h->dtype);
+    const long long ty = kTbRows(h->dtype, tb_wide(h, t)), tz = kTbCols(h->dtype, tb_wide(h, t));
     return ((N + ty - 1) / ty) * ((N + tz - 1) / tz);
   }
   const long long F = chunk_sites(h, t);
@@ -430,7 +434,7 @@ void make_items(fdtd_ctx* h, fdtd_tuning t, bool tiles, std::vector<Item>& phys,
   t.tblock = tiles ? 2 : 0;
   if (t.xchunk == 0) t.xchunk = auto_xchunk(h, t);
   const long long F = chunk_sites(h, t);
-  const int ty = kTbRows(h->dtype);
+  const int ty = kTbRows(h->dtype, tb_wide(h, t)), tz = kTbCols(h->dtype, tb_wide(h, t));
   phys.clear();
   order.clear();
   begin.assign(h->count, 0);
@@ -438,14 +442,14 @@ void make_items(fdtd_ctx* h, fdtd_tuning t, bool tiles, std::vector<Item>& phys,
   for (int i = 0; i < h->count; ++i) {
     const int N = h->mem[i].N;
     const int nchunk = (int)plane_items(h, t, N);
-    const int tz_n = (N + kTbCols(h->dtype) - 1) / kTbCols(h->dtype);  // tiles row-major over the plane
+    const int tz_n = (N + tz - 1) / tz;  // tiles row-major over the plane
     const int nx = x_parts(N, t.xchunk);
     begin[i] = (int)phys.size();
     for (int bx = 0; bx < nx; ++bx)
       for (int ch = 0; ch < nchunk; ++ch) {
         Item it;
         it.member = i;
-        it.f0 = tiles ? (ch / tz_n) * ty * N + (ch % tz_n) * kTbCols(h->dtype) : (int)(ch * F);
+        it.f0 = tiles ? (ch / tz_n) * ty * N + (ch % tz_n) * tz : (int)(ch * F);
         it.xb = x_bound(N, nx, bx);
         it.xe = x_bound(N, nx, bx + 1);
         it.slot = (int)phys.size();
@@ -606,7 +610,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
       a.ctrl = h->d_ctrl();
       const int grid = h->tun.grid > 0 ? h->tun.grid : h->n_cu;
       HIP_TRY(launch_persist_reset(a.ctrl, a.states, h->count, s));
-      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), grid, true, a, s));
+      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), tb_wide(h, h->tun), grid, true, a, s));
       if (k & 1) h->cur ^= 1;
       done += 2 * k;
     }
@@ -645,7 +649,8 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
       a.items = h->d_titems;
       a.n_items = h->n_titems;
       a.slot_stride = h->n_titems;
-      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), launch_grid(h, a.n_items), false, a, s));
+      HIP_TRY(launch_step2(h->dtype, h->tun.depth, use_fv(h), tb_wide(h, h->tun), launch_grid(h, a.n_items),
+                           false, a, s));
       h->cur ^= 1;  // psi_{t+2} is in the other buffer
     }
   }
@@ -661,7 +666,7 @@ fdtd_status launch_steps(fdtd_ctx* h, int n, int renorm_every, hipStream_t s) {
 bool same_tuning(const fdtd_tuning& a, const fdtd_tuning& b) {
   return a.vz == b.vz && a.ry == b.ry && a.xchunk == b.xchunk && a.grid == b.grid &&
          a.xcd_remap == b.xcd_remap && a.depth == b.depth && a.variant == b.variant &&
-         a.persist == b.persist && a.vfuse == b.vfuse && a.tblock == b.tblock;
+         a.persist == b.persist && a.vfuse == b.vfuse && a.tblock == b.tblock && a.tile == b.tile;
 }
 
 void drop_graphs(fdtd_ctx* h) {
@@ -863,6 +868,9 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
     return fail(FDTD_EINVAL, "tuning: persistent two-step launches take at most 32768 passes");
   if (t.vfuse != 0 && t.vfuse != 1) return fail(FDTD_EINVAL, "tuning: vfuse must be 0 or 1");
   if (t.tblock != 0 && t.tblock != 2) return fail(FDTD_EINVAL, "tuning: tblock must be 0 or 2");
+  if (t.tile != 0 && t.tile != 1) return fail(FDTD_EINVAL, "tuning: tile must be 0 or 1");
+  if (t.tile == 1 && (t.tblock != 2 || h->dtype == kF64))
+    return fail(FDTD_EINVAL, "tuning: tile 1 (16 x 128 tiles) needs tblock = 2 and an F32 or BF16 state");
   if (t.tblock == 2) {
     if (t.variant != 0) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs variant 0");
     if (t.ry != 1 || t.vz != vec_width(h->dtype)) return fail(FDTD_EINVAL, "tuning: tblock = 2 needs ry = 1 and vz = the dtype's vector width");
@@ -1568,15 +1576,17 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
         go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 1});
       }
     // two steps per pass (validation drops the shapes it does not cover),
-    // one launch per pass or (batches) persistent passes; the x-chunks
-    // between 64 and 128 matter on batches (64 lattices of side 48..160,
-    // depth 4: x-chunk 64 151.1 us per step, 80 140.7, 96 147.4)
-    for (int xc : {0, 32, 64, 80, 96, 128, 256})
-      for (int depth : {1, 2, 3, 4})
-        for (int persist : persists) {
-          if (!go || xc > maxN || !all_div || (depth == 4 && h->dtype == kF64)) continue;
-          go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, persist / 2, 0, 2});
-        }
+    // one launch per pass or (batches) persistent passes, on both tile shapes
+    // of F32 / BF16 states; the x-chunks between 64 and 128 matter on batches
+    // (64 lattices of side 48..160, depth 4: x-chunk 64 151.1 us per step, 80
+    // 140.7, 96 147.4)
+    for (int tile : {0, 1})
+      for (int xc : {0, 32, 64, 80, 96, 128, 256})
+        for (int depth : {1, 2, 3, 4})
+          for (int persist : persists) {
+            if (!go || xc > maxN || !all_div || (h->dtype == kF64 && (depth == 4 || tile))) continue;
+            go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, persist / 2, 0, 2, tile});
+          }
   }
   // restore
   h->cur = cur0;
@@ -1610,7 +1620,7 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
 // ------------------------------------------------------ launch-shape cache --
 namespace {
 constexpr const char* kTuneHeader =
-    "# fdtd launch shapes: key vz ry xchunk grid xcd_remap depth variant persist vfuse tblock";
+    "# fdtd launch shapes: key vz ry xchunk grid xcd_remap depth variant persist vfuse tblock tile";
 }
 
 extern "C" fdtd_status fdtd_tune_cache_save(const char* path) {
@@ -1627,7 +1637,7 @@ extern "C" fdtd_status fdtd_tune_cache_save(const char* path) {
     const fdtd_tuning& t = kv.second;
     f << kv.first << ' ' << t.vz << ' ' << t.ry << ' ' << t.xchunk << ' ' << t.grid << ' '
       << t.xcd_remap << ' ' << t.depth << ' ' << t.variant << ' ' << t.persist << ' ' << t.vfuse
-      << ' ' << t.tblock << "\n";
+      << ' ' << t.tblock << ' ' << t.tile << "\n";
   }
   f.flush();
   if (!f) return fail(FDTD_EINVAL, std::string("tune_cache_save: write failed on ") + path);
@@ -1649,10 +1659,10 @@ extern "C" fdtd_status fdtd_tune_cache_load(const char* path) {
     std::string key, extra;
     fdtd_tuning t{};
     if (!(in >> key >> t.vz >> t.ry >> t.xchunk >> t.grid >> t.xcd_remap >> t.depth >> t.variant >>
-          t.persist >> t.vfuse >> t.tblock) ||
+          t.persist >> t.vfuse >> t.tblock >> t.tile) ||
         (in >> extra))
       return fail(FDTD_EINVAL, "tune_cache_load: " + std::string(path) + " line " +
-                                   std::to_string(no) + ": expected a key and 10 integers");
+                                   std::to_string(no) + ": expected a key and 11 integers");
     got[key] = t;
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -11,10 +11,11 @@ namespace {
 
 // -------------------------------------- temporal blocking: two steps ----
 // k_step2 advances every member two steps per pass over HBM (psi and V read
-// once, psi'' written once).  A work item owns a tile of kTbRows(DT) x
-// kTbCols(DT) sites of the (y, z) plane and streams x; each lane holds one
-// vector of VZ consecutive z sites (a tile row is 256 bytes of F32 / F64; BF16
-// lattices use the F32 tile, 4 sites per lane).
+// once, psi'' written once).  A work item owns a tile of kTbRows(DT, WIDE) x
+// kTbCols(DT, WIDE) sites of the (y, z) plane and streams x; each lane holds
+// one vector of VZ consecutive z sites (a tile row is 256 bytes of F32 / F64,
+// 512 bytes for the wide F32 tile; BF16 lattices use the F32 tiles, 4 sites
+// per lane).
 // Step t runs on the tile's own vectors and on a frame of single halo sites
 // (the rows y0 - 1 and y0 + rows, the columns z0 - 1 and z0 + cols), with the
 // loads and arithmetic of the one-step kernel; its results stay in registers
@@ -67,10 +68,10 @@ constexpr int kTbTileBufs = kTbLdsU ? 3 : 2;
 #endif
 constexpr int tb_min_waves(int dt) { return dt == kF64 ? FDTD_TB_MIN_WAVES_F64 : FDTD_TB_MIN_WAVES_F32; }
 
-template <int DT, int VZ, int D, bool FV>
+template <int DT, int VZ, int D, bool FV, bool WIDE>
 struct Step2 {
   static constexpr int BT = kTbThreads(DT);
-  static constexpr int TZ = kTbCols(DT);            // tile columns (z sites)
+  static constexpr int TZ = kTbCols(DT, WIDE);      // tile columns (z sites)
   static constexpr int LPR = TZ / VZ;               // lanes per tile row
   static constexpr int TY = BT / LPR;               // tile rows
   static constexpr int NH = 2 * TZ + 2 * TY;        // halo sites, one per lane
@@ -82,7 +83,7 @@ struct Step2 {
   // D planes ahead needs D + 3 slots), US slots of step-t results
   static constexpr int RS = D <= 3 ? 6 : 8;
   static constexpr int US = D <= 3 ? 3 : 4;
-  static_assert(TY == kTbRows(DT) && TZ % VZ == 0, "tile shape");
+  static_assert(TY == kTbRows(DT, WIDE) && TZ % VZ == 0, "tile shape");
   static_assert(NH <= BT, "one halo site per lane");
   using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
   using H = StepBody<DT, 1, 1, true, FV>;   // halo sites
@@ -378,12 +379,12 @@ __device__ __forceinline__ void tb_lane(Lane<RYL, VZ, C>& ln, int r, unsigned f,
 // FENCE: the persistent form, where the next pass's tiles (on any XCD) read
 // this pass's state within the same launch: the partials are published with
 // a full release fence, as the persistent one-step kernel does.
-template <int DT, int VZ, int D, bool FV, bool FENCE>
+template <int DT, int VZ, int D, bool FV, bool WIDE, bool FENCE>
 __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int src,
-                                        typename Step2<DT, VZ, D, FV>::C* tile,
-                                        typename Step2<DT, VZ, D, FV>::C* ptile,
+                                        typename Step2<DT, VZ, D, FV, WIDE>::C* tile,
+                                        typename Step2<DT, VZ, D, FV, WIDE>::C* ptile,
                                         double (&s_red)[kTbThreads(DT) / 64][5], int& s_last) {
-  using T = Step2<DT, VZ, D, FV>;
+  using T = Step2<DT, VZ, D, FV, WIDE>;
   using B = typename T::B;
   using H = typename T::H;
   using C = typename T::C;
@@ -587,16 +588,16 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
   }
 }
 
-template <int DT, int VZ, int D, bool FV>
+template <int DT, int VZ, int D, bool FV, bool WIDE>
 __global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2(StepArgs A) {
-  using T = Step2<DT, VZ, D, FV>;
+  using T = Step2<DT, VZ, D, FV, WIDE>;
   __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
   __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
   __shared__ double s_red[kTbThreads(DT) / 64][5];
   __shared__ int s_last;
   for (int li = blockIdx.x; li < A.n_items; li += gridDim.x)
-    tb_item<DT, VZ, D, FV, false>(A, A.items[A.item_offset + li], A.src, tile, ptile, s_red,
-                                  s_last);
+    tb_item<DT, VZ, D, FV, WIDE, false>(A, A.items[A.item_offset + li], A.src, tile, ptile, s_red,
+                                        s_last);
 }
 
 // Persistent two-step passes: A.steps passes (2 A.steps steps) of every
@@ -609,9 +610,9 @@ __global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2(Step
 // waited on hold smaller tickets.  The same bounded poll and abort flag guard
 // them.  Per-tile arithmetic, partial slots and summation order are those of
 // k_step2: the same bits as one launch per pass.
-template <int DT, int VZ, int D, bool FV>
+template <int DT, int VZ, int D, bool FV, bool WIDE>
 __global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2_persist(StepArgs A) {
-  using T = Step2<DT, VZ, D, FV>;
+  using T = Step2<DT, VZ, D, FV, WIDE>;
   __shared__ __align__(16) typename T::C tile[kTbTileBufs * T::TS];
   __shared__ __align__(16) typename T::C ptile[T::kPsi ? 2 * T::TS : 4];
   __shared__ double s_red[kTbThreads(DT) / 64][5];
@@ -642,45 +643,56 @@ __global__ __launch_bounds__(kTbThreads(DT), tb_min_waves(DT)) void k_step2_pers
     const int tk = s_tk;
     if (tk >= total) break;
     const int pass = tk / A.n_items;
-    tb_item<DT, VZ, D, FV, true>(A, A.items[tk % A.n_items], A.src ^ (pass & 1), tile, ptile,
-                                 s_red, s_last);
+    tb_item<DT, VZ, D, FV, WIDE, true>(A, A.items[tk % A.n_items], A.src ^ (pass & 1), tile,
+                                       ptile, s_red, s_last);
   }
 }
 
 
-template <int DT, int D, bool FV>
+template <int DT, int D, bool FV, bool WIDE>
 hipError_t step2_one(int grid, bool persist, const StepArgs& a, hipStream_t s) {
   if (persist)
-    hipLaunchKernelGGL((k_step2_persist<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(kTbThreads(DT)), 0, s, a);
+    hipLaunchKernelGGL((k_step2_persist<DT, kTbVec(DT), D, FV, WIDE>), dim3(grid), dim3(kTbThreads(DT)),
+                       0, s, a);
   else
-    hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV>), dim3(grid), dim3(kTbThreads(DT)), 0, s, a);
+    hipLaunchKernelGGL((k_step2<DT, kTbVec(DT), D, FV, WIDE>), dim3(grid), dim3(kTbThreads(DT)), 0, s,
+                       a);
   return hipGetLastError();
 }
 
-template <int DT, bool FV>
+template <int DT, bool FV, bool WIDE>
 hipError_t step2_depth(int depth, int grid, bool persist, const StepArgs& a, hipStream_t s) {
   switch (depth) {
-    case 1: return step2_one<DT, 1, FV>(grid, persist, a, s);
-    case 2: return step2_one<DT, 2, FV>(grid, persist, a, s);
-    case 3: return step2_one<DT, 3, FV>(grid, persist, a, s);
+    case 1: return step2_one<DT, 1, FV, WIDE>(grid, persist, a, s);
+    case 2: return step2_one<DT, 2, FV, WIDE>(grid, persist, a, s);
+    case 3: return step2_one<DT, 3, FV, WIDE>(grid, persist, a, s);
     case 4:  // FP32-arithmetic lattices only (a ring of 8 plane slots)
-      if constexpr (DT != kF64) return step2_one<DT, 4, FV>(grid, persist, a, s);
+      if constexpr (DT != kF64) return step2_one<DT, 4, FV, WIDE>(grid, persist, a, s);
       else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }
 }
 
+// F32 / BF16 lattices: the tile shape (32 x 64, or 16 x 128 with wide)
+template <int DT, bool FV>
+hipError_t step2_tile(int depth, bool wide, int grid, bool persist, const StepArgs& a,
+                      hipStream_t s) {
+  return wide ? step2_depth<DT, FV, true>(depth, grid, persist, a, s)
+              : step2_depth<DT, FV, false>(depth, grid, persist, a, s);
+}
+
 }  // namespace
 
-hipError_t launch_step2(int dtype, int depth, bool fv, int grid, bool persist, const StepArgs& a,
-                        hipStream_t s) {
+hipError_t launch_step2(int dtype, int depth, bool fv, bool wide, int grid, bool persist,
+                        const StepArgs& a, hipStream_t s) {
   if (grid < 1 || (persist && (a.steps < 1 || !a.ctrl))) return hipErrorInvalidValue;
   switch (dtype) {
-    case kF64: return fv ? hipErrorInvalidValue : step2_depth<kF64, false>(depth, grid, persist, a, s);
-    case kF32: return fv ? step2_depth<kF32, true>(depth, grid, persist, a, s)
-                         : step2_depth<kF32, false>(depth, grid, persist, a, s);
-    case kBF16: return fv ? step2_depth<kBF16, true>(depth, grid, persist, a, s)
-                          : step2_depth<kBF16, false>(depth, grid, persist, a, s);
+    case kF64:
+      return fv || wide ? hipErrorInvalidValue : step2_depth<kF64, false, false>(depth, grid, persist, a, s);
+    case kF32: return fv ? step2_tile<kF32, true>(depth, wide, grid, persist, a, s)
+                         : step2_tile<kF32, false>(depth, wide, grid, persist, a, s);
+    case kBF16: return fv ? step2_tile<kBF16, true>(depth, wide, grid, persist, a, s)
+                          : step2_tile<kBF16, false>(depth, wide, grid, persist, a, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -60,7 +60,7 @@ class fdtd_tuning(C.Structure):
     _fields_ = [("vz", C.c_int32), ("ry", C.c_int32), ("xchunk", C.c_int32),
                 ("grid", C.c_int32), ("xcd_remap", C.c_int32), ("depth", C.c_int32),
                 ("variant", C.c_int32), ("persist", C.c_int32), ("vfuse", C.c_int32),
-                ("tblock", C.c_int32)]
+                ("tblock", C.c_int32), ("tile", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

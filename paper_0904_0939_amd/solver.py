@@ -102,9 +102,9 @@ class _Handle:
 
     def set_tuning(self, vz: int, ry: int, xchunk: int, grid: int = 0, xcd_remap: int = 1,
                    depth: int = 1, variant: int = 0, persist: int = 0, vfuse: int = 1,
-                   tblock: int = 0):
+                   tblock: int = 0, tile: int = 0):
         F.fdtd_set_tuning(self.h, F.fdtd_tuning(vz, ry, xchunk, grid, xcd_remap, depth, variant,
-                                                persist, vfuse, tblock))
+                                                persist, vfuse, tblock, tile))
 
     def autotune(self, steps_per_trial: int = 10):
         t, ms = F.fdtd_autotune(self.h, steps_per_trial)

@@ -115,7 +115,8 @@ def test_tuning_validation_is_host_side():
         F.fdtd_set_tuning(h, F.fdtd_tuning(1, 4, 5, 7, 0, 1))
         assert F.fdtd_get_tuning(h).as_dict() == {"vz": 1, "ry": 4, "xchunk": 5, "grid": 7,
                                                   "xcd_remap": 0, "depth": 1, "variant": 0,
-                                                  "persist": 0, "vfuse": 0, "tblock": 0}
+                                                  "persist": 0, "vfuse": 0, "tblock": 0,
+                                                  "tile": 0}
         # persistent launches: variant 0 only, bounded step count
         for bad in [F.fdtd_tuning(1, 1, 8, 0, 1, 1, 2, 8), F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, -1),
                     F.fdtd_tuning(1, 1, 8, 0, 1, 1, 0, 65537)]:
@@ -178,7 +179,8 @@ def test_write_through_variant_rules_and_default():
 def test_two_step_passes_validation():
     """tblock = 2: full vectors, ry = 1, variant 0, persistent passes
     allowed (up to 32768 per launch); any side (tiles of the (y, z) plane),
-    every dtype."""
+    every dtype; the wide tile (tile = 1) for F32 and BF16 two-step passes
+    only."""
     h32 = F.fdtd_create(cfg(N=64, dtype=F.F32))
     h64 = F.fdtd_create(cfg(N=64, dtype=F.F64))
     hb = F.fdtd_create(cfg(N=64, dtype=F.BF16))
@@ -200,6 +202,16 @@ def test_two_step_passes_validation():
         assert status_of("fdtd_set_tuning", hb, C.byref(F.fdtd_tuning(1, 1, 0, 0, 1, 1, 0, 0, 1, 2))) == F.EINVAL
         F.fdtd_set_tuning(big, F.fdtd_tuning(4, 1, 0, 0, 1, 1, 0, 0, 1, 2))
         assert F.fdtd_get_tuning(big).tblock == 2
+        # tile shapes: 1 (16 x 128) with tblock = 2 on F32 / BF16 states only
+        F.fdtd_set_tuning(h32, F.fdtd_tuning(4, 1, 0, 0, 1, 4, 0, 0, 0, 2, 1))
+        assert F.fdtd_get_tuning(h32).tile == 1
+        F.fdtd_set_tuning(hb, F.fdtd_tuning(8, 1, 0, 0, 1, 3, 0, 8, 1, 2, 1))
+        assert F.fdtd_get_tuning(hb).tile == 1
+        for h, bad in [(h64, F.fdtd_tuning(2, 1, 0, 0, 1, 3, 0, 0, 1, 2, 1)),   # F64
+                       (h32, F.fdtd_tuning(4, 2, 0, 0, 1, 1, 0, 0, 1, 0, 1)),   # one step per pass
+                       (h32, F.fdtd_tuning(4, 1, 0, 0, 1, 2, 0, 0, 1, 2, 2))]:  # no tile 2
+            assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
+            assert "tile" in F.fdtd_last_error()
     finally:
         for h in (h32, h64, hb, big):
             F.fdtd_destroy(h)
@@ -279,10 +291,11 @@ def test_tune_cache_file_round_trip_and_errors(tmp_path):
     """The autotuner's cache file is written and read back without a GPU;
     a malformed line is rejected and leaves the cache as it was; an empty
     file clears it."""
-    entries = ["gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0",
-               "gfx950/256cu:0:64:96 2 1 128 0 1 2 0 64 1 2"]
+    entries = ["gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0 0",
+               "gfx950/256cu:0:64:96 2 1 128 0 1 2 0 64 1 2 0",
+               "gfx950/256cu:1:1024 4 1 0 0 1 4 0 0 0 2 1"]
     good = tmp_path / "good.txt"
-    good.write_text("# shapes\n" + entries[0] + "\n\n   \n" + entries[1] + "\n")
+    good.write_text("# shapes\n" + entries[0] + "\n\n   \n" + "\n".join(entries[1:]) + "\n")
     F.fdtd_tune_cache_load(str(good))
     out = tmp_path / "out.txt"
 
@@ -294,9 +307,9 @@ def test_tune_cache_file_round_trip_and_errors(tmp_path):
 
     assert saved() == sorted(entries)
     bad = tmp_path / "bad.txt"
-    for text in ("gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1\n",      # a field missing
-                 "gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0 7\n",  # one too many
-                 "gfx950/256cu:1:512 4 x 0 0 1 1 3 0 1 0\n"):   # not an integer
+    for text in ("gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0\n",      # a field missing
+                 "gfx950/256cu:1:512 4 2 0 0 1 1 3 0 1 0 0 7\n",  # one too many
+                 "gfx950/256cu:1:512 4 x 0 0 1 1 3 0 1 0 0\n"):   # not an integer
         bad.write_text(entries[0] + "\n" + text)
         assert status_of("fdtd_tune_cache_load", os.fsencode(str(bad))) == F.EINVAL
         assert "line 2" in F.lib().fdtd_last_error().decode()

@@ -119,7 +119,7 @@ def test_autotune_cache_file_carries_shapes_to_a_new_cache(tmp_path):
     # vz = 3 fits no dtype: the entry is dropped, the shapes timed again
     key = lines[0].split()[0]
     bad = tmp_path / "bad.txt"
-    bad.write_text(f"{key} 3 1 0 0 1 1 0 0 1 0\n")
+    bad.write_text(f"{key} 3 1 0 0 1 1 0 0 1 0 0\n")
     F.fdtd_tune_cache_load(str(bad))
     s = solver()
     t3, ms3 = s.autotune(3)

@@ -128,16 +128,17 @@ def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps,
     assert out[0][2] == out[1][2]
 
 
-@pytest.mark.parametrize("dtype,depth", [("f64", 2), ("bf16", 2), ("f32", 4)])
-def test_single_lattice_persistent_two_step_equals_per_pass(dtype, depth):
-    say(f"case: persistent two-step single {dtype} depth={depth}")
+@pytest.mark.parametrize("dtype,depth,tile", [("f64", 2, 0), ("bf16", 2, 0), ("f32", 4, 0),
+                                              ("f32", 4, 1), ("bf16", 3, 1)])
+def test_single_lattice_persistent_two_step_equals_per_pass(dtype, depth, tile):
+    say(f"case: persistent two-step single {dtype} depth={depth} tile={tile}")
     vz = {"f64": 2, "bf16": 8, "f32": 4}[dtype]
     out = []
     for persist in (0, 8):
         s = Solver(72, 10.0, dtype=dtype)
         s.set_potential(F.POT_CORNELL, W.CORNELL_PARAMS)
         s.set_initial(2, parity=W.parity_word(z=2))
-        s.set_tuning(vz, 1, 0, 0, 1, depth, 0, persist, 1, 2)
+        s.set_tuning(vz, 1, 0, 0, 1, depth, 0, persist, 1, 2, tile)
         s.evolve(61)
         out.append((s.state(), s.observables()[0]))
         s.close()

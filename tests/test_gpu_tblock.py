@@ -35,35 +35,44 @@ VW = {"f32": 4, "f64": 2, "bf16": 8}
 POT = {"ho": (F.POT_HO, [1.0, 1.2, 0.8]), "cornell": (F.POT_CORNELL, W.CORNELL_PARAMS)}
 
 
-def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.0, seed=5):
+def run(dtype, N, pot, xchunk, depth, vfuse, tblock, steps, renorm, graph, L=10.0, seed=5,
+        tile=0):
     s = Solver(N, L, dtype=dtype)
     s.set_potential(*POT[pot])
     s.set_initial(seed)
-    # one-step launches prefetch at most 3 planes (depth 4 is the two-step pass's)
+    # one-step launches prefetch at most 3 planes (depth 4 is the two-step
+    # pass's) and have no tile shape
     s.set_tuning(VW[dtype], 1, xchunk, 0, 1, depth if tblock == 2 else min(depth, 3), 0, 0,
-                 vfuse, tblock)
+                 vfuse, tblock, tile if tblock == 2 else 0)
     s.evolve(steps, renorm_every=renorm, use_graph=graph)
     out = (s.state(), s.observables()[0], s.history(0, steps))
     s.close()
     return out
 
 
-# (dtype, N, potential, xchunk, depth, vfuse): tiles ragged in y and z,
+# (dtype, N, potential, xchunk, depth, vfuse, tile): tiles ragged in y and z,
 # several x-ranges per lattice, the in-kernel potential, and sides beyond
-# 256 vz (F32 and BF16 tiles are 32 x 64 sites, F64 16 x 32)
+# 256 vz (F32 and BF16 tiles are 32 x 64 sites, or 16 x 128 with tile 1; F64
+# 16 x 32)
 CASES = [
-    ("f32", 40, "cornell", 0, 1, 0),
-    ("f32", 64, "ho", 8, 2, 0),
-    ("f32", 96, "cornell", 24, 1, 1),
-    ("f32", 516, "cornell", 0, 2, 1),
-    ("f64", 48, "ho", 0, 1, 0),
-    ("f64", 300, "cornell", 32, 1, 0),
-    ("bf16", 64, "cornell", 0, 2, 0),
-    ("bf16", 96, "ho", 24, 3, 1),
+    ("f32", 40, "cornell", 0, 1, 0, 0),
+    ("f32", 64, "ho", 8, 2, 0, 0),
+    ("f32", 96, "cornell", 24, 1, 1, 0),
+    ("f32", 516, "cornell", 0, 2, 1, 0),
+    ("f64", 48, "ho", 0, 1, 0, 0),
+    ("f64", 300, "cornell", 32, 1, 0, 0),
+    ("bf16", 64, "cornell", 0, 2, 0, 0),
+    ("bf16", 96, "ho", 24, 3, 1, 0),
     # prefetch depth 4 (an 8-slot ring): whole trips, every tail length
-    ("f32", 72, "cornell", 0, 4, 0),
-    ("f32", 100, "ho", 30, 4, 1),
-    ("bf16", 64, "cornell", 0, 4, 1),
+    ("f32", 72, "cornell", 0, 4, 0, 0),
+    ("f32", 100, "ho", 30, 4, 1, 0),
+    ("bf16", 64, "cornell", 0, 4, 1, 0),
+    # 16 x 128 tiles: a lattice narrower than one tile, sides ragged in y and
+    # z (136 = 128 + 8, 8.5 tiles of 16 rows), side 516, BF16
+    ("f32", 40, "ho", 0, 2, 0, 1),
+    ("f32", 136, "cornell", 24, 4, 0, 1),
+    ("f32", 516, "cornell", 0, 4, 1, 1),
+    ("bf16", 136, "ho", 40, 3, 1, 1),
 ]
 
 
@@ -74,17 +83,18 @@ def same_records(h1, h2, rel):
             assert a[k] == pytest.approx(b[k], rel=rel, abs=1e-300), (a["step"], k)
 
 
-@pytest.mark.parametrize("dtype,N,pot,xchunk,depth,vfuse", CASES)
-def test_two_step_passes_equal_one_step_launches(dtype, N, pot, xchunk, depth, vfuse):
+@pytest.mark.parametrize("dtype,N,pot,xchunk,depth,vfuse,tile", CASES)
+def test_two_step_passes_equal_one_step_launches(dtype, N, pot, xchunk, depth, vfuse, tile):
     # graph-captured chunks of 64 + 54 (N < 256) or 50 steps: odd numbers of
     # passes, so the buffer holding the result flips differently from the
     # step count
     steps = 50 if N >= 256 else 118
     for graph in (True, False):
-        say(f"case: tblock {dtype} N={N} {pot} xchunk={xchunk} depth={depth} vfuse={vfuse} graph={graph}")
+        say(f"case: tblock {dtype} N={N} {pot} xchunk={xchunk} depth={depth} vfuse={vfuse} "
+            f"tile={tile} graph={graph}")
         # rescale off: the states are the same bits
         ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 0, graph)
-        got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 0, graph)
+        got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 0, graph, tile=tile)
         assert np.array_equal(got[0], ref[0])
         assert ref[1]["step"] == got[1]["step"] == steps
         # BF16 lanes hold 8 sites in one-step launches and 4 here: their FP32
@@ -93,7 +103,7 @@ def test_two_step_passes_equal_one_step_launches(dtype, N, pot, xchunk, depth, v
     # a rescale every second step: the scale comes from sums taken in another
     # order, so the states agree to that rounding
     ref = run(dtype, N, pot, xchunk, depth, vfuse, 0, steps, 2, True)
-    got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 2, True)
+    got = run(dtype, N, pot, xchunk, depth, vfuse, 2, steps, 2, True, tile=tile)
     tol = {"f32": 1e-6, "f64": 1e-13, "bf16": 1e-2}[dtype]
     got_s, ref_s = got[0], ref[0]
     if dtype == "bf16":
@@ -158,20 +168,22 @@ def test_rescale_every_step_and_odd_starts_follow_the_oracle(dtype, N, pot, tol)
 
 def test_batch_two_step_passes_equal_one_step_launches():
     """Lattices of several sides in one handle: tiles of every member in one
-    launch, each member's sums finalised by its own last work-group."""
+    launch (both tile shapes), each member's sums finalised by its own last
+    work-group."""
     say("case: tblock batch f32")
     rng = np.random.default_rng(4)
     lats = [W.Lattice(N, 12.0, W.POT_WELLS, W.random_wells(rng), seed=2) for N in (40, 64, 96, 48, 72)]
     out = []
-    for tblock in (0, 2):
+    for tblock, tile in ((0, 0), (2, 0), (2, 1)):
         b = Batch(lats, dtype="f32")
         for m, l in enumerate(lats):
             b.set_potential(l.pot_kind, l.pot_params, member=m)
         b.set_initial(2)
-        b.set_tuning(4, 1, 0, 0, 1, 2, 0, 0, 0, tblock)
+        b.set_tuning(4, 1, 0, 0, 1, 2, 0, 0, 0, tblock, tile)
         b.evolve(60, renorm_every=0)
         out.append(([b.state(m) for m in range(len(lats))], [b.history(m, 60) for m in range(len(lats))]))
         b.close()
-    for m in range(len(lats)):
-        assert np.array_equal(out[0][0][m], out[1][0][m]), m
-        same_records(out[1][1][m], out[0][1][m], 1e-12)
+    for got in out[1:]:
+        for m in range(len(lats)):
+            assert np.array_equal(out[0][0][m], got[0][m]), m
+            same_records(got[1][m], out[0][1][m], 1e-12)
