@@ -76,7 +76,7 @@ def summarize_rocprof(fetch_csv, write_csv, stats_csv, key, sites, dtype):
     copy_bytes = es * sites
 
     def is_step(name):
-        if key.endswith("_tb2"):
+        if "_tb2" in key:
             return "k_step2<" in name
         if "k_step<" not in name:
             return False
