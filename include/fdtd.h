@@ -195,7 +195,7 @@ typedef struct {
  *  tblock  0 (default): one pass over HBM per step; 2: temporal blocking, two
  *         steps per pass (psi and V read once, psi written once per two steps).
  *         Work items are then tiles of the (y, z) plane (F32 and BF16: 32 x
- *         64 sites, F64: 16 x 32) streaming x: a work item first advances its
+ *         64 sites, or 16 x 128 with tile = 1; F64: 16 x 32) streaming x: a work item first advances its
  *         tile plus a one-site frame around it (and one plane on each side in
  *         x) by one step, in registers and LDS, then its own tile by the
  *         second.  Any lattice side (a multiple of vz), ry = 1, vz = the
