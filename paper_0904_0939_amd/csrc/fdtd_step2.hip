@@ -124,19 +124,15 @@ struct Step2 {
                                                    const Lane<1, VZ, C>& ln, int x,
                                                    const C (&pc)[VZ], const C (&pn)[VZ],
                                                    C (&dxc)[VZ], const C (&vv)[VZ],
-                                                   const PlaneIn<1, VZ, C>& d, bool own,
-                                                   C (&bw)[VZ], C (&dw)[VZ], double (&acc)[5],
-                                                   C (&outv)[VZ]) {
+                                                   const PlaneIn<1, VZ, C>& d, C (&bw)[VZ],
+                                                   C (&dw)[VZ], double (&acc)[5], C (&outv)[VZ]) {
     static_assert(DT == kF32, "F32 states");
     const double xc = (2.0 * x - k.cN) * k.ha;
     const C rx2 = (C)(xc * xc);
     C s0 = 0, kin = 0, pot = 0, r2 = 0, s1 = 0;
-    // d holds the LDS values unmasked.  Beyond the lattice's z ends they are
-    // the frame's or the outside lanes' zeros, so no z mask is needed.  A
-    // vector outside the lattice has psi = 0 (its loads read zeros) and takes
-    // c = 0: its result and its sums are +0 whatever its neighbours hold, as
-    // with zero neighbours
-    const C cl = own ? k.c : C(0);
+    // d holds the LDS values unmasked: beyond the lattice's z ends they are
+    // the frame's or the outside lanes' zeros, so no z mask is needed (an
+    // outside vector has c = 0, see tb_item)
     const C lo = d.zm[0];
     const C hi = d.zp[0];
     // zd[j]: site j's difference towards z - 1; zd[VZ]: the last site's
@@ -165,7 +161,7 @@ struct Step2 {
         bw[j] = rcp_c(fma_c(k.eps, v, C(1)));
         dw[j] = k.dt * v;
       }
-      const C g = fma_c(cl, lap, -(dw[j] * p));  // c lap - dt V psi
+      const C g = fma_c(k.c, lap, -(dw[j] * p));  // c lap - dt V psi
       const C nv = k.sc * fma_c(bw[j], g, p);
       o.v[j] = nv;
       s1 = fma_c(nv, nv, s1);
@@ -183,28 +179,23 @@ struct Step2 {
   // Stage X (slot SL = (X - base) % RS, base = xb - 1): prefetch, step t at
   // plane X into registers and LDS buffer X & 1, then (STEP2) step t + 1 at
   // plane X - 1, then the work-group barrier.
-  // The y / z neighbours of the lane's own vector from an LDS plane; with
-  // MASK, zero for a vector outside the lattice (its result, zero, is then the
-  // boundary value its neighbours read; F32 states skip the masks, see
-  // update_tb).  FP32 arithmetic only: the reads are unconditional and the
-  // zeros come from masks; written as selects of the reads, they become a
-  // branch around the reads with zero moves on the other path, in every stage
-  // (the FP64 kernel keeps that form).
-  template <bool MASK = true>
-  static __device__ __forceinline__ void lds_nbrs(bool own, const C* p, int obase,
-                                                  PlaneIn<1, VZ, C>& d) {
+  // The y / z neighbours of the lane's own vector from an LDS plane, as
+  // stored (FP32 arithmetic).  A vector outside the lattice reads whatever
+  // its LDS neighbours hold: it takes c = 0 (tb_item), so its result, the
+  // boundary value its neighbours read, is +0 all the same.  (Masking the
+  // values instead cost about 20 VALU instructions per plane; FP64 lattices
+  // keep zero neighbours for outside vectors, as a branch around the reads.)
+  static __device__ __forceinline__ void lds_nbrs(const C* p, int obase, PlaneIn<1, VZ, C>& d) {
     static_assert(sizeof(C) == 4, "FP32 arithmetic");
-    const unsigned m = own || !MASK ? 0xffffffffu : 0u;
     const Pack<C, VZ> pm = *reinterpret_cast<const Pack<C, VZ>*>(p + obase - RP);
     const Pack<C, VZ> pp = *reinterpret_cast<const Pack<C, VZ>*>(p + obase + RP);
-    const C zm = p[obase - 1], zp = p[obase + VZ];
 #pragma unroll
     for (int j = 0; j < VZ; ++j) {
-      d.ym[0][j] = __uint_as_float(__float_as_uint(pm.v[j]) & m);
-      d.yp[0][j] = __uint_as_float(__float_as_uint(pp.v[j]) & m);
+      d.ym[0][j] = pm.v[j];
+      d.yp[0][j] = pp.v[j];
     }
-    d.zm[0] = __uint_as_float(__float_as_uint(zm) & m);
-    d.zp[0] = __uint_as_float(__float_as_uint(zp) & m);
+    d.zm[0] = p[obase - 1];
+    d.zp[0] = p[obase + VZ];
   }
 
   // Buffer of plane X (X >= -2) in the LDS tile of step-t results.
@@ -256,12 +247,11 @@ struct Step2 {
       C un[1][VZ];
       if constexpr (kPsi) {
         // y / z neighbours of plane X from the LDS copy written last stage
-        // (zero for a vector outside the lattice, as its loads would read)
         PlaneIn<1, VZ, C> d;
-        lds_nbrs<!kShare>(own, ptile + (X & 1) * TS, obase, d);
+        lds_nbrs(ptile + (X & 1) * TS, obase, d);
         if constexpr (kShare) {
           update_tb<true, 1>(kb, lb, X, g.qs[(SL + 1) % RS][0], g.qs[(SL + 2) % RS][0], g.dx1,
-                             g.vs[SL % RS][0], d, own, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
+                             g.vs[SL % RS][0], d, g.bw[SL % 2], g.dw[SL % 2], tmp, un[0]);
         } else {
           B::template update_core<false, true, 1>(kb, lb, X, g.qs[SL % RS], g.qs[(SL + 1) % RS],
                                                   g.qs[(SL + 2) % RS], g.vs[SL % RS], d, tmp, true,
@@ -296,8 +286,9 @@ struct Step2 {
     if constexpr (STEP2) {
       // step t + 1 at plane X - 1: psi_{t+1} planes X - 2, X - 1, X in
       // registers, the y / z neighbours of plane X - 1 from LDS.  A vector
-      // outside the lattice gets zero neighbours, as its loads in the
-      // one-step kernel: its result is not stored, but it enters the norm.
+      // outside the lattice must add nothing to the norm (its result is not
+      // stored): FP64 gives it zero neighbours, as its loads in the one-step
+      // kernel; FP32 arithmetic gives it c = 0.
       const C* tp = tile + tbuf(X - 1) * TS;
       PlaneIn<1, VZ, C> d;
       if constexpr (DT == kF64) {
@@ -311,7 +302,7 @@ struct Step2 {
         d.zm[0] = own ? tp[obase - 1] : C(0);
         d.zp[0] = own ? tp[obase + VZ] : C(0);
       } else {
-        lds_nbrs<!kShare>(own, tp, obase, d);
+        lds_nbrs(tp, obase, d);
       }
       if constexpr (kTbLdsU) {
         // planes X - 2, X - 1, X of the lane's own vector (X: written by this
@@ -330,8 +321,8 @@ struct Step2 {
       } else if constexpr (kShare) {
         C unused[VZ];
         update_tb<false, 2>(k2, lb, X - 1, g.us[(SL + US - 1) % US][0], g.us[SL % US][0], g.dx2,
-                            g.vs[(SL + RS - 1) % RS][0], d, own, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2],
-                            acc2, unused);
+                            g.vs[(SL + RS - 1) % RS][0], d, g.bw[(SL + 1) % 2], g.dw[(SL + 1) % 2], acc2,
+                            unused);
       } else {
         B::template update<false>(k2, lb, X - 1, g.us[(SL + US - 2) % US], g.us[(SL + US - 1) % US],
                                   g.us[SL % US], g.vs[(SL + RS - 1) % RS], d, acc2);
@@ -427,7 +418,7 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
     kh.vbytes = kb.vbytes;
     kh.N = N;
     kh.xe = kb.xe;
-    kh.c = kb.c;
+    kh.c = (C)M.c;
     kh.dt = kb.dt;
     kh.eps = kb.eps;
     kh.sc = kb.sc;
@@ -444,6 +435,14 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
     const int ly = tid / T::LPR, lz = (tid % T::LPR) * VZ;
     const int yo = y0 + ly, zo = z0 + lz;
     const bool own = yo < N && zo < N;
+    if constexpr (T::kPsi) {
+      // FP32 arithmetic: the own vectors' y / z neighbours come from LDS
+      // unmasked.  A vector outside the lattice has psi = 0 (its loads read
+      // zeros) and takes c = 0, so its result and its sums are +0 whatever its
+      // neighbours hold, as with zero neighbours.  (The halo sites keep c.)
+      kb.c = own ? kb.c : C(0);
+      k2.c = kb.c;
+    }
     const int obase = (ly + 1) * T::RP + 4 + lz;
     Lane<1, VZ, C> lb;
     tb_lane<B>(lb, 0, (unsigned)(yo * N + zo), own, M, N, cN, ha);
