@@ -435,11 +435,12 @@ __device__ __forceinline__ void tb_item(const StepArgs& A, const Item& item, int
     const int ly = tid / T::LPR, lz = (tid % T::LPR) * VZ;
     const int yo = y0 + ly, zo = z0 + lz;
     const bool own = yo < N && zo < N;
-    if constexpr (T::kPsi) {
-      // FP32 arithmetic: the own vectors' y / z neighbours come from LDS
-      // unmasked.  A vector outside the lattice has psi = 0 (its loads read
-      // zeros) and takes c = 0, so its result and its sums are +0 whatever its
-      // neighbours hold, as with zero neighbours.  (The halo sites keep c.)
+    if constexpr (DT != kF64) {
+      // FP32 arithmetic: the own vectors' y / z neighbours of step t + 1 (and,
+      // with the LDS copy of psi_t, of step t) come from LDS unmasked.  A
+      // vector outside the lattice has psi = 0 (its loads read zeros) and
+      // takes c = 0, so its result and its sums are +0 whatever its neighbours
+      // hold, as with zero neighbours.  (The halo sites keep c.)
       kb.c = own ? kb.c : C(0);
       k2.c = kb.c;
     }
