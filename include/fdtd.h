@@ -400,7 +400,8 @@ fdtd_status fdtd_set_tuning(fdtd_t h, const fdtd_tuning* t);
 
 /* Time every valid launch shape of the step kernel on this handle with HIP
  * events, keep the fastest, and cache it per (device architecture and CU
- * count, dtype, lattice sizes) for later handles of this process (and, through
+ * count, dtype, lattice sizes, whether the step evaluates V itself) for later
+ * handles of this process (and, through
  * fdtd_tune_cache_save / _load, of later processes).  The state, step counters and history
  * are saved first and restored after (the trials step the lattice).  A shape
  * found in the cache is set without timing; best_ms then receives -1.
@@ -412,7 +413,8 @@ fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tuning* chosen
 
 /* The autotuner's cache as a text file, so that a later process starts from
  * the shapes an earlier one measured.  One line per entry: the key (no
- * spaces; e.g. gfx950/256cu:1:512 for one F32 lattice of side 512), then the
+ * spaces; e.g. gfx950/256cu:1:512 for one F32 lattice of side 512 whose step
+ * reads the V table, gfx950/256cu:1:512:fv when it evaluates V itself), then the
  * eleven fdtd_tuning fields in their declaration order; lines starting with '#'
  * are comments.
  * save: writes every entry of this process's cache to `path` (created or

@@ -840,9 +840,14 @@ std::map<std::string, fdtd_tuning> g_tune_cache;
 
 // Cache key of a launch shape: the device's architecture and CU count, the
 // dtype and every member's side (no spaces: one token of the cache file).
+// Autotuner cache key: device (architecture, CU count), dtype, the members'
+// sides and, with ":fv", a step that evaluates V itself (the fastest shapes
+// differ: with the V table the 512^3 F32 two-step pass wants 16 x 128 tiles,
+// with the in-kernel potential 32 x 64).
 std::string tune_key(const fdtd_ctx* h) {
   std::string k = h->arch + "/" + std::to_string(h->n_cu) + "cu:" + std::to_string(h->dtype);
   for (auto& m : h->mem) k += ":" + std::to_string(m.N);
+  if (use_fv(h)) k += ":fv";
   return k;
 }
 

@@ -108,7 +108,8 @@ def test_autotune_cache_file_carries_shapes_to_a_new_cache(tmp_path):
     path = tmp_path / "shapes.txt"
     F.fdtd_tune_cache_save(str(path))
     lines = [line for line in path.read_text().splitlines() if not line.startswith("#")]
-    assert len(lines) == 1 and lines[0].split()[0].endswith(f"cu:{F.F32}:40")
+    # the HO potential is evaluated in the kernel (vfuse 1): the key says so
+    assert len(lines) == 1 and lines[0].split()[0].endswith(f"cu:{F.F32}:40:fv")
     assert lines[0].startswith("gfx950/")
     F.fdtd_tune_cache_load(str(empty))
     F.fdtd_tune_cache_load(str(path))
@@ -127,6 +128,34 @@ def test_autotune_cache_file_carries_shapes_to_a_new_cache(tmp_path):
     s.evolve(20)
     assert s.observables()[0]["step"] == 20
     s.close()
+
+
+def test_autotune_keys_the_potential_source(tmp_path):
+    """A lattice whose step reads the V table and one whose step evaluates V
+    itself are tuned apart: the second autotune call times its own shapes
+    and keeps the in-kernel potential."""
+    say("case: autotune key per potential source fp32 40^3")
+    empty = tmp_path / "empty.txt"
+    empty.write_text("")
+    F.fdtd_tune_cache_load(str(empty))
+    shapes = []
+    for vfuse in (0, 1):
+        s = Solver(40, 10.0, dtype="f32")
+        s.set_potential(F.POT_HO, [1, 1, 1])
+        s.set_initial(9)
+        t = s.tuning()
+        t["vfuse"] = vfuse
+        s.set_tuning(**t)
+        got, ms = s.autotune(3)
+        assert ms > 0 and got["vfuse"] == vfuse and s.tuning()["vfuse"] == vfuse
+        s.evolve(10)
+        assert s.observables()[0]["step"] == 10
+        s.close()
+    path = tmp_path / "shapes.txt"
+    F.fdtd_tune_cache_save(str(path))
+    keys = sorted(line.split()[0] for line in path.read_text().splitlines() if not line.startswith("#"))
+    assert len(keys) == 2 and keys[1] == keys[0] + ":fv"
+    F.fdtd_tune_cache_load(str(empty))
 
 
 def test_history_ring_keeps_the_last_records():
