@@ -226,6 +226,25 @@ def test_multires_chain_reaches_the_oracle_ground_state(two_step):
     assert rel_l2(s.psi(), psi) < 1e-3
 
 
+def test_multires_two_step_takes_wide_tiles_for_large_table_levels():
+    """two_step on a chain whose potential is only a table (the dodecahedron
+    well): the 512^3 FP32 level takes 16 x 128 tiles, and the chain ends where
+    the same chain with one step per pass ends (the rescale follows every
+    second step, so the energies agree to rounding)."""
+    say("case: multires 256 -> 512 dodecahedron two_step tiles")
+    out = []
+    for two_step in (False, True):
+        s, log = multires([256, 512], 25.6, F.POT_DODECA, [-100.0], ["f32", "f32"], seed=5,
+                          rel_tol=(0.0, 0.0), max_steps=(200, 200), two_step=two_step)
+        t = s.tuning()
+        if two_step:
+            assert t["tblock"] == 2 and t["tile"] == 1 and t["vfuse"] == 1
+        out.append((s.observables()[0]["energy"], [n for _, n, _ in log]))
+        s.close()
+    assert out[0][1] == out[1][1] == [200, 200]
+    assert out[1][0] == pytest.approx(out[0][0], rel=1e-6)
+
+
 def test_energy_of_potential_autograd_matches_oracle():
     """E(theta) with V(theta) = V0 + theta_0 W0 + theta_1 W1 built in torch:
     backward through the adjoint equals sum G W_k of the oracle's reverse
