@@ -177,7 +177,7 @@ TWO_STEP_VZ = {"f32": 4, "f64": 2, "bf16": 8}
 # prefetch depth of the two-step pass: 4 for F32 states (512^3 in-kernel V
 # 174.5 -> 162.0 us per step, 256^3 31.1 -> 29.2), 3 for BF16 (4: no faster)
 # and F64 (4: not built)
-TWO_STEP_DEPTH = {"f32": 4, "f64": 3, "bf16": 3}
+TWO_STEP_DEPTH = {"f32": 5, "f64": 3, "bf16": 3}
 
 
 def two_step_shape(s, dtype):
@@ -339,7 +339,7 @@ def time_to_e(N_levels=(128, 256, 512), max_plain_s=75.0, coarse_steps=(3000, 60
     t_p32, n_p32 = _first_within(p32, e_star, 1e-6)
     return {
         "workload": f"cornell_L30_{'->'.join(str(n) for n in N_levels)}",
-        "launch_form": "two steps per pass (tblock 2; prefetch depth 4 for F32, 3 for BF16 and F64) on every path",
+        "launch_form": "two steps per pass (tblock 2; prefetch depth 5 for F32, 3 for BF16 and F64) on every path",
         "e_star": e_star,
         "plain_fp64_seconds": t_plain, "plain_fp64_steps": n_plain,
         "plain_fp64_steps_to_1e-12": plain[-1][1],
@@ -737,8 +737,8 @@ def main():
         vw = {"f32": 4, "f64": 2}[args.dtype]
         if args.dtype == "f32":
             # V table: 16 x 128 tiles (half the frame's column sites, whose
-            # cache lines the L2s miss) and prefetch depth 4
-            s.set_tuning(vw, 1, 0, 0, 1, 4, 0, 0, 0, 2, 1)
+            # cache lines the L2s miss) and prefetch depth 5
+            s.set_tuning(vw, 1, 0, 0, 1, 5, 0, 0, 0, 2, 1)
         else:
             s.set_tuning(vw, 1, 0, 0, 1, 3, 0, 0, 0, 2)
         ms_2 = timed(args.steps, args.warmup)[0] / args.steps
@@ -754,8 +754,8 @@ def main():
                             "(tblock = 2); the rescale then follows every second step"}
         if args.dtype == "f32":
             # the library's default potential source for analytic kinds: V
-            # evaluated in the kernel (8 B per site and pass), prefetch depth 4
-            s.set_tuning(vw, 1, 0, 0, 1, 4, 0, 0, 1, 2)
+            # evaluated in the kernel (8 B per site and pass), prefetch depth 5
+            s.set_tuning(vw, 1, 0, 0, 1, 5, 0, 0, 1, 2)
             ms_2v = timed(args.steps, args.warmup)[0] / args.steps
             note(f"two steps per pass, in-kernel potential: {ms_2v:.4f} ms/step")
             two_step["in_kernel_v"] = {

@@ -163,8 +163,8 @@ typedef struct {
  *  grid   work-groups launched (0: one per work item);
  *  xcd_remap  1: order work items so that each XCD's L2 sees neighbouring tiles;
  *  depth  planes of HBM prefetch ahead of the plane being updated (1..3;
- *         1 for vz = 1; 4 also for two-step passes of F32 and BF16 states,
- *         whose odd last step of an evolve then prefetches 3);
+ *         1 for vz = 1; 4 and 5 also for two-step passes of F32 and BF16
+ *         states, whose odd last step of an evolve then prefetches 3);
  *  variant  0: 256-lane work-groups, y / z neighbours re-read through the
  *         caches, the new state streamed past the caches; 2: the same with
  *         512-lane work-groups (ry = 1); 3: variant 0 storing the new state

@@ -554,8 +554,8 @@ hipError_t launch_kernel(const fdtd_ctx* h, bool update, int grid, const StepArg
                          hipStream_t s) {
   if (h->tun.variant == 1)
     return launch_step_tile(h->dtype, update ? std::min(h->tun.depth, 3) : 1, update, grid, max_n(h), a, s);
-  // one-step launches prefetch at most 3 planes (depth 4 is the two-step
-  // pass's; the odd last step of a two-step evolve takes 3)
+  // one-step launches prefetch at most 3 planes (depths 4 and 5 are the
+  // two-step pass's; the odd last step of a two-step evolve takes 3)
   return launch_step(h->dtype, h->tun.vz, h->tun.ry, update ? std::min(h->tun.depth, 3) : 1, update, grid,
                      h->tun.variant == 2 ? 512 : 256, use_fv(h), h->tun.variant == 3, a, s);
 }
@@ -860,9 +860,9 @@ fdtd_status validate_tuning(const fdtd_ctx* h, const fdtd_tuning& t) {
     return fail(FDTD_EINVAL, "tuning: vz * ry must be <= 8 (<= 4 for F64)");
   if (t.xchunk < 0) return fail(FDTD_EINVAL, "tuning: xchunk must be >= 0 (0: automatic)");
   if (t.grid < 0) return fail(FDTD_EINVAL, "tuning: grid must be >= 0");
-  if (t.depth < 1 || t.depth > 4) return fail(FDTD_EINVAL, "tuning: depth must be 1, 2, 3 or 4");
-  if (t.depth == 4 && (t.tblock != 2 || h->dtype == kF64))
-    return fail(FDTD_EINVAL, "tuning: depth 4 needs tblock = 2 and an F32 or BF16 state");
+  if (t.depth < 1 || t.depth > 5) return fail(FDTD_EINVAL, "tuning: depth must be in 1..5");
+  if (t.depth >= 4 && (t.tblock != 2 || h->dtype == kF64))
+    return fail(FDTD_EINVAL, "tuning: depth 4 or 5 needs tblock = 2 and an F32 or BF16 state");
   if (t.vz == 1 && t.depth != 1) return fail(FDTD_EINVAL, "tuning: depth must be 1 when vz = 1");
   if (t.variant < 0 || t.variant > 3) return fail(FDTD_EINVAL, "tuning: variant must be 0, 1, 2 or 3");
   if (t.variant == 3 && (t.vz != vec_width(h->dtype) || t.ry > 2))
@@ -1587,9 +1587,9 @@ extern "C" fdtd_status fdtd_autotune(fdtd_t h, int32_t steps_per_trial, fdtd_tun
     // 140.7, 96 147.4)
     for (int tile : {0, 1})
       for (int xc : {0, 32, 64, 80, 96, 128, 256})
-        for (int depth : {1, 2, 3, 4})
+        for (int depth : {1, 2, 3, 4, 5})
           for (int persist : persists) {
-            if (!go || xc > maxN || !all_div || (h->dtype == kF64 && (depth == 4 || tile))) continue;
+            if (!go || xc > maxN || !all_div || (h->dtype == kF64 && (depth >= 4 || tile))) continue;
             go = trial(fdtd_tuning{vw, 1, xc, 0, 1, depth, 0, persist / 2, 0, 2, tile});
           }
   }

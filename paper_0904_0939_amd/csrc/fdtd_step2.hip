@@ -83,6 +83,7 @@ struct Step2 {
   // D planes ahead needs D + 3 slots), US slots of step-t results
   static constexpr int RS = D <= 3 ? 6 : 8;
   static constexpr int US = D <= 3 ? 3 : 4;
+  static_assert(D >= 1 && D + 3 <= RS, "prefetch depth 1..5");
   static_assert(TY == kTbRows(DT, WIDE) && TZ % VZ == 0, "tile shape");
   static_assert(NH <= BT, "one halo site per lane");
   using B = StepBody<DT, VZ, 1, true, FV>;  // own vectors
@@ -668,6 +669,9 @@ hipError_t step2_depth(int depth, int grid, bool persist, const StepArgs& a, hip
     case 3: return step2_one<DT, 3, FV, WIDE>(grid, persist, a, s);
     case 4:  // FP32-arithmetic lattices only (a ring of 8 plane slots)
       if constexpr (DT != kF64) return step2_one<DT, 4, FV, WIDE>(grid, persist, a, s);
+      else return hipErrorInvalidValue;
+    case 5:  // the same ring, every slot in use
+      if constexpr (DT != kF64) return step2_one<DT, 5, FV, WIDE>(grid, persist, a, s);
       else return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
   }

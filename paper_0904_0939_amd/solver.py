@@ -245,7 +245,7 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
     on level N (excited states, Sec. III).  keep: also return each level's
     final state (FP32 device tensor) in a dict.  two_step: every level whose
     side the dtype's vector width divides runs two steps per pass over HBM
-    (prefetch depth 4 for F32 states, 3 otherwise; 16 x 128 tiles for F32
+    (prefetch depth 5 for F32 states, 3 otherwise; 16 x 128 tiles for F32
     levels of side 512 or more that read the V table).  Returns (final Solver,
     per-level [(N, steps, converged)][, kept states])."""
     prev = None
@@ -262,7 +262,7 @@ def multires(levels: Sequence[int], L: float, kind: int, params: Sequence[float]
             vfuse = s.tuning()["vfuse"]
             table_v = kind > F.POT_CORNELL or not vfuse
             tile = 1 if dtypes[i] == "f32" and table_v and N >= 512 else 0
-            s.set_tuning(vw, 1, 0, 0, 1, 4 if dtypes[i] == "f32" else 3, 0, 0, vfuse, 2, tile)
+            s.set_tuning(vw, 1, 0, 0, 1, 5 if dtypes[i] == "f32" else 3, 0, 0, vfuse, 2, tile)
         if prev is None:
             s.set_initial(seed, parity=parity)
         else:

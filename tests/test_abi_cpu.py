@@ -130,20 +130,24 @@ def test_tuning_validation_is_host_side():
         F.fdtd_destroy(h)
 
 
-def test_depth_four_is_for_two_step_passes_of_fp32_arithmetic_states():
-    """depth 4 (an 8-slot register ring) exists for the two-step pass of F32
-    and BF16 states only: one-step shapes and F64 handles refuse it."""
+def test_depths_four_and_five_are_for_two_step_passes_of_fp32_arithmetic_states():
+    """depths 4 and 5 (an 8-slot register ring) exist for the two-step pass of
+    F32 and BF16 states only: one-step shapes and F64 handles refuse them, and
+    6 is refused everywhere."""
     f32 = F.fdtd_create(cfg(N=64, dtype=F.F32))
     f64 = F.fdtd_create(cfg(N=64, dtype=F.F64))
     try:
-        ok = F.fdtd_tuning(4, 1, 0, 0, 1, 4, 0, 0, 0, 2)
-        F.fdtd_set_tuning(f32, ok)
-        assert F.fdtd_get_tuning(f32).depth == 4
-        one_step = F.fdtd_tuning(4, 1, 0, 0, 1, 4, 0, 0, 0, 0)
-        assert status_of("fdtd_set_tuning", f32, C.byref(one_step)) == F.EINVAL
-        assert "depth 4" in F.fdtd_last_error()
-        for bad in (F.fdtd_tuning(2, 1, 0, 0, 1, 4, 0, 0, 0, 2), F.fdtd_tuning(4, 1, 0, 0, 1, 5, 0, 0, 0, 2)):
-            assert status_of("fdtd_set_tuning", f64 if bad.depth == 4 else f32, C.byref(bad)) == F.EINVAL
+        for depth in (4, 5):
+            ok = F.fdtd_tuning(4, 1, 0, 0, 1, depth, 0, 0, 0, 2)
+            F.fdtd_set_tuning(f32, ok)
+            assert F.fdtd_get_tuning(f32).depth == depth
+            one_step = F.fdtd_tuning(4, 1, 0, 0, 1, depth, 0, 0, 0, 0)
+            assert status_of("fdtd_set_tuning", f32, C.byref(one_step)) == F.EINVAL
+            assert "depth 4 or 5" in F.fdtd_last_error()
+        for h, bad in ((f64, F.fdtd_tuning(2, 1, 0, 0, 1, 4, 0, 0, 0, 2)),
+                       (f64, F.fdtd_tuning(2, 1, 0, 0, 1, 5, 0, 0, 0, 2)),
+                       (f32, F.fdtd_tuning(4, 1, 0, 0, 1, 6, 0, 0, 0, 2))):
+            assert status_of("fdtd_set_tuning", h, C.byref(bad)) == F.EINVAL
     finally:
         F.fdtd_destroy(f32)
         F.fdtd_destroy(f64)

@@ -213,7 +213,7 @@ def test_multires_chain_reaches_the_oracle_ground_state(two_step):
                       rel_tol=(1e-5, 1e-8), max_steps=(4000, 40000), check_every=50,
                       two_step=two_step)
     if two_step:
-        assert s.tuning()["tblock"] == 2 and s.tuning()["depth"] == 4
+        assert s.tuning()["tblock"] == 2 and s.tuning()["depth"] == 5
     assert [n for n, _, _ in log] == [16, 32]
     assert log[-1][2], log  # the FP32 level converged
     e = s.observables()[0]["energy"]

@@ -108,7 +108,8 @@ def test_bounded_wait_reports_an_error():
 
 
 @pytest.mark.parametrize("passes,steps,graph,depth", [(5, 150, True, 2), (64, 151, False, 2),
-                                                     (1, 40, True, 2), (8, 97, True, 4)])
+                                                     (1, 40, True, 2), (8, 97, True, 4),
+                                                     (8, 97, True, 5)])
 def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps, graph, depth):
     """Persistent two-step passes (tblock 2 with persist = passes per launch):
     the same bits, histories and observables as one launch per pass of the
@@ -129,7 +130,7 @@ def test_batch_persistent_two_step_passes_equal_per_pass_launches(passes, steps,
 
 
 @pytest.mark.parametrize("dtype,depth,tile", [("f64", 2, 0), ("bf16", 2, 0), ("f32", 4, 0),
-                                              ("f32", 4, 1), ("bf16", 3, 1)])
+                                              ("f32", 4, 1), ("bf16", 3, 1), ("f32", 5, 1)])
 def test_single_lattice_persistent_two_step_equals_per_pass(dtype, depth, tile):
     say(f"case: persistent two-step single {dtype} depth={depth} tile={tile}")
     vz = {"f64": 2, "bf16": 8, "f32": 4}[dtype]

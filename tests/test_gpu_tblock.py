@@ -63,15 +63,18 @@ CASES = [
     ("f64", 300, "cornell", 32, 1, 0, 0),
     ("bf16", 64, "cornell", 0, 2, 0, 0),
     ("bf16", 96, "ho", 24, 3, 1, 0),
-    # prefetch depth 4 (an 8-slot ring): whole trips, every tail length
+    # prefetch depths 4 and 5 (an 8-slot ring): whole trips, every tail length
     ("f32", 72, "cornell", 0, 4, 0, 0),
     ("f32", 100, "ho", 30, 4, 1, 0),
     ("bf16", 64, "cornell", 0, 4, 1, 0),
+    ("f32", 72, "ho", 9, 5, 1, 0),
+    ("f32", 100, "cornell", 0, 5, 0, 0),
+    ("bf16", 96, "cornell", 24, 5, 1, 0),
     # 16 x 128 tiles: a lattice narrower than one tile, sides ragged in y and
     # z (136 = 128 + 8, 8.5 tiles of 16 rows), side 516, BF16
     ("f32", 40, "ho", 0, 2, 0, 1),
     ("f32", 136, "cornell", 24, 4, 0, 1),
-    ("f32", 516, "cornell", 0, 4, 1, 1),
+    ("f32", 516, "cornell", 0, 5, 1, 1),
     ("bf16", 136, "ho", 40, 3, 1, 1),
 ]
 
