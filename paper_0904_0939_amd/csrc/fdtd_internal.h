@@ -108,7 +108,7 @@ hipError_t launch_step(int dtype, int vz, int ry, int depth, bool update, int gr
 // Two steps per pass (temporal blocking, update only): work items
 // are tiles of kTbRows(dtype, wide) x kTbCols(dtype, wide) sites of the (y, z)
 // plane, whose f0 is the tile origin y0 N + z0; one vector of kTbVec(dtype)
-// sites per lane (kTbThreads(dtype) lanes); depth 1..4 (4: F32 / BF16);
+// sites per lane (kTbThreads(dtype) lanes); depth 1..5 (4 and 5: F32 / BF16);
 // partials for 2 * slot_stride slots.
 // persist: one persistent launch of a.steps passes (2 a.steps steps; `grid`
 // work-groups take (pass, tile) tickets, a tile of pass p waiting until its
